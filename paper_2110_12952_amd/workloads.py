@@ -1,0 +1,154 @@
+"""Fractal definitions, workload sizes and seeded input generators.
+
+This module is shared by the tests, the benchmark and the code that drives the
+oracle.  It holds *inputs only*: replica offset lists, level/seed/probability
+choices and seeded random arrays.  None of the method's arithmetic (membership,
+the lambda/nu maps, the automaton, the initial-state generator) lives here.
+
+Replica offsets are (x, y) digit pairs in [0, s)^2, x to the right, y downwards,
+origin top-left (paper section 3).  The list order is the replica numbering that
+the compact index uses (section 3.1: the replica id of H must agree with the
+numbering used by lambda).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+Offsets = Tuple[Tuple[int, int], ...]
+
+
+@dataclass(frozen=True)
+class FractalDef:
+    """An NBB fractal F^{k,s}: k replicas, growth ratio s (section 1)."""
+    name: str
+    s: int
+    offsets: Offsets
+
+    @property
+    def k(self) -> int:
+        return len(self.offsets)
+
+    def flat_offsets(self) -> List[int]:
+        out: List[int] = []
+        for ox, oy in self.offsets:
+            out += [int(ox), int(oy)]
+        return out
+
+
+# Sierpinski triangle F^{3,2}: the paper's case study (section 4.1).
+TRIANGLE = FractalDef("triangle", 2, ((0, 0), (1, 0), (0, 1)))
+# Sierpinski carpet F^{8,3}: the 3x3 grid without its centre, row-major order.
+CARPET = FractalDef("carpet", 3, ((0, 0), (1, 0), (2, 0), (0, 1), (2, 1),
+                                  (0, 2), (1, 2), (2, 2)))
+# H-fractal F^{7,3}: both full columns plus the centre.
+HFRACTAL = FractalDef("hfractal", 3, ((0, 0), (0, 1), (0, 2), (1, 1),
+                                      (2, 0), (2, 1), (2, 2)))
+# Chandelier-like F^{4,3}: top row plus the centre.
+CHANDELIER = FractalDef("chandelier", 3, ((0, 0), (1, 0), (2, 0), (1, 1)))
+# Full square F^{4,2}: every cell of the box is a member; the compact order is
+# then the Z-order (Morton) curve and the automaton is plain Game of Life.
+FULLSQUARE = FractalDef("fullsquare", 2, ((0, 0), (1, 0), (0, 1), (1, 1)))
+# Textbook fractals of the same class, used as extra test fractals.
+VICSEK = FractalDef("vicsek", 3, ((1, 0), (0, 1), (1, 1), (2, 1), (1, 2)))
+XFRACTAL = FractalDef("xfractal", 3, ((0, 0), (2, 0), (1, 1), (0, 2), (2, 2)))
+CANTOR_DUST = FractalDef("cantordust", 3, ((0, 0), (2, 0), (0, 2), (2, 2)))
+# Cantor set F^{2,3} laid on the first row of its box (Table 1 lists F^{2,3}).
+CANTOR = FractalDef("cantor", 3, ((0, 0), (2, 0)))
+# A fractal with a single replica: one cell at every level.
+SINGLE = FractalDef("single", 2, ((1, 1),))
+# s = 4 with 12 replicas in a scrambled order (not one of the paper's pictures).
+GRID4 = FractalDef("grid4_12", 4, ((0, 0), (1, 0), (3, 0), (0, 1), (1, 1),
+                                   (3, 1), (0, 3), (1, 3), (2, 2), (3, 3),
+                                   (2, 3), (3, 2)))
+
+FRACTALS: Dict[str, FractalDef] = {
+    f.name: f for f in (TRIANGLE, CARPET, HFRACTAL, CHANDELIER, FULLSQUARE,
+                        VICSEK, XFRACTAL, CANTOR_DUST, CANTOR, SINGLE, GRID4)
+}
+
+# Game-of-Life rules as (birth counts, survival counts).
+RULES = {
+    "B3/S23": ((3,), (2, 3)),             # Conway's Game of Life
+    "B1357/S1357": ((1, 3, 5, 7), (1, 3, 5, 7)),    # replicator (XOR of neighbours)
+    "B1357/S02468": ((1, 3, 5, 7), (0, 2, 4, 6, 8)),  # Fredkin (self XOR neighbours)
+    "B36/S23": ((3, 6), (2, 3)),          # HighLife
+    "B2/S": ((2,), ()),                   # Seeds
+}
+
+
+def rule_mask(name_or_pair) -> int:
+    """Rule word: bit c (0..8) = birth with c live neighbours, bit 16+c = survival."""
+    birth, survive = RULES[name_or_pair] if isinstance(name_or_pair, str) else name_or_pair
+    m = 0
+    for c in birth:
+        m |= 1 << c
+    for c in survive:
+        m |= 1 << (16 + c)
+    return m
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One synthetic automaton run: fractal, level, Bernoulli(p) seed, steps."""
+    name: str
+    fractal: FractalDef
+    r: int
+    p: float
+    seeds: Tuple[int, ...]
+    steps: int
+    rule: str = "B3/S23"
+
+    @property
+    def n(self) -> int:
+        return self.fractal.s ** self.r
+
+    @property
+    def cells(self) -> int:
+        return self.fractal.k ** self.r
+
+
+# The workloads of the paper's case study and of the wider evaluation plan.
+SMALL_TRIANGLE = Workload("triangle_r10", TRIANGLE, 10, 0.5, (1, 2, 3), 100)
+LARGE_TRIANGLE = Workload("triangle_r16", TRIANGLE, 16, 0.3, (12952,), 1000)
+CARPET_R9 = Workload("carpet_r9", CARPET, 9, 0.5, (12952,), 200)
+HFRACTAL_R10 = Workload("hfractal_r10", HFRACTAL, 10, 0.5, (12952,), 200)
+
+WORKLOADS: Dict[str, Workload] = {
+    w.name: w for w in (SMALL_TRIANGLE, LARGE_TRIANGLE, CARPET_R9, HFRACTAL_R10)
+}
+
+
+def random_offsets(rng: np.random.Generator, s: int, k: int) -> Offsets:
+    """k distinct digit pairs in [0,s)^2 in random order (a random NBB fractal)."""
+    cells = rng.choice(s * s, size=k, replace=False)
+    return tuple((int(c % s), int(c // s)) for c in cells)
+
+
+def random_fractal(seed: int, s_choices: Sequence[int] = (2, 3, 4)) -> FractalDef:
+    rng = np.random.default_rng(seed)
+    s = int(rng.choice(list(s_choices)))
+    k = int(rng.integers(1, s * s + 1))
+    return FractalDef(f"random{seed}", s, random_offsets(rng, s, k))
+
+
+def random_coords(seed: int, count: int, lo: int, hi: int) -> Tuple[np.ndarray, np.ndarray]:
+    """count (x, y) pairs uniform in [lo, hi)^2, int32."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(lo, hi, size=count, dtype=np.int64).astype(np.int32)
+    y = rng.integers(lo, hi, size=count, dtype=np.int64).astype(np.int32)
+    return x, y
+
+
+def random_indices(seed: int, count: int, hi: int) -> np.ndarray:
+    """count uint32 indices uniform in [0, hi)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, hi, size=count, dtype=np.int64).astype(np.uint32)
+
+
+def random_bits(seed: int, count: int, p: float = 0.5) -> np.ndarray:
+    """count uint8 values in {0,1}, each 1 with probability p."""
+    rng = np.random.default_rng(seed)
+    return (rng.random(count) < p).astype(np.uint8)
