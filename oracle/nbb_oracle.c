@@ -249,6 +249,29 @@ void orc_compact_step(const orc_fractal *f, const uint8_t *in, uint8_t *out, uin
     }
 }
 
+/* State of compact cell i after `steps` generations, from the state `in`,
+ * by the definition itself: recursion over the cell's light cone (9^steps
+ * evaluations).  For spot checks of large runs at small step counts. */
+static uint8_t orc_cell_after(const orc_fractal *f, const uint8_t *in, int64_t i, uint32_t rule, int steps) {
+    if (steps == 0) return in[i];
+    int64_t x, y;
+    orc_lambda(f, i, &x, &y);
+    int64_t live = 0;
+    for (int64_t dy = -1; dy <= 1; ++dy)
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            int64_t j = orc_nu(f, x + dx, y + dy);
+            if (j != ORC_OUTSIDE && orc_cell_after(f, in, j, rule, steps - 1)) ++live;
+        }
+    return orc_apply_rule(rule, live, orc_cell_after(f, in, i, rule, steps - 1) != 0);
+}
+
+void orc_cells_after(const orc_fractal *f, const uint8_t *in, const int64_t *idx, int64_t count,
+                     uint32_t rule, int steps, uint8_t *out) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < count; ++t) out[t] = orc_cell_after(f, in, idx[t], rule, steps);
+}
+
 /* compact[i] = bbox[lambda(i)] */
 void orc_gather(const orc_fractal *f, const uint8_t *bbox, uint8_t *compact) {
 #pragma omp parallel for schedule(static)

@@ -51,6 +51,7 @@ def lib():
         L.orc_expand.argtypes = [vp, vp, vp]
         L.orc_lambda_many.argtypes = [vp, vp, i64, vp, vp]
         L.orc_nu_many.argtypes = [vp, vp, vp, i64, vp]
+        L.orc_cells_after.argtypes = [vp, vp, vp, i64, u32, ctypes.c_int, vp]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -167,6 +168,17 @@ class Fractal:
             lib().orc_bbox_step(self._h, _ptr(mask), _ptr(a), _ptr(b), int(rule))
             a, b = b, a
         return a
+
+    def cells_after(self, state: np.ndarray, idx, rule: int, steps: int) -> np.ndarray:
+        """States of the compact cells idx after `steps` generations (steps <= 3)."""
+        st = np.ascontiguousarray(state, dtype=np.uint8)
+        assert st.size == self.cells and 0 <= steps <= 3
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        if idx.size and (idx.min() < 0 or idx.max() >= self.cells):
+            raise IndexError("index out of range")
+        out = np.empty(idx.size, dtype=np.uint8)
+        lib().orc_cells_after(self._h, _ptr(st), _ptr(idx), idx.size, int(rule), int(steps), _ptr(out))
+        return out
 
     def compact_steps(self, state: np.ndarray, rule: int, steps: int) -> np.ndarray:
         a = np.ascontiguousarray(state, dtype=np.uint8).copy()

@@ -401,3 +401,13 @@ def test_init_threshold_boundary():
         top = O.splitmix64(seed, y * f.n + x) >> 40
         assert f.init_bbox(seed, top / 2.0 ** 24)[y, x] == 0
         assert f.init_bbox(seed, (top + 1) / 2.0 ** 24)[y, x] == 1
+
+
+@pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier", "cantor"])
+def test_cells_after_matches_full_steps(name):
+    f = frac(name, min(max_level(name), 5))
+    st = f.init_compact(31, 0.5)
+    idx = np.arange(0, f.cells, max(1, f.cells // 200))
+    for steps in (0, 1, 2, 3):
+        np.testing.assert_array_equal(f.cells_after(st, idx, B3S23, steps),
+                                      f.compact_steps(st, B3S23, steps)[idx])
