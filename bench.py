@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the compact-fractal automaton step on one MI355X.
+
+Workload (default): Sierpinski triangle F^{3,2} at level r = 16 (n = 65,536,
+43,046,721 compact cells), Bernoulli(0.3) initial state from seed 12952,
+Game of Life B3/S23.  A timed step is one generation of the compact step
+over the whole fractal (one kernel launch).  The same run also times the
+bounding-box step over the full 65,536^2 box (the paper's baseline) and the
+lambda / nu maps over all 43M indices, checks that the compact and box
+results agree, and times the CPU oracle on a bounded sample.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+COUNTERS = os.path.join(ROOT, "profiles", "compact_step_triangle_r16_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_12952_amd", "csrc", "kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_events(torch, fn, reps=1):
+    """Milliseconds of fn() on the current stream, bracketed by HIP events."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    out = None
+    for _ in range(reps):
+        out = fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), out
+
+
+def measured_traffic(per_launch_alg_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(W, wl, seconds):
+    from oracle import oracle as O
+    fd = wl.fractal
+    o = O.Fractal(fd.s, fd.offsets, wl.r)
+    st = o.init_compact(wl.seeds[0], wl.p)
+    rule = W.rule_mask(wl.rule)
+    steps, t = 0, 0.0
+    while t < seconds or steps == 0:
+        t0 = time.perf_counter()
+        st = o.compact_steps(st, rule, 1)
+        t += time.perf_counter() - t0
+        steps += 1
+        log(f"oracle step {steps}: {t:.1f} s")
+    return {"value": o.cells * steps / t, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{steps} generation(s) of the oracle's compact step (lambda, 8 x nu per cell) over "
+                      f"the full {o.cells}-cell state, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="triangle_r16")
+    ap.add_argument("--bbox-steps", type=int, default=None, help="box-step generations (default: --steps)")
+    ap.add_argument("--map-reps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bbox", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_12952_amd import nbbfrac as N
+    from paper_2110_12952_amd import workloads as W
+
+    wl = W.WORKLOADS[args.workload]
+    fd = wl.fractal
+    torch.cuda.set_device(0)
+    g = N.Fractal(fd.s, fd.offsets, wl.r)
+    info = g.info()
+    rule = W.rule_mask(wl.rule)
+    K, Wu = args.steps, args.warmup
+    log(f"{wl.name}: n={g.n} cells={g.cells} strategy={info.strategy} tile_level={info.tile_level}")
+
+    # ---- compact step -----------------------------------------------------
+    a = g.init_compact(wl.seeds[0], wl.p)
+    b = torch.empty_like(a)
+    init = a.clone()
+    if Wu:
+        g.step_compact(a.clone(), b, Wu, rule)
+    ms, res = time_events(torch, lambda: g.step_compact(a, b, K, rule))
+    ms_step = ms / K
+    value = g.cells * K / (ms * 1e-3)
+    alg_bytes = 2 * g.cells  # read + write one byte per cell per generation
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    log(f"compact: {ms_step * 1e3:.2f} us/step, {value:.3e} cell-updates/s, {achieved:.0f} GB/s")
+
+    # ---- box step (baseline) ----------------------------------------------
+    bbox = None
+    parity = None
+    if not args.no_bbox:
+        Kb = args.bbox_steps or K
+        box = g.init_bbox(wl.seeds[0], wl.p)
+        box2 = torch.empty_like(box)
+        if Wu:
+            g.step_bbox(box.clone(), box2, min(Wu, 5), rule)
+        msb, resb = time_events(torch, lambda: g.step_bbox(box, box2, Kb, rule))
+        msb_step = msb / Kb
+        box_cells = g.n * g.n
+        bbox = {"ms_per_step": msb_step, "steps": Kb,
+                "cell_updates_per_s": g.cells * Kb / (msb * 1e-3),
+                "box_cell_updates_per_s": box_cells * Kb / (msb * 1e-3),
+                "alg_gbps": 2 * box_cells / (msb_step * 1e-3) / 1e9}
+        bbox["roofline_frac"] = bbox["alg_gbps"] / HBM_PEAK_GBPS
+        log(f"bbox: {msb_step * 1e3:.1f} us/step, {bbox['alg_gbps']:.0f} GB/s")
+        if Kb == K:
+            parity = bool(torch.equal(g.gather(resb), res))
+            log(f"compact == gathered box after {K} steps: {parity}")
+        del box, box2, resb
+
+    # ---- maps ---------------------------------------------------------------
+    x = torch.empty(g.cells, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    idx = torch.empty_like(x)
+    g.lam(out=(x, y))
+    g.nu(x, y, out=idx)
+    msl, _ = time_events(torch, lambda: g.lam(out=(x, y)), args.map_reps)
+    msn, _ = time_events(torch, lambda: g.nu(x, y, out=idx), args.map_reps)
+    maps_ok = bool(torch.equal(idx.to(torch.int64), torch.arange(g.cells, device="cuda")))
+    maps = {"lambda_items_per_s": g.cells * args.map_reps / (msl * 1e-3),
+            "lambda_gbps": 8 * g.cells * args.map_reps / (msl * 1e-3) / 1e9,
+            "nu_items_per_s": g.cells * args.map_reps / (msn * 1e-3),
+            "nu_gbps": 12 * g.cells * args.map_reps / (msn * 1e-3) / 1e9,
+            "nu_of_lambda_is_identity": maps_ok}
+    log(f"maps: lambda {maps['lambda_gbps']:.0f} GB/s, nu {maps['nu_gbps']:.0f} GB/s, round trip ok={maps_ok}")
+    del x, y, idx
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(W, wl, args.cpu_seconds)
+        log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
+
+    traffic = measured_traffic(alg_bytes)
+    out = {
+        "metric": "compact cell-updates/sec + % HBM roofline vs bbox; batched p50/p99 latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wu,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "fractal": f"F^{{{fd.k},{fd.s}}} {fd.name}", "r": wl.r, "n": g.n,
+                   "cells": g.cells, "p": wl.p, "seed": wl.seeds[0], "rule": wl.rule,
+                   "strategy": "tiled" if info.strategy == N.STRATEGY_TILED else "direct",
+                   "tile_level": info.tile_level},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "k_step_tiled" if info.strategy == N.STRATEGY_TILED else "k_step_direct",
+                     "alg_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "bbox": bbox,
+        "speedup_vs_bbox": (bbox["ms_per_step"] / ms_step) if bbox else None,
+        "compact_equals_bbox": parity,
+        "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
+        "maps": maps,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

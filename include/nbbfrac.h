@@ -1,0 +1,214 @@
+/*
+ * libnbbfrac -- cellular-automaton steps on NBB fractals held in compact form,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Quezada & Navarro, "Accelerating Compact Fractals with Tensor Core
+ * GPUs" (technical report, 2021).  An NBB fractal F^{k,s} (section 1) at scale
+ * level r lives in an n x n box, n = s^r, and has k^r cells (eq. 1).  Its
+ * compact form stores only those k^r cells.  Two maps connect the spaces
+ * (section 3): lambda takes a compact index to its (x, y) in the box, nu takes
+ * (x, y) back to a compact index, or reports that the point is outside the
+ * fractal.  A stencil step in compact space (section 3, last two paragraphs)
+ * maps each cell with lambda, forms its neighbours' coordinates, maps them
+ * back with nu and applies the update rule.
+ *
+ * Conventions used by every entry point
+ *   - Coordinates: x to the right, y downwards, origin top-left (section 3).
+ *   - Replica offsets: k pairs (x_j, y_j) in [0,s)^2, listed as
+ *     x0,y0,x1,y1,...; list position j is replica id j, the value the helper H
+ *     of section 3.1 returns for that digit pair.
+ *   - Compact index: i = sum_{mu<r} H_mu k^mu, H_mu the replica id of the
+ *     level-mu base-s digit pair of (x, y).  lambda(i) = sum_mu o_{d_mu(i)} s^mu
+ *     with d_mu(i) the base-k digits of i.  (The paper draws the compact space
+ *     as a 2D unfolding, eqs. 3-8; that is a fixed permutation of these
+ *     indices.)  Every aligned run of k^m indices is then one level-m copy of
+ *     the fractal.
+ *   - State: one byte per cell, 0 = dead, 1 = alive.  Compact state is
+ *     uint8[k^r] in compact-index order.  Box state is n rows of `pitch`
+ *     bytes (cell (x,y) at y*pitch + x); pitch >= n and pitch % 16 == 0,
+ *     nbb_bbox_pitch() gives the smallest one.  Cells of the box outside the
+ *     fractal, and the padding columns x >= n, hold 0.
+ *   - Rule word: bit c (c = 0..8) set = a dead cell with c live Moore
+ *     neighbours is born; bit 16+c set = a live cell with c live neighbours
+ *     survives.  Conway's Life B3/S23 is NBB_RULE_B3S23.  Cells outside the
+ *     fractal or the box count as dead and stay dead.
+ *   - Device pointers are owned by the caller and must be device memory of the
+ *     device that was current at nbb_create (e.g. torch CUDA tensors).  A
+ *     `stream` is a hipStream_t (NULL = the null stream).  Calls check their
+ *     arguments, enqueue work and return; they do not wait for the device.
+ *     Faults of the enqueued work surface at the next synchronisation.
+ *   - Errors: every call returns an nbb_status; nbb_last_error() gives a
+ *     message for the calling thread's last failure.  No exception crosses
+ *     this interface.  A descriptor may be used from several threads at once
+ *     except during nbb_configure and nbb_destroy.
+ */
+#ifndef NBBFRAC_H
+#define NBBFRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NBB_OK = 0,
+    NBB_E_INVALID = 1, /* bad argument: null pointer, wrong length, overlap, ... */
+    NBB_E_RANGE = 2,   /* size beyond what the index types hold */
+    NBB_E_NOMEM = 3,   /* device or host allocation failed */
+    NBB_E_DEVICE = 4   /* HIP runtime error (no device, launch failure, ...) */
+} nbb_status;
+
+/* nu's result for a coordinate outside the box or outside the fractal. */
+#define NBB_OUTSIDE 0xFFFFFFFFu
+
+/* B3/S23: born with 3, survives with 2 or 3. */
+#define NBB_RULE_B3S23 ((1u << 3) | ((1u << 2 | 1u << 3) << 16))
+
+/* How nbb_step_compact evaluates a step (nbb_configure). */
+#define NBB_STRATEGY_AUTO 0u   /* TILED when the fractal allows it, else DIRECT */
+#define NBB_STRATEGY_TILED 1u  /* level-m tiles staged in LDS with their halo */
+#define NBB_STRATEGY_DIRECT 2u /* one thread per cell: lambda, 8 x nu, rule */
+
+typedef struct nbb_fractal nbb_fractal;
+
+typedef struct {
+    uint64_t n;            /* box side s^r */
+    uint64_t cells;        /* k^r */
+    uint64_t tiles;        /* k^(r - tile_level) */
+    uint32_t k, s, r;
+    uint32_t strategy;     /* NBB_STRATEGY_TILED or NBB_STRATEGY_DIRECT */
+    uint32_t tile_level;   /* m: a tile is an aligned run of k^m compact cells */
+    uint32_t tile_side;    /* s^m */
+    uint32_t halo_cells;   /* neighbour cells staged per tile */
+    uint32_t lds_bytes;    /* LDS used by one work-group of the tiled step */
+    uint64_t bbox_pitch;   /* smallest pitch the box entry points accept */
+    uint64_t device_table_bytes;
+} nbb_info;
+
+/*
+ * Create the descriptor of F^{k,s} at level r (sections 1 and 3.1) and upload
+ * its tables to the current device.
+ *   offsets: 2k int32 values x0,y0,...; each pair in [0,s)^2, no duplicates.
+ * Returns NBB_E_INVALID for out == NULL, offsets == NULL, k == 0, s < 2,
+ * s > 16, k > s*s, an offset outside [0,s)^2 or a repeated offset;
+ * NBB_E_RANGE if k^r > 2^32 - 1 or s^r + 1 > 2^31 - 1; NBB_E_DEVICE /
+ * NBB_E_NOMEM if the tables cannot be uploaded.  On failure *out is NULL.
+ * The descriptor owns its host and device tables; free with nbb_destroy.
+ */
+nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
+                      nbb_fractal **out);
+
+/* Free a descriptor (NULL is a no-op).  No enqueued work may still use it. */
+void nbb_destroy(nbb_fractal *f);
+
+/* Describe a descriptor.  NBB_E_INVALID for NULL arguments. */
+nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
+
+/*
+ * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED,
+ * the tile level m (0 = automatic; otherwise 1 <= m <= r).  TILED needs
+ * 2 <= s <= 4 and r >= 1; NBB_E_INVALID when the request cannot be met (the
+ * descriptor keeps its previous plan).  Rebuilds and re-uploads the tile
+ * tables; must not overlap other calls on the same descriptor.
+ */
+nbb_status nbb_configure(nbb_fractal *f, uint32_t strategy, uint32_t tile_level);
+
+/*
+ * lambda (section 3): x[t], y[t] = embedded coordinate of compact index idx[t],
+ * t < count.  idx == NULL means idx[t] = t.  An index >= k^r gives x = y = -1.
+ * Device arrays; count == 0 is a no-op.
+ */
+nbb_status nbb_lambda(const nbb_fractal *f, const uint32_t *idx, uint64_t count, int32_t *x,
+                      int32_t *y, void *stream);
+
+/*
+ * nu (section 3.1, eqs. 6-8 in compact-index form): idx[t] = compact index of
+ * (x[t], y[t]), or NBB_OUTSIDE when the point is outside [0,n)^2 or not a
+ * fractal cell.  Device arrays; count == 0 is a no-op.
+ */
+nbb_status nbb_nu(const nbb_fractal *f, const int32_t *x, const int32_t *y, uint64_t count,
+                  uint32_t *idx, void *stream);
+
+/*
+ * Bernoulli(p) initial state.  Cell (x, y) of the fractal is alive iff the top
+ * 24 bits of SplitMix64 output number key = y*n + x of the stream seeded with
+ * `seed` (Steele, Lea & Flood 2014: mix(seed + (key+1)*0x9E3779B97F4A7C15))
+ * are below floor(p * 2^24).  Both layouts therefore hold the same state.
+ * nbb_init_compact: len must be k^r.  nbb_init_bbox: len must be n*pitch,
+ * pitch as described above; non-members and padding are written 0.
+ * p must lie in [0, 1].
+ */
+nbb_status nbb_init_compact(const nbb_fractal *f, uint8_t *state, uint64_t len, uint64_t seed,
+                            double p, void *stream);
+nbb_status nbb_init_bbox(const nbb_fractal *f, uint8_t *state, uint64_t pitch, uint64_t len,
+                         uint64_t seed, double p, void *stream);
+
+/*
+ * `steps` synchronous generations of `rule` on the compact state (section 3,
+ * stencil procedure; section 4, Game of Life on the fractal).  The state
+ * starts in a; buffers a and b alternate, and *result_in_b (if not NULL) is
+ * set to steps & 1, i.e. whether the result ended in b.  len must be k^r;
+ * a and b must not overlap; the rule may only use bits 0-8 and 16-24; state
+ * bytes must be 0 or 1.  steps == 0 leaves both buffers untouched.
+ */
+nbb_status nbb_step_compact(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len,
+                            uint32_t steps, uint32_t rule, int *result_in_b, void *stream);
+
+/*
+ * The bounding-box baseline the paper compares against (section 4, method 1):
+ * the same generations computed on the whole box, every box cell visited.
+ * len must be n*pitch.  The input must hold 0 at non-members and padding;
+ * the output does too.  Other rules as nbb_step_compact.
+ */
+nbb_status nbb_step_bbox(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t pitch,
+                         uint64_t len, uint32_t steps, uint32_t rule, int *result_in_b,
+                         void *stream);
+
+/* bbox[lambda(i)] = compact[i]; every other box byte becomes 0. */
+nbb_status nbb_expand(const nbb_fractal *f, const uint8_t *compact, uint8_t *bbox, uint64_t pitch,
+                      uint64_t len, void *stream);
+
+/* compact[i] = bbox[lambda(i)] (the inverse of nbb_expand on members). */
+nbb_status nbb_gather(const nbb_fractal *f, const uint8_t *bbox, uint64_t pitch, uint8_t *compact,
+                      uint64_t len, void *stream);
+
+/* Smallest box pitch for this descriptor: n rounded up to a multiple of 16. */
+uint64_t nbb_bbox_pitch(const nbb_fractal *f);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *nbb_last_error(void);
+
+/* Name of a status code. */
+const char *nbb_status_string(nbb_status s);
+
+/*
+ * Host-side view of the tile plan the tiled step would use for F^{k,s} at
+ * level r with tile level m (0 = automatic), without touching a device.  For
+ * inspection and tests.  The arrays belong to the plan; free it with
+ * nbb_plan_free.
+ *   lut0[i], i < tile_cells: byte offset in the tile's LDS box of local cell i
+ *   lut1[b], b < blocks: offset of the 3-row/col window corner of level-1 block b
+ *   halo_src[h] = (direction << 29) | local index in that neighbour tile,
+ *   direction = (dy+1)*3 + (dx+1) skipping the centre (0..7);
+ *   halo_dst[h] = byte offset in the LDS box.
+ */
+typedef struct nbb_plan nbb_plan;
+typedef struct {
+    uint32_t tile_level, tile_side, tile_cells, blocks, halo_count;
+    uint32_t box_pitch, box_rows, lds_bytes;
+    uint64_t tiles;
+    const uint16_t *lut0;
+    const uint16_t *lut1;
+    const uint32_t *halo_src;
+    const uint32_t *halo_dst;
+} nbb_plan_view;
+nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
+                          uint32_t tile_level, nbb_plan **out, nbb_plan_view *view);
+void nbb_plan_free(nbb_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBBFRAC_H */

@@ -1,0 +1,545 @@
+// C ABI of libnbbfrac (declared in include/nbbfrac.h): argument checks, the
+// descriptor's device tables, and kernel launches.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/nbbfrac.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace nbb;
+
+namespace {
+
+thread_local std::string g_err;
+
+nbb_status fail(nbb_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+nbb_status hip_fail(hipError_t e, const char *what) {
+    return fail(NBB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// One device allocation holding a set of tables; offsets are 256-aligned.
+struct DevBlob {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct nbb_fractal {
+    Fractal f;
+    MapTables maps;
+    TilePlan tile;
+    BoxTables box;
+    uint32_t strategy = NBB_STRATEGY_DIRECT;
+    int device = 0;
+    int cu_count = 256;
+    DevBlob dmap, dtile, dbox;
+    MapParams mp{};
+    TileParams tp{};
+    BoxParams bp{};
+    uint32_t lam_words = 0, nu_halves = 0;
+};
+
+struct nbb_plan {
+    Fractal f;
+    TilePlan tile;
+};
+
+namespace {
+
+void blob_free(DevBlob *b) {
+    if (b->ptr) (void)hipFree(b->ptr);
+    b->ptr = nullptr;
+    b->bytes = 0;
+}
+
+// Upload `parts` (host pointer, bytes) into one fresh device allocation and
+// return the device address of each part.
+nbb_status upload(DevBlob *blob, const void *const *src, const size_t *bytes, int nparts,
+                  void **dst) {
+    size_t total = 0;
+    size_t off[8];
+    for (int i = 0; i < nparts; ++i) {
+        off[i] = total;
+        total += align256(std::max<size_t>(bytes[i], 1));
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? fail(NBB_E_NOMEM, "device table allocation failed")
+                                        : hip_fail(e, "hipMalloc");
+    }
+    for (int i = 0; i < nparts; ++i) {
+        if (bytes[i]) {
+            e = hipMemcpy(static_cast<char *>(p) + off[i], src[i], bytes[i], hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(p);
+                return hip_fail(e, "hipMemcpy");
+            }
+        }
+        dst[i] = static_cast<char *>(p) + off[i];
+    }
+    blob->ptr = p;
+    blob->bytes = total;
+    return NBB_OK;
+}
+
+nbb_status upload_maps(nbb_fractal *F) {
+    const Fractal &f = F->f;
+    const MapTables &t = F->maps;
+    uint8_t ox[kMaxK], oy[kMaxK];
+    for (uint32_t j = 0; j < f.k; ++j) {
+        ox[j] = uint8_t(f.ox[j]);
+        oy[j] = uint8_t(f.oy[j]);
+    }
+    const void *src[5] = {t.lam.data(), t.nu.data(), ox, oy, f.hl};
+    size_t bytes[5] = {t.lam.size() * 4, t.nu.size() * 2, f.k, f.k, 256};
+    void *dst[5];
+    nbb_status s = upload(&F->dmap, src, bytes, 5, dst);
+    if (s != NBB_OK) return s;
+    MapParams &P = F->mp;
+    P.k = f.k;
+    P.s = f.s;
+    P.r = f.r;
+    P.n = uint32_t(f.n);
+    P.cells_m1 = uint32_t(f.cells - 1);
+    P.divk = make_udiv(f.k);
+    P.divs = make_udiv(f.s);
+    P.jl = t.jl;
+    P.jl_top = t.jl_top;
+    P.nchunks_l = t.nchunks_l;
+    uint64_t kl = 1, sl = 1;
+    for (uint32_t i = 0; i < t.jl; ++i) {
+        kl *= f.k;
+        sl *= f.s;
+    }
+    P.kl = uint32_t(kl);
+    P.sl = uint32_t(sl);
+    P.divkl = make_udiv(P.kl);
+    P.lam_top_off = t.lam_top_off;
+    P.jn = t.jn;
+    P.jn_top = t.jn_top;
+    P.nchunks_n = t.nchunks_n;
+    uint64_t sn = 1, kn = 1, st = 1;
+    for (uint32_t i = 0; i < t.jn; ++i) {
+        sn *= f.s;
+        kn *= f.k;
+    }
+    for (uint32_t i = 0; i < t.jn_top; ++i) st *= f.s;
+    P.sn = uint32_t(sn);
+    P.kn = uint32_t(kn);
+    P.sn_top = uint32_t(st);
+    P.divsn = make_udiv(P.sn);
+    P.nu_top_off = t.nu_top_off;
+    P.lam_lut = static_cast<const uint32_t *>(dst[0]);
+    P.nu_lut = static_cast<const uint16_t *>(dst[1]);
+    P.ox = static_cast<const uint8_t *>(dst[2]);
+    P.oy = static_cast<const uint8_t *>(dst[3]);
+    P.hl = static_cast<const uint8_t *>(dst[4]);
+    F->lam_words = uint32_t(t.lam.size());
+    F->nu_halves = uint32_t(t.nu.size());
+    return NBB_OK;
+}
+
+nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TileParams *T) {
+    const void *src[4] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data()};
+    size_t bytes[4] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4};
+    void *dst[4];
+    nbb_status s = upload(blob, src, bytes, 4, dst);
+    if (s != NBB_OK) return s;
+    *T = TileParams{};
+    T->m = p.m;
+    T->S = p.S;
+    T->K = p.K;
+    T->W = p.W;
+    T->nblk = p.nblk;
+    T->box_bytes = p.box_bytes;
+    T->cout_off = p.cout_off;
+    T->lds_total = p.lds_total;
+    T->rm = p.rm;
+    T->ntiles = uint32_t(p.ntiles);
+    T->Sc = p.Sc;
+    T->halo_count = uint32_t(p.halo_src.size());
+    T->cells = uint32_t(F->f.cells);
+    T->lut0_stride = p.lut0_stride;
+    T->lut0p = static_cast<const uint16_t *>(dst[0]);
+    T->lut1 = static_cast<const uint16_t *>(dst[1]);
+    T->halo_src = static_cast<const uint32_t *>(dst[2]);
+    T->halo_dst = static_cast<const uint32_t *>(dst[3]);
+    std::memset(T->hl, 0xFF, sizeof(T->hl));
+    for (uint32_t i = 0; i < F->f.s * F->f.s && i < 16; ++i) T->hl[i] = F->f.hl[i];
+    return NBB_OK;
+}
+
+nbb_status upload_box(nbb_fractal *F) {
+    const BoxTables &b = F->box;
+    if (b.high.empty()) return NBB_OK;  // box too large to exist; box calls report NBB_E_RANGE
+    const void *src[2] = {b.low.data(), b.high.data()};
+    size_t bytes[2] = {b.low.size() * 4, b.high.size()};
+    void *dst[2];
+    nbb_status s = upload(&F->dbox, src, bytes, 2, dst);
+    if (s != NBB_OK) return s;
+    BoxParams &B = F->bp;
+    B.n = uint32_t(F->f.n);
+    B.SL = b.SL;
+    B.LW = b.LW;
+    B.NH = b.NH;
+    B.divSL = make_udiv(b.SL);
+    B.low = static_cast<const uint32_t *>(dst[0]);
+    B.high = static_cast<const uint8_t *>(dst[1]);
+    B.pitch = box_pitch(F->f);
+    // Rows per work-group: enough work-groups to fill the chip, long enough
+    // bands that the two extra rows each band reads stay a small fraction.
+    const uint64_t gx = (B.pitch / 16 + 255) / 256;
+    uint32_t rows = 64;
+    while (rows > 8 && gx * ((F->f.n + rows - 1) / rows) < uint64_t(F->cu_count) * 16) rows /= 2;
+    B.rows_per_wg = rows;
+    return NBB_OK;
+}
+
+nbb_status check_device(const nbb_fractal *f) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != f->device) return fail(NBB_E_INVALID, "descriptor belongs to another device");
+    return NBB_OK;
+}
+
+bool overlap(const void *a, const void *b, uint64_t len) {
+    uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + len && y < x + len;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+const uint32_t kRuleMask = 0x1FFu | (0x1FFu << 16);
+
+int map_grid(const nbb_fractal *F, uint64_t work_items) {
+    uint64_t g = (work_items + 511) / 512;
+    uint64_t cap = uint64_t(F->cu_count) * 4;
+    return int(std::max<uint64_t>(1, std::min(g, cap)));
+}
+
+nbb_status launched(hipError_t e, const char *what) {
+    if (e != hipSuccess) return hip_fail(e, what);
+    return NBB_OK;
+}
+
+nbb_status check_box_args(const nbb_fractal *f, const void *p, uint64_t pitch, uint64_t len) {
+    if (f->box.high.empty() || !f->dbox.ptr) return fail(NBB_E_RANGE, "the box of this fractal is too large");
+    if (!p) return fail(NBB_E_INVALID, "null state pointer");
+    if (!aligned16(p)) return fail(NBB_E_INVALID, "box state must be 16-byte aligned");
+    if (pitch < f->f.n || pitch % 16 != 0)
+        return fail(NBB_E_INVALID, "pitch must be >= n and a multiple of 16");
+    if (pitch > 0xFFFFFFFFull) return fail(NBB_E_RANGE, "pitch too large");
+    if (len != f->f.n * pitch) return fail(NBB_E_INVALID, "len must equal n * pitch");
+    return NBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nbb_last_error(void) { return g_err.c_str(); }
+
+const char *nbb_status_string(nbb_status s) {
+    switch (s) {
+        case NBB_OK: return "NBB_OK";
+        case NBB_E_INVALID: return "NBB_E_INVALID";
+        case NBB_E_RANGE: return "NBB_E_RANGE";
+        case NBB_E_NOMEM: return "NBB_E_NOMEM";
+        case NBB_E_DEVICE: return "NBB_E_DEVICE";
+    }
+    return "unknown";
+}
+
+nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
+                          uint32_t tile_level, nbb_plan **out, nbb_plan_view *view) {
+    if (!out || !view) return fail(NBB_E_INVALID, "out and view must not be NULL");
+    *out = nullptr;
+    nbb_plan *p = new (std::nothrow) nbb_plan;
+    if (!p) return fail(NBB_E_NOMEM, "host allocation failed");
+    std::string msg;
+    int v = validate_fractal(k, s, offsets, r, &p->f, &msg);
+    if (v) {
+        delete p;
+        return fail(v == 2 ? NBB_E_RANGE : NBB_E_INVALID, msg);
+    }
+    uint32_t m = tile_level ? tile_level : auto_tile_level(p->f);
+    if (!build_tile_plan(p->f, m, &p->tile, &msg)) {
+        delete p;
+        return fail(NBB_E_INVALID, msg);
+    }
+    const TilePlan &t = p->tile;
+    view->tile_level = t.m;
+    view->tile_side = t.S;
+    view->tile_cells = t.K;
+    view->blocks = t.nblk;
+    view->halo_count = uint32_t(t.halo_src.size());
+    view->box_pitch = t.W;
+    view->box_rows = t.S + 2;
+    view->lds_bytes = t.lds_total;
+    view->tiles = t.ntiles;
+    view->lut0 = t.lut0.data();
+    view->lut1 = t.lut1.data();
+    view->halo_src = t.halo_src.data();
+    view->halo_dst = t.halo_dst.data();
+    *out = p;
+    return NBB_OK;
+}
+
+void nbb_plan_free(nbb_plan *p) { delete p; }
+
+nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, nbb_fractal **out) {
+    if (!out) return fail(NBB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    nbb_fractal *F = new (std::nothrow) nbb_fractal;
+    if (!F) return fail(NBB_E_NOMEM, "host allocation failed");
+    std::string msg;
+    int v = validate_fractal(k, s, offsets, r, &F->f, &msg);
+    if (v) {
+        delete F;
+        return fail(v == 2 ? NBB_E_RANGE : NBB_E_INVALID, msg);
+    }
+    hipError_t e = hipGetDevice(&F->device);
+    if (e != hipSuccess) {
+        delete F;
+        (void)hipGetLastError();
+        return hip_fail(e, "hipGetDevice");
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, F->device) == hipSuccess && cus > 0)
+        F->cu_count = cus;
+    build_map_tables(F->f, &F->maps);
+    build_box_tables(F->f, &F->box);
+    nbb_status st = upload_maps(F);
+    if (st == NBB_OK) st = upload_box(F);
+    if (st == NBB_OK) {
+        if (tiled_supported(F->f)) {
+            if (build_tile_plan(F->f, auto_tile_level(F->f), &F->tile, &msg)) {
+                st = upload_tile(F, F->tile, &F->dtile, &F->tp);
+                if (st == NBB_OK) F->strategy = NBB_STRATEGY_TILED;
+            }
+        }
+    }
+    if (st != NBB_OK) {
+        blob_free(&F->dmap);
+        blob_free(&F->dbox);
+        blob_free(&F->dtile);
+        delete F;
+        return st;
+    }
+    *out = F;
+    return NBB_OK;
+}
+
+void nbb_destroy(nbb_fractal *F) {
+    if (!F) return;
+    blob_free(&F->dmap);
+    blob_free(&F->dbox);
+    blob_free(&F->dtile);
+    delete F;
+}
+
+nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
+    if (!F || !info) return fail(NBB_E_INVALID, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n = F->f.n;
+    info->cells = F->f.cells;
+    info->k = F->f.k;
+    info->s = F->f.s;
+    info->r = F->f.r;
+    info->strategy = F->strategy;
+    if (F->strategy == NBB_STRATEGY_TILED) {
+        info->tiles = F->tile.ntiles;
+        info->tile_level = F->tile.m;
+        info->tile_side = F->tile.S;
+        info->halo_cells = uint32_t(F->tile.halo_src.size());
+        info->lds_bytes = F->tile.lds_total;
+    } else {
+        info->tiles = F->f.cells;
+        info->tile_level = 0;
+        info->tile_side = 1;
+    }
+    info->bbox_pitch = box_pitch(F->f);
+    info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes;
+    return NBB_OK;
+}
+
+nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level) {
+    if (!F) return fail(NBB_E_INVALID, "null descriptor");
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (strategy == NBB_STRATEGY_AUTO) strategy = tiled_supported(F->f) ? NBB_STRATEGY_TILED : NBB_STRATEGY_DIRECT;
+    if (strategy == NBB_STRATEGY_DIRECT) {
+        if (tile_level != 0) return fail(NBB_E_INVALID, "the direct strategy takes no tile level");
+        F->strategy = NBB_STRATEGY_DIRECT;
+        return NBB_OK;
+    }
+    if (strategy != NBB_STRATEGY_TILED) return fail(NBB_E_INVALID, "unknown strategy");
+    std::string msg;
+    TilePlan plan;
+    uint32_t m = tile_level ? tile_level : auto_tile_level(F->f);
+    if (!tiled_supported(F->f) || !build_tile_plan(F->f, m, &plan, &msg))
+        return fail(NBB_E_INVALID, msg.empty() ? "the tiled step does not support this fractal" : msg);
+    DevBlob blob;
+    TileParams T;
+    st = upload_tile(F, plan, &blob, &T);
+    if (st != NBB_OK) return st;
+    blob_free(&F->dtile);
+    F->dtile = blob;
+    F->tile = std::move(plan);
+    F->tp = T;
+    F->strategy = NBB_STRATEGY_TILED;
+    return NBB_OK;
+}
+
+uint64_t nbb_bbox_pitch(const nbb_fractal *F) { return F ? box_pitch(F->f) : 0; }
+
+nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count, int32_t *x, int32_t *y,
+                      void *stream) {
+    if (!F || !x || !y) return fail(NBB_E_INVALID, "null argument");
+    if (count == 0) return NBB_OK;
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_lambda(F->mp, F->lam_words, idx, count, x, y, map_grid(F, count),
+                                  static_cast<hipStream_t>(stream)),
+                    "lambda launch");
+}
+
+nbb_status nbb_nu(const nbb_fractal *F, const int32_t *x, const int32_t *y, uint64_t count, uint32_t *idx,
+                  void *stream) {
+    if (!F || !x || !y || !idx) return fail(NBB_E_INVALID, "null argument");
+    if (count == 0) return NBB_OK;
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_nu(F->mp, F->nu_halves, x, y, count, idx, map_grid(F, count),
+                              static_cast<hipStream_t>(stream)),
+                    "nu launch");
+}
+
+static uint32_t threshold24(double p) {
+    if (p >= 1.0) return 1u << 24;
+    return uint32_t(p * 16777216.0);
+}
+
+nbb_status nbb_init_compact(const nbb_fractal *F, uint8_t *state, uint64_t len, uint64_t seed, double p,
+                            void *stream) {
+    if (!F || !state) return fail(NBB_E_INVALID, "null argument");
+    if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
+    if (!aligned16(state)) return fail(NBB_E_INVALID, "state must be 16-byte aligned");
+    if (!(p >= 0.0 && p <= 1.0)) return fail(NBB_E_INVALID, "p must lie in [0, 1]");
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_init_compact(F->mp, F->lam_words, state, seed, threshold24(p),
+                                        map_grid(F, (len + 15) / 16), static_cast<hipStream_t>(stream)),
+                    "init launch");
+}
+
+nbb_status nbb_init_bbox(const nbb_fractal *F, uint8_t *state, uint64_t pitch, uint64_t len, uint64_t seed,
+                         double p, void *stream) {
+    if (!F) return fail(NBB_E_INVALID, "null descriptor");
+    nbb_status st = check_box_args(F, state, pitch, len);
+    if (st != NBB_OK) return st;
+    if (!(p >= 0.0 && p <= 1.0)) return fail(NBB_E_INVALID, "p must lie in [0, 1]");
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    BoxParams B = F->bp;
+    B.pitch = pitch;
+    return launched(launch_init_box(B, state, seed, threshold24(p), static_cast<hipStream_t>(stream)),
+                    "box init launch");
+}
+
+nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                            uint32_t rule, int *result_in_b, void *stream) {
+    if (!F || !a || !b) return fail(NBB_E_INVALID, "null argument");
+    if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "state buffers must be 16-byte aligned");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (result_in_b) *result_in_b = int(steps & 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *in = a, *out = b;
+    if (F->strategy == NBB_STRATEGY_TILED) {
+        const int per_cu = tiled_groups_per_cu(F->tp.lds_total);
+        const int grid = int(std::min<uint64_t>(uint64_t(F->cu_count) * per_cu, F->tp.ntiles));
+        for (uint32_t i = 0; i < steps; ++i) {
+            hipError_t e = launch_step_tiled(F->mp, F->tp, in, out, rule, grid, s);
+            if (e != hipSuccess) return hip_fail(e, "tiled step launch");
+            std::swap(in, out);
+        }
+    } else {
+        const int grid = map_grid(F, len);
+        for (uint32_t i = 0; i < steps; ++i) {
+            hipError_t e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in, out, rule, grid, s);
+            if (e != hipSuccess) return hip_fail(e, "direct step launch");
+            std::swap(in, out);
+        }
+    }
+    return NBB_OK;
+}
+
+nbb_status nbb_step_bbox(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t pitch, uint64_t len,
+                         uint32_t steps, uint32_t rule, int *result_in_b, void *stream) {
+    if (!F || !b) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_box_args(F, a, pitch, len);
+    if (st != NBB_OK) return st;
+    if (!aligned16(b)) return fail(NBB_E_INVALID, "box state must be 16-byte aligned");
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (result_in_b) *result_in_b = int(steps & 1);
+    BoxParams B = F->bp;
+    B.pitch = pitch;
+    uint8_t *in = a, *out = b;
+    for (uint32_t i = 0; i < steps; ++i) {
+        hipError_t e = launch_step_box(B, in, out, rule, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "box step launch");
+        std::swap(in, out);
+    }
+    return NBB_OK;
+}
+
+nbb_status nbb_expand(const nbb_fractal *F, const uint8_t *compact, uint8_t *bbox, uint64_t pitch, uint64_t len,
+                      void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_box_args(F, bbox, pitch, len);
+    if (st != NBB_OK) return st;
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_fill_zero(bbox, len, s);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    return launched(launch_expand(F->mp, F->lam_words, compact, bbox, pitch, map_grid(F, F->f.cells), s),
+                    "expand launch");
+}
+
+nbb_status nbb_gather(const nbb_fractal *F, const uint8_t *bbox, uint64_t pitch, uint8_t *compact, uint64_t len,
+                      void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
+    nbb_status st = check_box_args(F, bbox, pitch, F->f.n * pitch);
+    if (st != NBB_OK) return st;
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_gather(F->mp, F->lam_words, bbox, pitch, compact, map_grid(F, len),
+                                  static_cast<hipStream_t>(stream)),
+                    "gather launch");
+}
+
+}  // extern "C"

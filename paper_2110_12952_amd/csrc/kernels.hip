@@ -1,0 +1,610 @@
+// HIP kernels for gfx950 (MI355X): the maps lambda / nu, the compact-space
+// automaton step (tiled and per-cell), the bounding-box step, and the
+// initial-state / layout-conversion kernels.
+//
+// Wavefronts are 64 lanes.  State is one byte per cell; four cells share a
+// dword and neighbour counts are formed four bytes at a time (SWAR): no count
+// exceeds 9, so byte lanes never carry into each other.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace nbb {
+
+static constexpr uint32_t kOutside = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t udiv(const UDiv &u, uint32_t a) {
+    uint32_t t = __umulhi(a, u.m);
+    return (t + ((a - t) >> u.s1)) >> u.s2;
+}
+
+__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t sh) {
+    return __builtin_amdgcn_alignbyte(hi, lo, sh);
+}
+
+// Work-group -> work-item mapping that keeps a contiguous range of items on
+// each XCD.  Work-groups are dispatched round-robin over the 8 XCDs
+// (blockIdx % 8), so group x of every 8 gets the x-th slice of the items and
+// walks it in order; neighbouring items then share that XCD's L2.
+struct XcdRange {
+    uint64_t first, end, step;
+};
+__device__ __forceinline__ XcdRange xcd_range(uint32_t wg, uint32_t G, uint64_t T) {
+    XcdRange r;
+    if (G >= 8) {
+        uint32_t x = wg & 7, slot = wg >> 3;
+        uint32_t cnt = (G - x + 7) >> 3;
+        uint64_t before = uint64_t(x) * (G >> 3) + min(x, G & 7);
+        uint64_t start = T * before / G;
+        r.end = T * (before + cnt) / G;
+        r.first = start + slot;
+        r.step = cnt;
+    } else {
+        r.first = wg;
+        r.end = T;
+        r.step = G;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// lambda / nu, chunked look-up tables held in LDS (section 3: lambda maps
+// compact -> embedded, nu embedded -> compact; section 3.1 builds nu from the
+// per-level replica id H; both are sums of one term per level, here evaluated
+// jl (resp. jn) levels per table look-up).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lam_lut(const MapParams &P, const uint32_t *lam, uint32_t i,
+                                        uint32_t &x, uint32_t &y) {
+    uint32_t px = 0, py = 0, scale = 1;
+    for (uint32_t c = 0; c + 1 < P.nchunks_l; ++c) {
+        uint32_t q = udiv(P.divkl, i);
+        uint32_t e = lam[i - q * P.kl];
+        px += (e & 0xFFFFu) * scale;
+        py += (e >> 16) * scale;
+        scale *= P.sl;
+        i = q;
+    }
+    if (P.nchunks_l) {
+        uint32_t e = lam[P.lam_top_off + i];
+        px += (e & 0xFFFFu) * scale;
+        py += (e >> 16) * scale;
+    }
+    x = px;
+    y = py;
+}
+
+__device__ __forceinline__ uint32_t nu_lut(const MapParams &P, const uint16_t *nu, int32_t x,
+                                           int32_t y) {
+    if (uint32_t(x) >= P.n || uint32_t(y) >= P.n) return kOutside;
+    uint32_t ux = uint32_t(x), uy = uint32_t(y), idx = 0, w = 1, bad = 0;
+    for (uint32_t c = 0; c + 1 < P.nchunks_n; ++c) {
+        uint32_t qx = udiv(P.divsn, ux), qy = udiv(P.divsn, uy);
+        uint32_t v = nu[(uy - qy * P.sn) * P.sn + (ux - qx * P.sn)];
+        bad |= (v == 0xFFFFu);
+        idx += v * w;
+        w *= P.kn;
+        ux = qx;
+        uy = qy;
+    }
+    if (P.nchunks_n) {
+        uint32_t v = nu[P.nu_top_off + uy * P.sn_top + ux];
+        bad |= (v == 0xFFFFu);
+        idx += v * w;
+    }
+    return bad ? kOutside : idx;
+}
+
+// Cooperative copy of the map tables into LDS.  Layout: lambda table
+// (lam_words u32) then nu table (nu_halves u16).
+__device__ __forceinline__ void load_map_tables(const MapParams &P, uint32_t lam_words,
+                                                uint32_t nu_halves, uint32_t *lam, uint16_t *nu) {
+    for (uint32_t t = threadIdx.x; t < lam_words; t += blockDim.x) lam[t] = P.lam_lut[t];
+    for (uint32_t t = threadIdx.x; t < nu_halves; t += blockDim.x) nu[t] = P.nu_lut[t];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_lambda(MapParams P, uint32_t lam_words,
+                                                const uint32_t *__restrict__ idx, uint64_t count,
+                                                int32_t *__restrict__ x, int32_t *__restrict__ y) {
+    extern __shared__ __align__(16) uint32_t smem_l[];
+    load_map_tables(P, lam_words, 0, smem_l, nullptr);
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride) {
+        uint64_t i = idx ? uint64_t(idx[t]) : t;
+        int32_t ox = -1, oy = -1;
+        if (i <= P.cells_m1) {
+            uint32_t ux, uy;
+            lam_lut(P, smem_l, uint32_t(i), ux, uy);
+            ox = int32_t(ux);
+            oy = int32_t(uy);
+        }
+        x[t] = ox;
+        y[t] = oy;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_nu(MapParams P, uint32_t nu_halves,
+                                            const int32_t *__restrict__ x,
+                                            const int32_t *__restrict__ y, uint64_t count,
+                                            uint32_t *__restrict__ idx) {
+    extern __shared__ __align__(16) uint16_t smem_n[];
+    load_map_tables(P, 0, nu_halves, nullptr, smem_n);
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride)
+        idx[t] = nu_lut(P, smem_n, x[t], y[t]);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) output number
+// key = y*n + x of the stream seeded with `seed`; alive iff its top 24 bits
+// are below thr = floor(p 2^24) and the cell is a fractal member.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t key) {
+    uint64_t z = seed + (key + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t alive_draw(uint64_t seed, uint32_t thr, uint32_t n, uint32_t x,
+                                               uint32_t y) {
+    uint64_t key = uint64_t(y) * n + x;
+    return uint32_t(splitmix64_at(seed, key) >> 40) < thr ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(512) void k_init_compact(MapParams P, uint32_t lam_words,
+                                                      uint8_t *__restrict__ st, uint64_t seed,
+                                                      uint32_t thr) {
+    extern __shared__ __align__(16) uint32_t smem_i[];
+    load_map_tables(P, lam_words, 0, smem_i, nullptr);
+    const uint64_t cells = uint64_t(P.cells_m1) + 1;
+    const uint64_t chunks = (cells + 15) / 16;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < chunks; c += stride) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        uint64_t base = c * 16;
+        for (int b = 0; b < 16; ++b) {
+            if (base + b >= cells) break;
+            uint32_t x, y;
+            lam_lut(P, smem_i, uint32_t(base + b), x, y);
+            w[b >> 2] |= alive_draw(seed, thr, P.n, x, y) << (8 * (b & 3));
+        }
+        if (base + 16 <= cells) {
+            *reinterpret_cast<uint4 *>(st + base) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+            for (uint64_t b = 0; base + b < cells; ++b) st[base + b] = uint8_t(w[b >> 2] >> (8 * (b & 3)));
+        }
+    }
+}
+
+// Membership of the 16 cells x0..x0+15 of row y as a 16-bit mask (bit j =
+// cell x0 + j), from the low-level bitmap and the high-level byte map.
+struct BoxLane {
+    uint32_t xl, xh, straddle_shift, colmask;
+    bool straddle;
+};
+__device__ __forceinline__ BoxLane box_lane(const BoxParams &B, uint32_t x0) {
+    BoxLane L;
+    L.xh = udiv(B.divSL, x0);
+    L.xl = x0 - L.xh * B.SL;
+    L.straddle = (L.xl + 16 > B.SL) && (L.xh + 1 < B.NH);
+    L.straddle_shift = B.SL - L.xl;
+    uint32_t valid = x0 < B.n ? min(16u, B.n - x0) : 0u;
+    L.colmask = valid >= 16 ? 0xFFFFu : ((1u << valid) - 1u);
+    return L;
+}
+__device__ __forceinline__ uint32_t box_member16(const BoxParams &B, const BoxLane &L, uint32_t y) {
+    uint32_t yh = udiv(B.divSL, y);
+    uint32_t yl = y - yh * B.SL;
+    const uint32_t *row = B.low + size_t(yl) * B.LW;
+    uint32_t wa = row[L.xl >> 5], wb = row[(L.xl >> 5) + 1];
+    uint32_t m = __builtin_amdgcn_alignbit(wb, wa, L.xl & 31) & 0xFFFFu;
+    if (L.xh >= B.NH || !B.high[size_t(yh) * B.NH + L.xh]) m = 0;
+    if (L.straddle && B.high[size_t(yh) * B.NH + L.xh + 1]) m |= (row[0] << L.straddle_shift) & 0xFFFFu;
+    return m & L.colmask;
+}
+// Bit j of the 4-bit nibble -> byte j (value 0 or 1) of a dword.
+__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
+    return __umul24(nib, 0x00204081u) & 0x01010101u;
+}
+
+__global__ __launch_bounds__(256) void k_init_box(BoxParams B, uint8_t *__restrict__ st,
+                                                  uint64_t seed, uint32_t thr) {
+    const uint32_t x0 = (blockIdx.x * 256 + threadIdx.x) * 16;
+    if (x0 >= B.pitch) return;
+    const BoxLane L = box_lane(B, x0);
+    const uint32_t y0 = blockIdx.y * B.rows_per_wg;
+    const uint32_t y1 = min(y0 + B.rows_per_wg, B.n);
+    for (uint32_t y = y0; y < y1; ++y) {
+        uint32_t m = box_member16(B, L, y);
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 16; ++j)
+            if ((m >> j) & 1u) w[j >> 2] |= alive_draw(seed, thr, B.n, x0 + j, y) << (8 * (j & 3));
+        *reinterpret_cast<uint4 *>(st + uint64_t(y) * B.pitch + x0) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion: box <-> compact through lambda.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill_zero(uint4 *__restrict__ p, uint64_t n16) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n16; t += stride)
+        p[t] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(512) void k_expand(MapParams P, uint32_t lam_words,
+                                                const uint8_t *__restrict__ compact,
+                                                uint8_t *__restrict__ box, uint64_t pitch) {
+    extern __shared__ __align__(16) uint32_t smem_e[];
+    load_map_tables(P, lam_words, 0, smem_e, nullptr);
+    const uint64_t cells = uint64_t(P.cells_m1) + 1;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        uint32_t x, y;
+        lam_lut(P, smem_e, uint32_t(i), x, y);
+        box[uint64_t(y) * pitch + x] = compact[i];
+    }
+}
+
+__global__ __launch_bounds__(512) void k_gather(MapParams P, uint32_t lam_words,
+                                                const uint8_t *__restrict__ box, uint64_t pitch,
+                                                uint8_t *__restrict__ compact) {
+    extern __shared__ __align__(16) uint32_t smem_g[];
+    load_map_tables(P, lam_words, 0, smem_g, nullptr);
+    const uint64_t cells = uint64_t(P.cells_m1) + 1;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        uint32_t x, y;
+        lam_lut(P, smem_g, uint32_t(i), x, y);
+        compact[i] = box[uint64_t(y) * pitch + x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compact step, one thread per cell: the paper's stencil procedure as
+// written (section 3): lambda(i), the eight neighbour coordinates, nu of each,
+// read, count, rule.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_words,
+                                                     uint32_t nu_halves,
+                                                     const uint8_t *__restrict__ in,
+                                                     uint8_t *__restrict__ out, uint32_t rule) {
+    extern __shared__ __align__(16) uint32_t smem_d[];
+    uint16_t *nu = reinterpret_cast<uint16_t *>(smem_d + lam_words);
+    load_map_tables(P, lam_words, nu_halves, smem_d, nu);
+    const uint64_t cells = uint64_t(P.cells_m1) + 1;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        uint32_t x, y;
+        lam_lut(P, smem_d, uint32_t(i), x, y);
+        uint32_t live = 0;
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            if (d == 4) continue;
+            uint32_t j = nu_lut(P, nu, int32_t(x) + d % 3 - 1, int32_t(y) + d / 3 - 1);
+            if (j != kOutside) live += in[j];
+        }
+        uint32_t self = in[i];
+        out[i] = uint8_t((rule >> (live + 16 * self)) & 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compact step, tiled (section 3, blocked approach, applied to compact
+// storage).  Tile t = compact cells [t K, (t+1) K), K = k^m: one level-m copy
+// of the fractal, covering the S x S block (S = s^m) of the box whose corner
+// is S * lambda_{r-m}(t).  Since every tile is the same copy of F_m, the
+// position of local cell i inside its block (lut0) and the list of neighbour
+// cells that touch the block (halo) are the same for every tile; only the
+// eight neighbour tiles differ, found with nu_{r-m} of the neighbouring
+// coarse coordinates.  A work-group:
+//   1. scatters the tile's K bytes and its halo into an LDS box of
+//      (S+2) x W bytes (dead cells stay 0),
+//   2. evaluates the rule for each level-1 block (k cells inside an s x s
+//      square) from an (s+2) x (s+2) window, four columns per SWAR dword,
+//      writing results in compact order to an LDS staging row,
+//   3. stores the staging row to global memory with aligned 16-byte stores.
+// Work-groups are persistent and walk an XCD-contiguous range of tiles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void coarse_lambda(const MapParams &P, uint32_t levels, uint32_t t,
+                                              int32_t &X, int32_t &Y) {
+    uint32_t x = 0, y = 0, scale = 1;
+    for (uint32_t mu = 0; mu < levels; ++mu) {
+        uint32_t q = udiv(P.divk, t);
+        uint32_t d = t - q * P.k;
+        x += P.ox[d] * scale;
+        y += P.oy[d] * scale;
+        scale *= P.s;
+        t = q;
+    }
+    X = int32_t(x);
+    Y = int32_t(y);
+}
+__device__ __forceinline__ uint32_t coarse_nu(const MapParams &P, uint32_t levels, uint32_t side,
+                                              int32_t X, int32_t Y) {
+    if (uint32_t(X) >= side || uint32_t(Y) >= side) return kOutside;
+    uint32_t x = uint32_t(X), y = uint32_t(Y), idx = 0, w = 1;
+    for (uint32_t mu = 0; mu < levels; ++mu) {
+        uint32_t qx = udiv(P.divs, x), qy = udiv(P.divs, y);
+        uint32_t h = P.hl[(x - qx * P.s) + P.s * (y - qy * P.s)];
+        if (h == 0xFFu) return kOutside;
+        idx += h * w;
+        w *= P.k;
+        x = qx;
+        y = qy;
+    }
+    return idx;
+}
+// Neighbour tile in direction d (0..7 = the Moore directions in row-major
+// order without the centre), or kOutside.
+__device__ __forceinline__ uint32_t neighbour_tile(const MapParams &P, const TileParams &T,
+                                                   uint32_t t, uint32_t d) {
+    int32_t BX, BY;
+    coarse_lambda(P, T.rm, t, BX, BY);
+    uint32_t dc = d < 4 ? d : d + 1;
+    return coarse_nu(P, T.rm, T.Sc, BX + int32_t(dc % 3) - 1, BY + int32_t(dc / 3) - 1);
+}
+
+template <int SS>
+__global__ __launch_bounds__(256) void k_step_tiled(MapParams P, TileParams T,
+                                                    const uint8_t *__restrict__ in,
+                                                    uint8_t *__restrict__ out, uint32_t rule) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint8_t *box = lds;
+    uint8_t *cout = lds + T.cout_off;
+    __shared__ uint32_t nbr[2][8];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = T.K;
+
+    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
+    for (uint32_t o = tid * 16; o < T.cout_off; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(box + o) = make_uint4(0, 0, 0, 0);
+    if (tid < 8 && R.first < R.end) nbr[0][tid] = neighbour_tile(P, T, uint32_t(R.first), tid);
+    __syncthreads();
+
+    uint32_t buf = 0;
+    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, buf ^= 1) {
+        const uint32_t t = uint32_t(t64);
+        const uint32_t B = t * K;  // first compact cell of the tile (< 2^32)
+        const uint32_t ph = B & 15;
+        const uint32_t q0 = B >> 4;
+        const uint32_t nchunks = (ph + K + 15) >> 4;
+
+        // 1a. own cells -> box
+        const uint16_t *lut = T.lut0p + size_t(ph) * T.lut0_stride;
+        for (uint32_t c = tid; c < nchunks; c += 256) {
+            const uint64_t g = uint64_t(q0 + c) * 16;
+            uint32_t v[4];
+            if (g + 16 <= T.cells) {
+                uint4 w = *reinterpret_cast<const uint4 *>(in + g);
+                v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+            } else {
+                v[0] = v[1] = v[2] = v[3] = 0;
+                for (uint32_t b = 0; g + b < T.cells; ++b) v[b >> 2] |= uint32_t(in[g + b]) << (8 * (b & 3));
+            }
+            const uint4 e0 = *reinterpret_cast<const uint4 *>(lut + 16 * c);
+            const uint4 e1 = *reinterpret_cast<const uint4 *>(lut + 16 * c + 8);
+            const uint32_t e[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const uint32_t off = (e[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
+                if (off != 0xFFFFu) box[off] = uint8_t(v[b >> 2] >> (8 * (b & 3)));
+            }
+        }
+        // 1b. halo cells from the neighbour tiles (0 where a neighbour is absent)
+        for (uint32_t h = tid; h < T.halo_count; h += 256) {
+            const uint32_t src = T.halo_src[h];
+            const uint32_t nt = nbr[buf][src >> 29];
+            box[T.halo_dst[h]] = nt != kOutside ? in[uint64_t(nt) * K + (src & 0x1FFFFFFFu)] : uint8_t(0);
+        }
+        __syncthreads();
+
+        // 2. rule per level-1 block, results in compact order into cout
+        if (tid < 8) {
+            const uint64_t tn = t64 + R.step;
+            if (tn < R.end) nbr[buf ^ 1][tid] = neighbour_tile(P, T, uint32_t(tn), tid);
+        }
+        const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
+        const uint32_t W4 = T.W >> 2;
+        for (uint32_t a = tid; a < T.nblk; a += 256) {
+            const uint32_t base = T.lut1[a];
+            const uint32_t a0 = base >> 2, sh = base & 3;
+            uint32_t lo[SS + 2], hi[SS + 2], H[SS + 2];
+#pragma unroll
+            for (int rr = 0; rr < SS + 2; ++rr) {
+                const uint32_t d0 = box32[a0 + rr * W4], d1 = box32[a0 + rr * W4 + 1];
+                lo[rr] = alignbyte(d1, d0, sh);          // window columns 0..3
+                if (SS == 2) {
+                    hi[rr] = 0;
+                    H[rr] = lo[rr] + (lo[rr] >> 8) + (lo[rr] >> 16);
+                } else {
+                    hi[rr] = d1 >> (8 * sh);             // window columns 4..7
+                    H[rr] = lo[rr] + alignbyte(hi[rr], lo[rr], 1) + alignbyte(hi[rr], lo[rr], 2);
+                }
+            }
+            uint8_t *dst = cout + ph + a * P.k;
+#pragma unroll
+            for (int rr = 0; rr < SS; ++rr) {
+                const uint32_t V = H[rr] + H[rr + 1] + H[rr + 2];  // 3x3 sums incl. self
+                const uint32_t C = SS == 2 ? (lo[rr + 1] >> 8) : alignbyte(hi[rr + 1], lo[rr + 1], 1);
+                // byte c: live neighbours + 16 * self = V + 15 * self
+                const uint32_t I = SS == 4 ? V + (C << 4) - C : V + __umul24(C, 15u);
+#pragma unroll
+                for (int cc = 0; cc < SS; ++cc) {
+                    const uint32_t id = T.hl[cc + SS * rr];
+                    if (id != 0xFFu) dst[id] = uint8_t((rule >> ((I >> (8 * cc)) & 0xFFu)) & 1u);
+                }
+            }
+        }
+        __syncthreads();
+
+        // 3. staging -> global, aligned 16-byte stores; the two edge chunks
+        //    are shared with the neighbouring tiles and written bytewise.
+        for (uint32_t c = tid; c < nchunks; c += 256) {
+            const uint64_t g = uint64_t(q0 + c) * 16;
+            const uint32_t lo_b = 16 * c < ph ? ph : 16 * c;
+            const uint32_t hi_b = min(16 * c + 16, ph + K);
+            if (lo_b == 16 * c && hi_b == 16 * c + 16) {
+                *reinterpret_cast<uint4 *>(out + g) = *reinterpret_cast<const uint4 *>(cout + 16 * c);
+            } else {
+                for (uint32_t b = lo_b; b < hi_b; ++b) out[g + (b - 16 * c)] = cout[b];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bounding-box step (section 4, method 1): every cell of the n x n box is
+// visited.  A thread owns 16 consecutive columns and walks down a band of
+// rows, keeping the horizontal 3-sums of three rows in registers, so each
+// input byte is fetched once per band.  Non-member cells come out 0.
+// ---------------------------------------------------------------------------
+struct Row16 {
+    uint32_t w[4];
+    uint32_t h[4];  // horizontal 3-sums (cols x-1..x+1) per byte
+};
+__device__ __forceinline__ Row16 load_row16(const BoxParams &B, const uint8_t *__restrict__ in,
+                                            uint32_t x0, int64_t y) {
+    Row16 r;
+    if (y < 0 || y >= int64_t(B.n)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r.w[i] = r.h[i] = 0;
+        return r;
+    }
+    const uint8_t *row = in + uint64_t(y) * B.pitch;
+    const uint4 c = *reinterpret_cast<const uint4 *>(row + x0);
+    const uint32_t left = x0 > 0 ? *reinterpret_cast<const uint32_t *>(row + x0 - 4) : 0u;
+    const uint32_t right = x0 + 16 < B.pitch ? *reinterpret_cast<const uint32_t *>(row + x0 + 16) : 0u;
+    r.w[0] = c.x; r.w[1] = c.y; r.w[2] = c.z; r.w[3] = c.w;
+    const uint32_t ext[6] = {left, c.x, c.y, c.z, c.w, right};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        r.h[i] = alignbyte(ext[i + 1], ext[i], 3) + ext[i + 1] + alignbyte(ext[i + 2], ext[i + 1], 1);
+    return r;
+}
+
+template <bool B3S23>
+__global__ __launch_bounds__(256) void k_step_box(BoxParams B, uint32_t gx,
+                                                  const uint8_t *__restrict__ in,
+                                                  uint8_t *__restrict__ out, uint32_t rule) {
+    const uint32_t G = gridDim.x;
+    uint32_t lid = blockIdx.x;
+    if (G >= 8) {  // XCD-contiguous order of (band, column group)
+        uint32_t x = lid & 7, slot = lid >> 3;
+        lid = x * (G >> 3) + min(x, G & 7) + slot;
+    }
+    const uint32_t by = lid / gx, bx = lid - by * gx;
+    const uint32_t x0 = (bx * 256 + threadIdx.x) * 16;
+    if (x0 >= B.pitch) return;
+    const BoxLane L = box_lane(B, x0);
+    const uint32_t y0 = by * B.rows_per_wg;
+    const uint32_t y1 = min(y0 + B.rows_per_wg, B.n);
+    Row16 up = load_row16(B, in, x0, int64_t(y0) - 1);
+    Row16 mid = load_row16(B, in, x0, y0);
+    for (uint32_t y = y0; y < y1; ++y) {
+        const Row16 dn = load_row16(B, in, x0, int64_t(y) + 1);
+        const uint32_t m16 = box_member16(B, L, y);
+        uint32_t o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t V = up.h[i] + mid.h[i] + dn.h[i];  // 3x3 sums incl. self
+            const uint32_t self = mid.w[i];
+            uint32_t res;
+            if (B3S23) {
+                // born with 3, survives with 2 or 3  <=>  (neighbours | self) == 3
+                const uint32_t X = ((V - self) | self) ^ 0x03030303u;
+                res = (~(X + 0x7F7F7F7Fu) & 0x80808080u) >> 7;
+            } else {
+                const uint32_t I = V + (self << 4) - self;  // neighbours + 16 * self
+                res = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) res |= ((rule >> ((I >> (8 * b)) & 0xFFu)) & 1u) << (8 * b);
+            }
+            o[i] = res & nibble_to_bytes((m16 >> (4 * i)) & 0xFu);
+        }
+        *reinterpret_cast<uint4 *>(out + uint64_t(y) * B.pitch + x0) = make_uint4(o[0], o[1], o[2], o[3]);
+        up = mid;
+        mid = dn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_lambda(const MapParams &P, uint32_t lam_words, const uint32_t *idx, uint64_t count,
+                         int32_t *x, int32_t *y, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_lambda, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, idx, count, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, const int32_t *y,
+                     uint64_t count, uint32_t *idx, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_nu, dim3(grid), dim3(512), nu_halves * 2, st, P, nu_halves, x, y, count, idx);
+    return hipGetLastError();
+}
+hipError_t launch_init_compact(const MapParams &P, uint32_t lam_words, uint8_t *st_, uint64_t seed,
+                               uint32_t thr, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_compact, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, st_, seed, thr);
+    return hipGetLastError();
+}
+hipError_t launch_init_box(const BoxParams &B, uint8_t *st_, uint64_t seed, uint32_t thr, hipStream_t st) {
+    const uint32_t gx = uint32_t((B.pitch / 16 + 255) / 256);
+    const uint32_t gy = (B.n + B.rows_per_wg - 1) / B.rows_per_wg;
+    hipLaunchKernelGGL(k_init_box, dim3(gx, gy), dim3(256), 0, st, B, st_, seed, thr);
+    return hipGetLastError();
+}
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t st) {
+    const uint64_t n16 = bytes / 16;
+    const uint32_t grid = uint32_t(std::min<uint64_t>((n16 + 255) / 256, 65536));
+    if (n16) hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint4 *>(p), n16);
+    return hipGetLastError();
+}
+hipError_t launch_expand(const MapParams &P, uint32_t lam_words, const uint8_t *compact, uint8_t *box,
+                         uint64_t pitch, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_expand, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, compact, box, pitch);
+    return hipGetLastError();
+}
+hipError_t launch_gather(const MapParams &P, uint32_t lam_words, const uint8_t *box, uint64_t pitch,
+                         uint8_t *compact, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, box, pitch, compact);
+    return hipGetLastError();
+}
+hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t nu_halves, const uint8_t *in,
+                              uint8_t *out, uint32_t rule, int grid, hipStream_t st) {
+    const size_t lds = size_t(lam_words) * 4 + size_t(nu_halves) * 2;
+    hipLaunchKernelGGL(k_step_direct, dim3(grid), dim3(512), lds, st, P, lam_words, nu_halves, in, out, rule);
+    return hipGetLastError();
+}
+hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                             uint32_t rule, int grid, hipStream_t st) {
+    switch (P.s) {
+        case 2: hipLaunchKernelGGL(k_step_tiled<2>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
+        case 3: hipLaunchKernelGGL(k_step_tiled<3>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
+        case 4: hipLaunchKernelGGL(k_step_tiled<4>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st) {
+    const uint32_t gx = uint32_t((B.pitch / 16 + 255) / 256);
+    const uint32_t gy = (B.n + B.rows_per_wg - 1) / B.rows_per_wg;
+    const uint32_t G = gx * gy;
+    if (rule == ((1u << 3) | ((1u << 2 | 1u << 3) << 16)))
+        hipLaunchKernelGGL(k_step_box<true>, dim3(G), dim3(256), 0, st, B, gx, in, out, rule);
+    else
+        hipLaunchKernelGGL(k_step_box<false>, dim3(G), dim3(256), 0, st, B, gx, in, out, rule);
+    return hipGetLastError();
+}
+
+// Resident work-groups per CU for a given dynamic LDS size (static parts of
+// the kernels are small).
+int tiled_groups_per_cu(uint32_t lds_total) {
+    const uint32_t lds_cu = 160 * 1024;
+    int g = int(lds_cu / (lds_total + 128));
+    return g < 1 ? 1 : (g > 8 ? 8 : g);
+}
+
+}  // namespace nbb

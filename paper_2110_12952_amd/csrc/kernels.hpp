@@ -1,0 +1,29 @@
+// Host launchers for the kernels in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "params.hpp"
+
+namespace nbb {
+
+hipError_t launch_lambda(const MapParams &P, uint32_t lam_words, const uint32_t *idx, uint64_t count,
+                         int32_t *x, int32_t *y, int grid, hipStream_t st);
+hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, const int32_t *y,
+                     uint64_t count, uint32_t *idx, int grid, hipStream_t st);
+hipError_t launch_init_compact(const MapParams &P, uint32_t lam_words, uint8_t *state, uint64_t seed,
+                               uint32_t thr, int grid, hipStream_t st);
+hipError_t launch_init_box(const BoxParams &B, uint8_t *state, uint64_t seed, uint32_t thr, hipStream_t st);
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t st);
+hipError_t launch_expand(const MapParams &P, uint32_t lam_words, const uint8_t *compact, uint8_t *box,
+                         uint64_t pitch, int grid, hipStream_t st);
+hipError_t launch_gather(const MapParams &P, uint32_t lam_words, const uint8_t *box, uint64_t pitch,
+                         uint8_t *compact, int grid, hipStream_t st);
+hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t nu_halves, const uint8_t *in,
+                              uint8_t *out, uint32_t rule, int grid, hipStream_t st);
+hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                             uint32_t rule, int grid, hipStream_t st);
+hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st);
+int tiled_groups_per_cu(uint32_t lds_total);
+
+}  // namespace nbb

@@ -1,0 +1,82 @@
+// Launch parameter blocks shared by the host plan builder and the HIP kernels.
+// Plain structs passed by value as kernel arguments, so every field is uniform
+// across a wavefront and lives in scalar registers / the kernel-argument
+// segment.
+#pragma once
+#include <stdint.h>
+
+namespace nbb {
+
+// Division by a run-time invariant d with one multiply-high (Granlund &
+// Montgomery, "Division by invariant integers using multiplication",
+// PLDI 1994, fig. 4.1): q = (t + ((a - t) >> s1)) >> s2, t = mulhi(a, m).
+// Exact for every 32-bit a and 1 <= d < 2^32.
+struct UDiv {
+    uint32_t m, s1, s2, d;
+};
+
+constexpr int kMaxK = 256;  // k <= s^2 <= 256
+
+// Tables and constants for the maps lambda / nu (section 3) and for every
+// kernel that evaluates them per element.
+struct MapParams {
+    uint32_t k, s, r;
+    uint32_t n;          // s^r (n + 1 < 2^31)
+    uint32_t cells_m1;   // k^r - 1
+    UDiv divk, divs;
+    // lambda in chunks of jl levels: table of k^jl packed (x | y << 16) for the
+    // low chunks, and one of k^jl_top entries for the most significant chunk.
+    uint32_t jl, jl_top, nchunks_l;
+    uint32_t kl, sl;     // k^jl, s^jl
+    UDiv divkl;
+    uint32_t lam_top_off;  // offset (entries) of the top table in lam_lut
+    // nu in chunks of jn levels: (s^jn)^2 table, entry = local compact index
+    // or 0xFFFF, indexed yc * s^jn + xc; the top chunk has its own table.
+    uint32_t jn, jn_top, nchunks_n;
+    uint32_t sn, kn, sn_top;
+    UDiv divsn;
+    uint32_t nu_top_off;
+    const uint32_t *lam_lut;
+    const uint16_t *nu_lut;
+    const uint8_t *ox;   // replica offsets (k entries)
+    const uint8_t *oy;
+    const uint8_t *hl;   // digit pair a + s*b -> replica id, 0xFF if none
+};
+
+// The tiled compact step: a tile is an aligned run of K = k^m compact cells,
+// i.e. one level-m copy of the fractal occupying an S x S block (S = s^m) of
+// the box.  A work-group stages the tile and the neighbour cells that touch
+// it in an LDS box of (S + 2) rows by W bytes.
+struct TileParams {
+    uint32_t m, S, K, W;
+    uint32_t nblk;        // k^(m-1) level-1 blocks per tile
+    uint32_t box_bytes;   // LDS box allocation
+    uint32_t cout_off;    // LDS offset of the compact output staging
+    uint32_t lds_total;
+    uint32_t rm;          // coarse levels r - m
+    uint32_t ntiles;      // k^(r-m)
+    uint32_t Sc;          // s^(r-m)
+    uint32_t halo_count;
+    uint32_t cells;       // k^r (<= 2^32 - 1)
+    uint32_t lut0_stride; // entries per phase copy of lut0
+    const uint16_t *lut0p;   // 16 phase copies: copy p entry j = box offset of local cell j - p
+    const uint16_t *lut1;    // box offset of the window corner of each level-1 block
+    const uint32_t *halo_src;
+    const uint32_t *halo_dst;
+    uint8_t hl[16];       // digit pair a + s*b -> replica id (s <= 4), 0xFF if none
+};
+
+// The bounding-box step.  Membership splits into the low L levels (an
+// SL x SL bitmap, SL = s^L, one row of LW words per y) and the high r - L
+// levels (an NH x NH byte map, NH = s^(r-L)).
+struct BoxParams {
+    uint32_t n;
+    uint32_t SL, LW, NH;
+    UDiv divSL;
+    uint32_t rows_per_wg;
+    uint64_t pitch;
+    const uint32_t *low;
+    const uint8_t *high;
+};
+
+}  // namespace nbb

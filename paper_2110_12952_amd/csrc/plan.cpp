@@ -1,0 +1,270 @@
+// Host-side tables for the compact-fractal kernels.  See plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace nbb {
+
+UDiv make_udiv(uint32_t d) {
+    UDiv u{};
+    u.d = d;
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    uint64_t two_l = uint64_t(1) << l;
+    u.m = uint32_t(((uint64_t(1) << 32) * (two_l - d)) / d + 1);
+    u.s1 = l < 1 ? l : 1;
+    u.s2 = l > 1 ? l - 1 : 0;
+    return u;
+}
+
+uint32_t udiv_apply(const UDiv &u, uint32_t a) {
+    uint32_t t = uint32_t((uint64_t(a) * u.m) >> 32);
+    return (t + ((a - t) >> u.s1)) >> u.s2;
+}
+
+static uint64_t upow(uint64_t b, uint32_t e, bool *overflow) {
+    uint64_t p = 1;
+    for (uint32_t i = 0; i < e; ++i) {
+        if (p > (uint64_t(1) << 40) / (b ? b : 1)) *overflow = true;
+        p *= b;
+        if (p > (uint64_t(1) << 40)) {
+            *overflow = true;
+            p = uint64_t(1) << 40;
+        }
+    }
+    return p;
+}
+
+int validate_fractal(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, Fractal *f,
+                     std::string *msg) {
+    if (!offsets) {
+        *msg = "offsets is NULL";
+        return 1;
+    }
+    if (k == 0) {
+        *msg = "k must be at least 1";
+        return 1;
+    }
+    if (s < 2 || s > 16) {
+        *msg = "s must lie in [2, 16]";
+        return 1;
+    }
+    if (k > s * s) {
+        *msg = "k may not exceed s*s (replicas cannot overlap)";
+        return 1;
+    }
+    Fractal g;
+    std::memset(g.hl, 0xFF, sizeof(g.hl));
+    for (uint32_t j = 0; j < k; ++j) {
+        int32_t a = offsets[2 * j], b = offsets[2 * j + 1];
+        if (a < 0 || b < 0 || a >= int32_t(s) || b >= int32_t(s)) {
+            *msg = "replica offset " + std::to_string(j) + " lies outside [0,s)^2";
+            return 1;
+        }
+        if (g.hl[a + s * b] != 0xFF) {
+            *msg = "replica offset " + std::to_string(j) + " repeats an earlier one";
+            return 1;
+        }
+        g.hl[a + s * b] = uint8_t(j);
+        g.ox[j] = a;
+        g.oy[j] = b;
+    }
+    bool of = false;
+    uint64_t n = upow(s, r, &of);
+    uint64_t cells = upow(k, r, &of);
+    if (of || cells > 0xFFFFFFFFull || n + 1 > 0x7FFFFFFFull) {
+        *msg = "level too large: need k^r <= 2^32-1 and s^r + 1 <= 2^31-1";
+        return 2;
+    }
+    g.k = k;
+    g.s = s;
+    g.r = r;
+    g.n = n;
+    g.cells = cells;
+    *f = g;
+    return 0;
+}
+
+void lambda_levels(const Fractal &f, uint32_t levels, uint64_t i, int64_t *x, int64_t *y) {
+    int64_t px = 0, py = 0, scale = 1;
+    for (uint32_t mu = 0; mu < levels; ++mu) {
+        uint64_t d = i % f.k;
+        i /= f.k;
+        px += f.ox[d] * scale;
+        py += f.oy[d] * scale;
+        scale *= f.s;
+    }
+    *x = px;
+    *y = py;
+}
+
+int64_t nu_levels(const Fractal &f, uint32_t levels, int64_t x, int64_t y) {
+    int64_t side = 1;
+    for (uint32_t mu = 0; mu < levels; ++mu) side *= f.s;
+    if (x < 0 || y < 0 || x >= side || y >= side) return -1;
+    int64_t idx = 0, w = 1;
+    for (uint32_t mu = 0; mu < levels; ++mu) {
+        uint32_t h = f.hl[(x % f.s) + f.s * (y % f.s)];
+        if (h == 0xFF) return -1;
+        idx += int64_t(h) * w;
+        w *= f.k;
+        x /= f.s;
+        y /= f.s;
+    }
+    return idx;
+}
+
+static uint64_t ipow64(uint64_t b, uint32_t e) {
+    uint64_t p = 1;
+    while (e--) p *= b;
+    return p;
+}
+
+void build_map_tables(const Fractal &f, MapTables *t) {
+    // lambda chunk: k^jl <= 4096 entries (two tables <= 32 KB of LDS), s^jl <= 32768
+    // so x, y fit 16 bits.
+    uint32_t jl = 1;
+    while (ipow64(f.k, jl + 1) <= 4096 && ipow64(f.s, jl + 1) <= 32768 && jl + 1 <= std::max(f.r, 1u))
+        ++jl;
+    t->jl = jl;
+    t->nchunks_l = f.r == 0 ? 0 : (f.r + jl - 1) / jl;
+    t->jl_top = f.r == 0 ? 0 : f.r - (t->nchunks_l - 1) * jl;
+    uint64_t kl = ipow64(f.k, jl), kt = ipow64(f.k, t->jl_top);
+    t->lam.assign(kl + kt, 0);
+    for (uint64_t i = 0; i < kl; ++i) {
+        int64_t x, y;
+        lambda_levels(f, jl, i, &x, &y);
+        t->lam[i] = uint32_t(x) | (uint32_t(y) << 16);
+    }
+    t->lam_top_off = uint32_t(kl);
+    for (uint64_t i = 0; i < kt; ++i) {
+        int64_t x, y;
+        lambda_levels(f, t->jl_top, i, &x, &y);
+        t->lam[kl + i] = uint32_t(x) | (uint32_t(y) << 16);
+    }
+    // nu chunk: (s^jn)^2 <= 8192 entries, k^jn <= 65535 (0xFFFF = outside).
+    uint32_t jn = 1;
+    while (ipow64(f.s, 2 * (jn + 1)) <= 8192 && ipow64(f.k, jn + 1) <= 65535 && jn + 1 <= std::max(f.r, 1u))
+        ++jn;
+    t->jn = jn;
+    t->nchunks_n = f.r == 0 ? 0 : (f.r + jn - 1) / jn;
+    t->jn_top = f.r == 0 ? 0 : f.r - (t->nchunks_n - 1) * jn;
+    uint64_t sn = ipow64(f.s, jn), st = ipow64(f.s, t->jn_top);
+    t->nu.assign(sn * sn + st * st, 0xFFFF);
+    for (uint64_t yc = 0; yc < sn; ++yc)
+        for (uint64_t xc = 0; xc < sn; ++xc) {
+            int64_t v = nu_levels(f, jn, int64_t(xc), int64_t(yc));
+            t->nu[yc * sn + xc] = v < 0 ? 0xFFFF : uint16_t(v);
+        }
+    t->nu_top_off = uint32_t(sn * sn);
+    for (uint64_t yc = 0; yc < st; ++yc)
+        for (uint64_t xc = 0; xc < st; ++xc) {
+            int64_t v = nu_levels(f, t->jn_top, int64_t(xc), int64_t(yc));
+            t->nu[sn * sn + yc * st + xc] = v < 0 ? 0xFFFF : uint16_t(v);
+        }
+}
+
+bool tiled_supported(const Fractal &f) { return f.s >= 2 && f.s <= 4 && f.r >= 1; }
+
+static uint32_t box_pitch_bytes(uint32_t S) { return (S + 2 + 3) & ~3u; }
+static uint32_t box_alloc_bytes(uint32_t S) { return (S + 2) * box_pitch_bytes(S) + 8; }
+
+// LDS budget of the tile box: keeps several work-groups resident per CU.
+static const uint32_t kBoxBudget = 24 * 1024;
+// Below this many tiles a smaller tile level is preferred for parallelism.
+static const uint64_t kMinTiles = 512;
+
+uint32_t auto_tile_level(const Fractal &f) {
+    if (!tiled_supported(f)) return 0;
+    uint32_t m = 1;
+    while (m + 1 <= f.r && box_alloc_bytes(uint32_t(ipow64(f.s, m + 1))) <= kBoxBudget) ++m;
+    while (m > 1 && ipow64(f.k, f.r - m) < kMinTiles) --m;
+    return m;
+}
+
+bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg) {
+    *p = TilePlan();
+    if (!tiled_supported(f)) {
+        *msg = "the tiled step needs 2 <= s <= 4 and r >= 1";
+        return false;
+    }
+    if (m < 1 || m > f.r) {
+        *msg = "tile level must lie in [1, r]";
+        return false;
+    }
+    uint64_t S = ipow64(f.s, m);
+    if (S > 250 || box_alloc_bytes(uint32_t(S)) > 65535) {
+        *msg = "tile level too large for 16-bit LDS offsets";
+        return false;
+    }
+    p->m = m;
+    p->S = uint32_t(S);
+    p->K = uint32_t(ipow64(f.k, m));
+    p->W = box_pitch_bytes(p->S);
+    p->nblk = uint32_t(ipow64(f.k, m - 1));
+    p->box_bytes = box_alloc_bytes(p->S);
+    p->cout_off = (p->box_bytes + 15) & ~15u;
+    uint32_t cout_bytes = ((p->K + 16 + 15) & ~15u) + 16;
+    p->lds_total = p->cout_off + cout_bytes;
+    p->rm = f.r - m;
+    p->ntiles = ipow64(f.k, p->rm);
+    p->Sc = uint32_t(ipow64(f.s, p->rm));
+    p->lut0.resize(p->K);
+    for (uint32_t i = 0; i < p->K; ++i) {
+        int64_t x, y;
+        lambda_levels(f, m, i, &x, &y);
+        p->lut0[i] = uint16_t((y + 1) * p->W + (x + 1));
+    }
+    p->lut0_stride = (p->K + 16 + 15) & ~15u;  // >= every 16-entry read of any phase
+    p->lut0p.assign(size_t(16) * p->lut0_stride, 0xFFFF);
+    for (uint32_t ph = 0; ph < 16; ++ph)
+        for (uint32_t i = 0; i < p->K; ++i) p->lut0p[size_t(ph) * p->lut0_stride + i + ph] = p->lut0[i];
+    p->lut1.resize(p->nblk);
+    for (uint32_t b = 0; b < p->nblk; ++b) {
+        int64_t X, Y;
+        lambda_levels(f, m - 1, b, &X, &Y);
+        p->lut1[b] = uint16_t(Y * f.s * p->W + X * f.s);
+    }
+    const int64_t Si = p->S;
+    uint32_t dir8 = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            for (uint32_t i = 0; i < p->K; ++i) {
+                int64_t x, y;
+                lambda_levels(f, m, i, &x, &y);
+                int64_t tx = x + dx * Si, ty = y + dy * Si;
+                if (tx < -1 || ty < -1 || tx > Si || ty > Si) continue;
+                p->halo_src.push_back((dir8 << 29) | i);
+                p->halo_dst.push_back(uint32_t((ty + 1) * p->W + (tx + 1)));
+            }
+            ++dir8;
+        }
+    p->ok = true;
+    return true;
+}
+
+uint64_t box_pitch(const Fractal &f) { return std::max<uint64_t>(16, (f.n + 15) & ~uint64_t(15)); }
+
+void build_box_tables(const Fractal &f, BoxTables *b) {
+    uint32_t L = 0;
+    while (L + 1 <= f.r && ipow64(f.s, L + 1) <= 1024) ++L;
+    b->L = L;
+    b->SL = uint32_t(ipow64(f.s, L));
+    b->LW = (b->SL + 31) / 32 + 1;
+    b->NH = uint32_t(ipow64(f.s, f.r - L));
+    b->low.assign(size_t(b->SL) * b->LW, 0);
+    for (uint32_t y = 0; y < b->SL; ++y)
+        for (uint32_t x = 0; x < b->SL; ++x)
+            if (nu_levels(f, L, x, y) >= 0) b->low[size_t(y) * b->LW + x / 32] |= 1u << (x % 32);
+    if (uint64_t(b->NH) * b->NH > (uint64_t(1) << 26)) {  // the box itself could not be allocated
+        b->high.clear();
+        return;
+    }
+    b->high.assign(size_t(b->NH) * b->NH, 0);
+    for (uint32_t y = 0; y < b->NH; ++y)
+        for (uint32_t x = 0; x < b->NH; ++x) b->high[size_t(y) * b->NH + x] = nu_levels(f, f.r - L, x, y) >= 0;
+}
+
+}  // namespace nbb

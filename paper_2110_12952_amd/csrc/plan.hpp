@@ -1,0 +1,67 @@
+// Host-side description of an NBB fractal and every table the kernels use.
+// Pure C++ (no HIP calls): the C-ABI layer uploads these tables.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "params.hpp"
+
+namespace nbb {
+
+UDiv make_udiv(uint32_t d);
+uint32_t udiv_apply(const UDiv &u, uint32_t a);  // host check of the same formula
+
+struct Fractal {
+    uint32_t k = 0, s = 0, r = 0;
+    uint64_t n = 0, cells = 0;
+    int32_t ox[kMaxK] = {}, oy[kMaxK] = {};
+    uint8_t hl[256];  // a + s*b -> replica id or 0xFF
+};
+
+// Checks the arguments of nbb_create; returns 0 (ok), 1 (invalid) or 2 (range)
+// and fills *msg on failure.
+int validate_fractal(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, Fractal *f,
+                     std::string *msg);
+
+// lambda and nu at `levels` levels (levels <= r), plain digit loops.
+void lambda_levels(const Fractal &f, uint32_t levels, uint64_t i, int64_t *x, int64_t *y);
+int64_t nu_levels(const Fractal &f, uint32_t levels, int64_t x, int64_t y);  // -1 outside
+
+struct MapTables {
+    uint32_t jl = 0, jl_top = 0, nchunks_l = 0, jn = 0, jn_top = 0, nchunks_n = 0;
+    std::vector<uint32_t> lam;  // low table then top table
+    uint32_t lam_top_off = 0;
+    std::vector<uint16_t> nu;   // low table then top table
+    uint32_t nu_top_off = 0;
+};
+void build_map_tables(const Fractal &f, MapTables *t);
+
+struct TilePlan {
+    bool ok = false;
+    uint32_t m = 0, S = 0, K = 0, W = 0, nblk = 0, box_bytes = 0, cout_off = 0, lds_total = 0;
+    uint32_t rm = 0, Sc = 0, lut0_stride = 0;
+    uint64_t ntiles = 0;
+    std::vector<uint16_t> lut0;   // phase 0, K entries
+    std::vector<uint16_t> lut0p;  // 16 phase copies
+    std::vector<uint16_t> lut1;
+    std::vector<uint32_t> halo_src, halo_dst;
+};
+// True if the tiled step supports this fractal (2 <= s <= 4, r >= 1).
+bool tiled_supported(const Fractal &f);
+// Largest usable tile level, then reduced while fewer than `min_tiles` tiles.
+uint32_t auto_tile_level(const Fractal &f);
+// Builds the plan at tile level m (1 <= m <= r); false if it does not fit.
+bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg);
+
+struct BoxTables {
+    uint32_t L = 0, SL = 0, LW = 0, NH = 0;
+    std::vector<uint32_t> low;
+    std::vector<uint8_t> high;
+};
+void build_box_tables(const Fractal &f, BoxTables *b);
+
+uint64_t box_pitch(const Fractal &f);
+
+}  // namespace nbb

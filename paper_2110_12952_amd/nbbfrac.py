@@ -1,0 +1,266 @@
+"""Python binding of libnbbfrac (include/nbbfrac.h): argument marshalling only.
+
+Device memory and streams come from PyTorch-ROCm (torch.cuda tensors and the
+current stream); every step of the computation runs in the library's HIP
+kernels.  The library is loaded from this package directory; if it is missing
+the import of the binding fails with an error that says how to build it --
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbbfrac.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nbbfrac.h")
+
+NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
+NBB_OUTSIDE = 0xFFFFFFFF
+NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
+STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT = 0, 1, 2
+
+
+class NbbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+STATUS_NAMES = {0: "NBB_OK", 1: "NBB_E_INVALID", 2: "NBB_E_RANGE", 3: "NBB_E_NOMEM", 4: "NBB_E_DEVICE"}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("cells", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+                ("k", ctypes.c_uint32), ("s", ctypes.c_uint32), ("r", ctypes.c_uint32),
+                ("strategy", ctypes.c_uint32), ("tile_level", ctypes.c_uint32),
+                ("tile_side", ctypes.c_uint32), ("halo_cells", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("bbox_pitch", ctypes.c_uint64),
+                ("device_table_bytes", ctypes.c_uint64)]
+
+
+class PlanView(ctypes.Structure):
+    _fields_ = [("tile_level", ctypes.c_uint32), ("tile_side", ctypes.c_uint32),
+                ("tile_cells", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("halo_count", ctypes.c_uint32), ("box_pitch", ctypes.c_uint32),
+                ("box_rows", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32),
+                ("tiles", ctypes.c_uint64),
+                ("lut0", ctypes.POINTER(ctypes.c_uint16)), ("lut1", ctypes.POINTER(ctypes.c_uint16)),
+                ("halo_src", ctypes.POINTER(ctypes.c_uint32)), ("halo_dst", ctypes.POINTER(ctypes.c_uint32))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                          "g.build()'` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32p = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+    st = ctypes.c_int
+    L.nbb_create.argtypes = [u32, u32, vp, u32, ctypes.POINTER(vp)]
+    L.nbb_create.restype = st
+    L.nbb_destroy.argtypes = [vp]
+    L.nbb_destroy.restype = None
+    L.nbb_query.argtypes = [vp, ctypes.POINTER(Info)]
+    L.nbb_query.restype = st
+    L.nbb_configure.argtypes = [vp, u32, u32]
+    L.nbb_configure.restype = st
+    L.nbb_lambda.argtypes = [vp, vp, u64, vp, vp, vp]
+    L.nbb_lambda.restype = st
+    L.nbb_nu.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.nbb_nu.restype = st
+    L.nbb_init_compact.argtypes = [vp, vp, u64, u64, ctypes.c_double, vp]
+    L.nbb_init_compact.restype = st
+    L.nbb_init_bbox.argtypes = [vp, vp, u64, u64, u64, ctypes.c_double, vp]
+    L.nbb_init_bbox.restype = st
+    L.nbb_step_compact.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_step_compact.restype = st
+    L.nbb_step_bbox.argtypes = [vp, vp, vp, u64, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_step_bbox.restype = st
+    L.nbb_expand.argtypes = [vp, vp, vp, u64, u64, vp]
+    L.nbb_expand.restype = st
+    L.nbb_gather.argtypes = [vp, vp, u64, vp, u64, vp]
+    L.nbb_gather.restype = st
+    L.nbb_bbox_pitch.argtypes = [vp]
+    L.nbb_bbox_pitch.restype = u64
+    L.nbb_last_error.restype = ctypes.c_char_p
+    L.nbb_status_string.argtypes = [st]
+    L.nbb_status_string.restype = ctypes.c_char_p
+    L.nbb_plan_build.argtypes = [u32, u32, vp, u32, u32, ctypes.POINTER(vp), ctypes.POINTER(PlanView)]
+    L.nbb_plan_build.restype = st
+    L.nbb_plan_free.argtypes = [vp]
+    L.nbb_plan_free.restype = None
+    _lib = L
+    return L
+
+
+def header_symbols() -> list:
+    """Names of the functions include/nbbfrac.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbb_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(status: int) -> None:
+    if status != NBB_OK:
+        raise NbbError(status, lib().nbb_last_error().decode())
+
+
+def _offsets_array(offsets: Sequence[Tuple[int, int]]) -> np.ndarray:
+    return np.ascontiguousarray([c for o in offsets for c in o], dtype=np.int32)
+
+
+def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: int = 0) -> dict:
+    """Host-side tile plan (no device involved) as numpy arrays."""
+    offs = _offsets_array(offsets)
+    h = ctypes.c_void_p()
+    v = PlanView()
+    _check(lib().nbb_plan_build(len(offsets), s, offs.ctypes.data, r, tile_level, ctypes.byref(h),
+                                ctypes.byref(v)))
+    try:
+        out = {f: getattr(v, f) for f in ("tile_level", "tile_side", "tile_cells", "blocks", "halo_count",
+                                          "box_pitch", "box_rows", "lds_bytes", "tiles")}
+        out["lut0"] = np.ctypeslib.as_array(v.lut0, (v.tile_cells,)).copy()
+        out["lut1"] = np.ctypeslib.as_array(v.lut1, (v.blocks,)).copy()
+        out["halo_src"] = np.ctypeslib.as_array(v.halo_src, (v.halo_count,)).copy() if v.halo_count else \
+            np.zeros(0, np.uint32)
+        out["halo_dst"] = np.ctypeslib.as_array(v.halo_dst, (v.halo_count,)).copy() if v.halo_count else \
+            np.zeros(0, np.uint32)
+        return out
+    finally:
+        lib().nbb_plan_free(h)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev_ptr(t, dtype_name: str, numel: Optional[int] = None) -> int:
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Fractal:
+    """Descriptor of F^{k,s} at level r (nbb_create / nbb_destroy)."""
+
+    def __init__(self, s: int, offsets: Sequence[Tuple[int, int]], r: int):
+        offs = _offsets_array(offsets)
+        h = ctypes.c_void_p()
+        _check(lib().nbb_create(len(offsets), s, offs.ctypes.data, r, ctypes.byref(h)))
+        self._h = h
+        self.s, self.r, self.k = int(s), int(r), len(offsets)
+        self.offsets = tuple((int(a), int(b)) for a, b in offsets)
+        inf = self.info()
+        self.n, self.cells, self.pitch = int(inf.n), int(inf.cells), int(inf.bbox_pitch)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(lib().nbb_query(self._h, ctypes.byref(inf)))
+        return inf
+
+    def configure(self, strategy: int = STRATEGY_AUTO, tile_level: int = 0) -> None:
+        _check(lib().nbb_configure(self._h, strategy, tile_level))
+
+    # ---- maps ------------------------------------------------------------
+    def lam(self, idx=None, count: Optional[int] = None, out=None, stream=None):
+        import torch
+        if idx is not None:
+            count = idx.numel()
+            ip = _dev_ptr(idx, "int32") if idx.dtype == torch.int32 else _dev_ptr(idx, "uint32")
+        else:
+            ip = None
+            count = self.cells if count is None else int(count)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        x, y = out if out is not None else (torch.empty(count, dtype=torch.int32, device=dev),
+                                             torch.empty(count, dtype=torch.int32, device=dev))
+        _check(lib().nbb_lambda(self._h, ip, count, _dev_ptr(x, "int32", count), _dev_ptr(y, "int32", count),
+                                _stream(stream)))
+        return x, y
+
+    def nu(self, x, y, out=None, stream=None):
+        import torch
+        count = x.numel()
+        idx = out if out is not None else torch.empty(count, dtype=torch.int32, device=x.device)
+        _check(lib().nbb_nu(self._h, _dev_ptr(x, "int32", count), _dev_ptr(y, "int32", count), count,
+                            _dev_ptr(idx, "int32", count), _stream(stream)))
+        return idx  # int32 view of the uint32 result: NBB_OUTSIDE reads as -1
+
+    # ---- states ----------------------------------------------------------
+    def new_compact(self):
+        import torch
+        return torch.empty(self.cells, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+
+    def new_bbox(self):
+        import torch
+        return torch.empty((self.n, self.pitch), dtype=torch.uint8,
+                           device=torch.device("cuda", torch.cuda.current_device()))
+
+    def init_compact(self, seed: int, p: float, out=None, stream=None):
+        st = self.new_compact() if out is None else out
+        _check(lib().nbb_init_compact(self._h, _dev_ptr(st, "uint8", self.cells), self.cells,
+                                      seed & (2 ** 64 - 1), float(p), _stream(stream)))
+        return st
+
+    def init_bbox(self, seed: int, p: float, out=None, stream=None):
+        st = self.new_bbox() if out is None else out
+        pitch = st.shape[-1] if st.dim() == 2 else self.pitch
+        _check(lib().nbb_init_bbox(self._h, _dev_ptr(st, "uint8"), pitch, st.numel(), seed & (2 ** 64 - 1),
+                                   float(p), _stream(stream)))
+        return st
+
+    def step_compact(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        """Returns the tensor (a or b) that holds the result."""
+        res = ctypes.c_int(0)
+        _check(lib().nbb_step_compact(self._h, _dev_ptr(a, "uint8", self.cells), _dev_ptr(b, "uint8", self.cells),
+                                      self.cells, int(steps), int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a
+
+    def step_bbox(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        res = ctypes.c_int(0)
+        pitch = a.shape[-1]
+        _check(lib().nbb_step_bbox(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), pitch, a.numel(),
+                                   int(steps), int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a
+
+    def expand(self, compact, out=None, stream=None):
+        box = self.new_bbox() if out is None else out
+        _check(lib().nbb_expand(self._h, _dev_ptr(compact, "uint8", self.cells), _dev_ptr(box, "uint8"),
+                                box.shape[-1], box.numel(), _stream(stream)))
+        return box
+
+    def gather(self, box, out=None, stream=None):
+        c = self.new_compact() if out is None else out
+        _check(lib().nbb_gather(self._h, _dev_ptr(box, "uint8"), box.shape[-1], _dev_ptr(c, "uint8", self.cells),
+                                self.cells, _stream(stream)))
+        return c

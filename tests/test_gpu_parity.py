@@ -1,0 +1,311 @@
+"""GPU parity: every entry point of libnbbfrac against the CPU oracle, bit-exact.
+
+All inputs are seeded and synthetic; expected values come from oracle/ only.
+Small levels are compared element by element over whole states; the full-size
+workloads are compared over whole states where the oracle is fast enough and
+on sampled cells (light-cone evaluation) where it is not, plus the compact
+step against the box step on the GPU for the full step counts.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2110_12952_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B3S23 = W.rule_mask("B3/S23")
+RULES = ["B3/S23", "B36/S23", "B1357/S02468", "B2/S"]
+
+
+@pytest.fixture(scope="module")
+def N():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2110_12952_amd import nbbfrac
+    nbbfrac.lib()  # fails loudly if the HIP library is missing
+    return nbbfrac
+
+
+def pair(name, r, N):
+    fd = W.FRACTALS[name]
+    return fd, O.Fractal(fd.s, fd.offsets, r), N.Fractal(fd.s, fd.offsets, r)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def box_view(g, box):
+    """n x n view of an n x pitch host copy; padding must be zero."""
+    b = host(box)
+    assert not b[:, g.n:].any()
+    return b[:, :g.n]
+
+
+SMALL = [("triangle", r) for r in (0, 1, 2, 3, 5, 8)] + \
+        [("carpet", r) for r in (1, 2, 3, 4)] + [("hfractal", r) for r in (1, 2, 4)] + \
+        [("chandelier", r) for r in (2, 5)] + \
+        [("fullsquare", 5), ("vicsek", 4), ("xfractal", 3), ("cantordust", 3), ("cantor", 6),
+         ("single", 6), ("grid4_12", 3)]
+
+
+# ---------------------------------------------------------------- the maps --
+@pytest.mark.parametrize("name,r", SMALL)
+def test_lambda_every_index(N, name, r):
+    fd, o, g = pair(name, r, N)
+    x, y = g.lam()
+    ox, oy = o.lam_many(np.arange(o.cells))
+    np.testing.assert_array_equal(host(x), ox)
+    np.testing.assert_array_equal(host(y), oy)
+    # explicit indices, including ones beyond k^r
+    idx = np.concatenate([W.random_indices(r, 1000, o.cells), [o.cells, o.cells + 7, 2**32 - 1]])
+    idx = idx.astype(np.uint32)
+    x, y = g.lam(dev(idx.view(np.int32)))
+    hx, hy = host(x), host(y)
+    ok = idx < o.cells
+    ox, oy = o.lam_many(idx[ok].astype(np.int64))
+    np.testing.assert_array_equal(hx[ok], ox)
+    np.testing.assert_array_equal(hy[ok], oy)
+    assert (hx[~ok] == -1).all() and (hy[~ok] == -1).all()
+
+
+@pytest.mark.parametrize("name,r", SMALL)
+def test_nu_whole_box_and_ring(N, name, r):
+    fd, o, g = pair(name, r, N)
+    yy, xx = np.mgrid[-1:o.n + 1, -1:o.n + 1]
+    xs, ys = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
+    got = host(g.nu(dev(xs), dev(ys))).astype(np.int64)
+    np.testing.assert_array_equal(got, o.nu_many(xs, ys))
+    # far outside, and the int32 extremes
+    far = np.array([-2**31, 2**31 - 1, o.n + 5, -7], dtype=np.int32)
+    gx, gy = np.repeat(far, 4), np.tile(far, 4)
+    assert (host(g.nu(dev(gx), dev(gy))) == -1).all()
+
+
+def test_maps_empty_count(N):
+    g = N.Fractal(2, W.TRIANGLE.offsets, 4)
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    x, y = g.lam(count=0)
+    assert x.numel() == 0
+    assert g.nu(e, e).numel() == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_maps_random_fractals(N, seed):
+    fd = W.random_fractal(100 + seed, s_choices=(2, 3, 4, 5, 7))
+    r = 1
+    while fd.k ** (r + 1) <= 200000 and fd.s ** (r + 1) <= 4096 and r < 12:
+        r += 1
+    o = O.Fractal(fd.s, fd.offsets, r)
+    g = N.Fractal(fd.s, fd.offsets, r)
+    x, y = g.lam()
+    ox, oy = o.lam_many(np.arange(o.cells))
+    np.testing.assert_array_equal(host(x), ox)
+    np.testing.assert_array_equal(host(y), oy)
+    cx, cy = W.random_coords(seed, 200000, -2, o.n + 2)
+    np.testing.assert_array_equal(host(g.nu(dev(cx), dev(cy))).astype(np.int64), o.nu_many(cx, cy))
+
+
+def test_maps_full_size_triangle_r16(N):
+    # lambda over all 43,046,721 indices; nu(lambda(i)) = i everywhere on the
+    # GPU; lambda and nu on sampled points against the oracle.
+    fd, o, g = pair("triangle", 16, N)
+    x, y = g.lam()
+    idx = g.nu(x, y)
+    iota = torch.arange(o.cells, dtype=torch.int64, device="cuda")
+    assert bool((idx.to(torch.int64) == iota).all())
+    assert bool(((x & y) == 0).all())  # members of the triangle
+    samp = W.random_indices(16, 300000, o.cells).astype(np.int64)
+    ox, oy = o.lam_many(samp)
+    np.testing.assert_array_equal(host(x)[samp], ox)
+    np.testing.assert_array_equal(host(y)[samp], oy)
+    cx, cy = W.random_coords(17, 1000000, -1, o.n + 1)
+    np.testing.assert_array_equal(host(g.nu(dev(cx), dev(cy))).astype(np.int64), o.nu_many(cx, cy))
+
+
+# -------------------------------------------------------------------- init --
+@pytest.mark.parametrize("name,r", SMALL)
+def test_init_compact_and_box(N, name, r):
+    fd, o, g = pair(name, r, N)
+    for seed, p in [(1, 0.5), (12952, 0.3), (2**64 - 3, 0.9), (5, 0.0), (6, 1.0)]:
+        np.testing.assert_array_equal(host(g.init_compact(seed, p)), o.init_compact(seed, p))
+        np.testing.assert_array_equal(box_view(g, g.init_bbox(seed, p)), o.init_bbox(seed, p))
+
+
+# ------------------------------------------------------------ compact step --
+def tile_levels(fd, r):
+    out = [("auto", 0)]
+    for m in range(1, r + 1):
+        S = fd.s ** m
+        if 2 <= fd.s <= 4 and S <= 250 and (S + 2) * ((S + 5) & ~3) + 8 <= 65535:
+            out.append(("tiled", m))
+    out.append(("direct", 0))
+    return out
+
+
+def configure(N, g, how):
+    kind, m = how
+    if kind == "auto":
+        g.configure(N.STRATEGY_AUTO, 0)
+    elif kind == "tiled":
+        g.configure(N.STRATEGY_TILED, m)
+    else:
+        g.configure(N.STRATEGY_DIRECT, 0)
+
+
+@pytest.mark.parametrize("name,r", SMALL)
+def test_step_compact_small(N, name, r):
+    fd, o, g = pair(name, r, N)
+    st0 = o.init_compact(77 + r, 0.45)
+    for how in tile_levels(fd, r):
+        configure(N, g, how)
+        for rule in RULES:
+            rm = W.rule_mask(rule)
+            for steps in (1, 2, 7):
+                a = dev(st0)
+                b = torch.full_like(a, 0xAB)
+                res = g.step_compact(a, b, steps, rm)
+                np.testing.assert_array_equal(host(res), o.compact_steps(st0, rm, steps),
+                                              err_msg=f"{name} r={r} {how} {rule} steps={steps}")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_step_compact_random_fractals(N, seed):
+    fd = W.random_fractal(200 + seed)
+    r = 1
+    while fd.k ** (r + 1) <= 300000 and r < 12:
+        r += 1
+    o = O.Fractal(fd.s, fd.offsets, r)
+    g = N.Fractal(fd.s, fd.offsets, r)
+    st0 = o.init_compact(seed, 0.5)
+    for how in tile_levels(fd, r):
+        configure(N, g, how)
+        a = dev(st0)
+        res = g.step_compact(a, torch.empty_like(a), 5, B3S23)
+        np.testing.assert_array_equal(host(res), o.compact_steps(st0, B3S23, 5), err_msg=str((fd, r, how)))
+
+
+def test_step_compact_zero_steps_and_buffers(N):
+    fd, o, g = pair("triangle", 6, N)
+    a = dev(o.init_compact(3, 0.5))
+    b = torch.full_like(a, 7)
+    a0 = host(a).copy()
+    assert g.step_compact(a, b, 0) is a
+    np.testing.assert_array_equal(host(a), a0)
+    assert (host(b) == 7).all()
+    res = g.step_compact(a, b, 4)
+    assert res is a  # even step count ends in a
+
+
+def test_step_compact_rejects_bad_arguments(N):
+    fd, o, g = pair("triangle", 5, N)
+    a = g.new_compact()
+    b = g.new_compact()
+    big = torch.empty(o.cells + 64, dtype=torch.uint8, device="cuda")
+    L = N.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    assert L.nbb_step_compact(g._h, a.data_ptr(), b.data_ptr(), o.cells - 1, 1, B3S23, None, s) == N.NBB_E_INVALID
+    assert L.nbb_step_compact(g._h, a.data_ptr(), a.data_ptr(), o.cells, 1, B3S23, None, s) == N.NBB_E_INVALID
+    assert L.nbb_step_compact(g._h, big.data_ptr(), big.data_ptr() + 32, o.cells, 1, B3S23, None, s) == \
+        N.NBB_E_INVALID
+    assert L.nbb_step_compact(g._h, big.data_ptr() + 1, b.data_ptr(), o.cells, 1, B3S23, None, s) == \
+        N.NBB_E_INVALID
+    assert L.nbb_step_compact(g._h, a.data_ptr(), b.data_ptr(), o.cells, 1, 1 << 12, None, s) == N.NBB_E_INVALID
+    with pytest.raises(N.NbbError):
+        g.configure(N.STRATEGY_TILED, 9)
+    with pytest.raises(N.NbbError):
+        N.Fractal(5, [(0, 0), (4, 4)], 3).configure(N.STRATEGY_TILED, 1)
+
+
+# ---------------------------------------------------------------- box step --
+@pytest.mark.parametrize("name,r", SMALL)
+def test_step_bbox_small(N, name, r):
+    fd, o, g = pair(name, r, N)
+    st0 = o.init_bbox(91 + r, 0.45)
+    for rule in RULES:
+        rm = W.rule_mask(rule)
+        for steps in (1, 2, 7):
+            a = g.init_bbox(91 + r, 0.45)
+            res = g.step_bbox(a, torch.full_like(a, 0), steps, rm)
+            np.testing.assert_array_equal(box_view(g, res), o.bbox_steps(st0, rm, steps),
+                                          err_msg=f"{name} r={r} {rule} steps={steps}")
+
+
+def test_step_bbox_wider_pitch(N):
+    fd, o, g = pair("hfractal", 4, N)
+    pitch = g.pitch + 48
+    a = torch.empty((o.n, pitch), dtype=torch.uint8, device="cuda")
+    g.init_bbox(4, 0.5, out=a)
+    res = g.step_bbox(a, torch.empty_like(a), 5)
+    np.testing.assert_array_equal(box_view(g, res), o.bbox_steps(o.init_bbox(4, 0.5), B3S23, 5))
+
+
+@pytest.mark.parametrize("name,r", SMALL)
+def test_expand_gather(N, name, r):
+    fd, o, g = pair(name, r, N)
+    st = o.init_compact(8, 0.5)
+    box = g.expand(dev(st))
+    np.testing.assert_array_equal(box_view(g, box), o.expand(st))
+    np.testing.assert_array_equal(host(g.gather(box)), st)
+
+
+# ------------------------------------------------------- the workload sizes --
+def test_small_triangle_workload(N):
+    # triangle r = 10 (59,049 cells), Bernoulli(0.5), seeds 1, 2, 3, 100 steps
+    w = W.SMALL_TRIANGLE
+    fd, o, g = pair("triangle", w.r, N)
+    for seed in w.seeds:
+        st0 = o.init_compact(seed, w.p)
+        a = g.init_compact(seed, w.p)
+        np.testing.assert_array_equal(host(a), st0)
+        res = g.step_compact(a, torch.empty_like(a), w.steps)
+        np.testing.assert_array_equal(host(res), o.compact_steps(st0, B3S23, w.steps))
+        box = g.init_bbox(seed, w.p)
+        resb = g.step_bbox(box, torch.empty_like(box), w.steps)
+        np.testing.assert_array_equal(host(g.gather(resb)), host(res))
+
+
+def test_large_triangle_workload(N):
+    # triangle r = 16 (43,046,721 cells), Bernoulli(0.3), seed 12952: whole
+    # state against the oracle after 2 steps; then 1000 steps of the compact
+    # step against 1000 steps of the box step on the GPU.
+    w = W.LARGE_TRIANGLE
+    fd, o, g = pair("triangle", w.r, N)
+    st0 = o.init_compact(w.seeds[0], w.p)
+    a = g.init_compact(w.seeds[0], w.p)
+    np.testing.assert_array_equal(host(a), st0)
+    b = torch.empty_like(a)
+    res = g.step_compact(a.clone(), b, 2)
+    np.testing.assert_array_equal(host(res), o.compact_steps(st0, B3S23, 2))
+    res = g.step_compact(a, b, w.steps)
+    box = g.init_bbox(w.seeds[0], w.p)
+    resb = g.step_bbox(box, torch.empty_like(box), w.steps)
+    assert torch.equal(g.gather(resb), res)
+    del box, resb
+
+
+@pytest.mark.parametrize("wname", ["carpet_r9", "hfractal_r10"])
+def test_large_carpet_and_h_workloads(N, wname):
+    # carpet r = 9 (134M cells) and H r = 10 (282M cells), Bernoulli(0.5):
+    # whole initial state against the oracle, sampled cells after 1 and 2
+    # steps (light-cone evaluation), then compact vs box on the GPU for 200 steps.
+    w = W.WORKLOADS[wname]
+    fd, o, g = pair(w.fractal.name, w.r, N)
+    st0 = o.init_compact(w.seeds[0], w.p)
+    a = g.init_compact(w.seeds[0], w.p)
+    np.testing.assert_array_equal(host(a), st0)
+    samp = W.random_indices(3, 20000, o.cells).astype(np.int64)
+    b = torch.empty_like(a)
+    for steps in (1, 2):
+        res = g.step_compact(a.clone(), b, steps)
+        np.testing.assert_array_equal(host(res)[samp], o.cells_after(st0, samp, B3S23, steps))
+    res = g.step_compact(a, b, w.steps)
+    box = g.init_bbox(w.seeds[0], w.p)
+    resb = g.step_bbox(box, torch.empty_like(box), w.steps)
+    assert torch.equal(g.gather(resb), res)

@@ -1,0 +1,167 @@
+"""Host-side checks of libnbbfrac that need no GPU: the library loads and
+exports what include/nbbfrac.h declares, argument validation, and the tile
+plan tables against the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2110_12952_amd import nbbfrac as N
+from paper_2110_12952_amd import workloads as W
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    names = N.header_symbols()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = N.lib()
+    for code, name in N.STATUS_NAMES.items():
+        assert L.nbb_status_string(code).decode() == name
+
+
+def _create(k, s, offsets, r):
+    L = N.lib()
+    h = ctypes.c_void_p()
+    arr = np.ascontiguousarray(offsets, dtype=np.int32) if offsets is not None else None
+    st = L.nbb_create(k, s, arr.ctypes.data if arr is not None else None, r, ctypes.byref(h))
+    if st == N.NBB_OK:
+        L.nbb_destroy(h)
+    return st, L.nbb_last_error().decode()
+
+
+@pytest.mark.parametrize("k,s,offsets,r,why", [
+    (0, 2, [0, 0], 3, "k=0"),
+    (1, 1, [0, 0], 3, "s<2"),
+    (1, 17, [0, 0], 3, "s>16"),
+    (5, 2, [0, 0, 1, 0, 0, 1, 1, 1, 0, 0], 3, "k>s^2"),
+    (2, 2, [0, 0, 2, 0], 3, "offset out of range"),
+    (2, 2, [0, 0, -1, 0], 3, "negative offset"),
+    (2, 2, [0, 1, 0, 1], 3, "duplicate offset"),
+    (2, 2, None, 3, "null offsets"),
+])
+def test_create_rejects_invalid(k, s, offsets, r, why):
+    st, msg = _create(k, s, offsets, r)
+    assert st == N.NBB_E_INVALID, why
+    assert msg
+
+
+@pytest.mark.parametrize("k,s,offsets,r", [
+    (3, 2, [0, 0, 1, 0, 0, 1], 21),     # 3^21 > 2^32 - 1
+    (1, 2, [1, 1], 31),                 # n = 2^31 does not fit int32 coordinates
+    (8, 3, [0, 0, 1, 0, 2, 0, 0, 1, 2, 1, 0, 2, 1, 2, 2, 2], 11),  # 8^11 = 2^33
+])
+def test_create_rejects_too_large(k, s, offsets, r):
+    st, msg = _create(k, s, offsets, r)
+    assert st == N.NBB_E_RANGE
+    assert "large" in msg
+
+
+def test_create_null_out():
+    L = N.lib()
+    arr = np.array([0, 0, 1, 0, 0, 1], dtype=np.int32)
+    assert L.nbb_create(3, 2, arr.ctypes.data, 4, None) == N.NBB_E_INVALID
+
+
+def test_create_without_device_reports_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, msg = _create(3, 2, [0, 0, 1, 0, 0, 1], 4)
+    assert st == N.NBB_E_DEVICE
+
+
+def test_null_descriptor_calls():
+    L = N.lib()
+    assert L.nbb_query(None, ctypes.byref(N.Info())) == N.NBB_E_INVALID
+    assert L.nbb_configure(None, 0, 0) == N.NBB_E_INVALID
+    assert L.nbb_step_compact(None, None, None, 0, 1, N.NBB_RULE_B3S23, None, None) == N.NBB_E_INVALID
+    assert L.nbb_bbox_pitch(None) == 0
+    L.nbb_destroy(None)
+
+
+# ----------------------------------------------------------------- tile plan --
+PLAN_CASES = [("triangle", r) for r in (1, 2, 4, 7, 9)] + \
+             [("carpet", r) for r in (1, 2, 4)] + [("hfractal", r) for r in (1, 3, 4)] + \
+             [("chandelier", r) for r in (2, 4)] + [("fullsquare", 5), ("vicsek", 3), ("cantor", 4),
+                                                    ("single", 5), ("grid4_12", 3), ("xfractal", 3)]
+
+
+def _plan_levels(name, r):
+    f = W.FRACTALS[name]
+    levels = [0]
+    for m in range(1, r + 1):
+        if f.s ** m <= 250 and (f.s ** m + 2) * ((f.s ** m + 5) & ~3) + 8 <= 65535:
+            levels.append(m)
+    return levels
+
+
+@pytest.mark.parametrize("name,r", PLAN_CASES)
+def test_plan_tables_match_oracle(name, r):
+    fd = W.FRACTALS[name]
+    for m in _plan_levels(name, r):
+        p = N.plan_tables(fd.s, fd.offsets, r, m)
+        m = p["tile_level"]
+        S, Wp = p["tile_side"], p["box_pitch"]
+        assert S == fd.s ** m and p["tile_cells"] == fd.k ** m and p["tiles"] == fd.k ** (r - m)
+        assert Wp % 4 == 0 and Wp >= S + 2 and p["box_rows"] == S + 2
+        fm = O.Fractal(fd.s, fd.offsets, m)
+        xs, ys = fm.lam_many(np.arange(fm.cells))
+        np.testing.assert_array_equal(p["lut0"], (ys + 1) * Wp + (xs + 1))
+        fb = O.Fractal(fd.s, fd.offsets, m - 1)
+        bx, by = fb.lam_many(np.arange(fb.cells))
+        np.testing.assert_array_equal(p["lut1"], by * fd.s * Wp + bx * fd.s)
+        # halo: every member of each neighbouring level-m copy that lands in
+        # the ring [-1, S]^2 around the tile, with its local index
+        want = set()
+        d8 = 0
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0:
+                    continue
+                for i in range(fm.cells):
+                    tx, ty = xs[i] + dx * S, ys[i] + dy * S
+                    if -1 <= tx <= S and -1 <= ty <= S:
+                        assert fm.nu(xs[i], ys[i]) == i
+                        want.add(((d8 << 29) | i, (ty + 1) * Wp + (tx + 1)))
+                d8 += 1
+        got = set(zip(p["halo_src"].tolist(), p["halo_dst"].tolist()))
+        assert got == want
+        assert len(got) == p["halo_count"]
+
+
+@pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier", "vicsek", "grid4_12"])
+def test_tile_decomposition_identity(name):
+    # lambda(i) = s^m lambda_{r-m}(i div k^m) + lambda_m(i mod k^m): the fact the
+    # tiled step rests on (every aligned run of k^m indices is one level-m copy).
+    fd = W.FRACTALS[name]
+    r = 4 if fd.s > 2 else 6
+    fr = O.Fractal(fd.s, fd.offsets, r)
+    xs, ys = fr.lam_many(np.arange(fr.cells))
+    for m in range(0, r + 1):
+        fm, fc = O.Fractal(fd.s, fd.offsets, m), O.Fractal(fd.s, fd.offsets, r - m)
+        i = np.arange(fr.cells)
+        cx, cy = fc.lam_many(i // fm.cells)
+        lx, ly = fm.lam_many(i % fm.cells)
+        np.testing.assert_array_equal(xs, fd.s ** m * cx + lx)
+        np.testing.assert_array_equal(ys, fd.s ** m * cy + ly)
+
+
+def test_plan_rejects_unsupported():
+    with pytest.raises(N.NbbError):
+        N.plan_tables(5, [(0, 0), (1, 1)], 3)       # s = 5: no tiled step
+    with pytest.raises(N.NbbError):
+        N.plan_tables(2, [(0, 0), (1, 0), (0, 1)], 4, 5)  # m > r
+    with pytest.raises(N.NbbError):
+        N.plan_tables(2, [(0, 0), (1, 0), (0, 1)], 10, 8)  # box too large for 16-bit offsets
+
+
+def test_auto_tile_levels_for_the_workloads():
+    got = {w.name: N.plan_tables(w.fractal.s, w.fractal.offsets, w.r)["tile_level"]
+           for w in W.WORKLOADS.values()}
+    assert got["triangle_r16"] == 7 and got["carpet_r9"] == 4 and got["hfractal_r10"] == 4
