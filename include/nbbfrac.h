@@ -189,20 +189,24 @@ const char *nbb_status_string(nbb_status s);
  * inspection and tests.  The arrays belong to the plan; free it with
  * nbb_plan_free.
  *   lut0[i], i < tile_cells: byte offset in the tile's LDS box of local cell i
- *   lut1[b], b < blocks: offset of the 3-row/col window corner of level-1 block b
+ *   lut1[b], b < blocks: offset of the window corner (one row up, one column
+ *   left) of block b, a level-block_level square of side block_side
  *   halo_src[h] = (direction << 29) | local index in that neighbour tile,
  *   direction = (dy+1)*3 + (dx+1) skipping the centre (0..7);
- *   halo_dst[h] = byte offset in the LDS box.
+ *   halo_dst[h] = byte offset in the LDS box;
+ *   nbr[8 t + d] = tile in direction d of tile t (same numbering), or
+ *   0xFFFFFFFF where that block of the box holds no fractal cell.
  */
 typedef struct nbb_plan nbb_plan;
 typedef struct {
-    uint32_t tile_level, tile_side, tile_cells, blocks, halo_count;
+    uint32_t tile_level, tile_side, tile_cells, block_level, block_side, blocks, halo_count;
     uint32_t box_pitch, box_rows, lds_bytes;
     uint64_t tiles;
     const uint16_t *lut0;
     const uint16_t *lut1;
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
+    const uint32_t *nbr;
 } nbb_plan_view;
 nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
                           uint32_t tile_level, nbb_plan **out, nbb_plan_view *view);

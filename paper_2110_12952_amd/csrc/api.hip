@@ -154,19 +154,25 @@ nbb_status upload_maps(nbb_fractal *F) {
 }
 
 nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TileParams *T) {
-    const void *src[4] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data()};
-    size_t bytes[4] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4};
-    void *dst[4];
-    nbb_status s = upload(blob, src, bytes, 4, dst);
+    const void *src[5] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data()};
+    size_t bytes[5] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
+                       p.nbr.size() * 4};
+    void *dst[5];
+    nbb_status s = upload(blob, src, bytes, 5, dst);
     if (s != NBB_OK) return s;
     *T = TileParams{};
     T->m = p.m;
     T->S = p.S;
     T->K = p.K;
     T->W = p.W;
+    T->q = p.q;
+    T->BS = p.BS;
+    T->CB = p.CB;
+    T->cbmask = p.CB >= 32 ? 0xFFFFFFFFu : ((1u << p.CB) - 1u);
     T->nblk = p.nblk;
     T->box_bytes = p.box_bytes;
-    T->cout_off = p.cout_off;
+    T->bits_off = p.bits_off;
+    T->bits_bytes = p.bits_bytes;
     T->lds_total = p.lds_total;
     T->rm = p.rm;
     T->ntiles = uint32_t(p.ntiles);
@@ -174,12 +180,13 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->halo_count = uint32_t(p.halo_src.size());
     T->cells = uint32_t(F->f.cells);
     T->lut0_stride = p.lut0_stride;
+    T->dummy = p.dummy;
     T->lut0p = static_cast<const uint16_t *>(dst[0]);
     T->lut1 = static_cast<const uint16_t *>(dst[1]);
     T->halo_src = static_cast<const uint32_t *>(dst[2]);
     T->halo_dst = static_cast<const uint32_t *>(dst[3]);
-    std::memset(T->hl, 0xFF, sizeof(T->hl));
-    for (uint32_t i = 0; i < F->f.s * F->f.s && i < 16; ++i) T->hl[i] = F->f.hl[i];
+    T->nbr = static_cast<const uint32_t *>(dst[4]);
+    std::memcpy(T->bid, p.bid, sizeof(T->bid));
     return NBB_OK;
 }
 
@@ -286,6 +293,8 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->tile_level = t.m;
     view->tile_side = t.S;
     view->tile_cells = t.K;
+    view->block_level = t.q;
+    view->block_side = t.BS;
     view->blocks = t.nblk;
     view->halo_count = uint32_t(t.halo_src.size());
     view->box_pitch = t.W;
@@ -296,6 +305,7 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->lut1 = t.lut1.data();
     view->halo_src = t.halo_src.data();
     view->halo_dst = t.halo_dst.data();
+    view->nbr = t.nbr.data();
     *out = p;
     return NBB_OK;
 }
@@ -410,8 +420,9 @@ uint64_t nbb_bbox_pitch(const nbb_fractal *F) { return F ? box_pitch(F->f) : 0; 
 
 nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count, int32_t *x, int32_t *y,
                       void *stream) {
-    if (!F || !x || !y) return fail(NBB_E_INVALID, "null argument");
+    if (!F) return fail(NBB_E_INVALID, "null descriptor");
     if (count == 0) return NBB_OK;
+    if (!x || !y) return fail(NBB_E_INVALID, "null argument");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
     return launched(launch_lambda(F->mp, F->lam_words, idx, count, x, y, map_grid(F, count),
@@ -421,8 +432,9 @@ nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count,
 
 nbb_status nbb_nu(const nbb_fractal *F, const int32_t *x, const int32_t *y, uint64_t count, uint32_t *idx,
                   void *stream) {
-    if (!F || !x || !y || !idx) return fail(NBB_E_INVALID, "null argument");
+    if (!F) return fail(NBB_E_INVALID, "null descriptor");
     if (count == 0) return NBB_OK;
+    if (!x || !y || !idx) return fail(NBB_E_INVALID, "null argument");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
     return launched(launch_nu(F->mp, F->nu_halves, x, y, count, idx, map_grid(F, count),
@@ -475,10 +487,8 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *in = a, *out = b;
     if (F->strategy == NBB_STRATEGY_TILED) {
-        const int per_cu = tiled_groups_per_cu(F->tp.lds_total);
-        const int grid = int(std::min<uint64_t>(uint64_t(F->cu_count) * per_cu, F->tp.ntiles));
         for (uint32_t i = 0; i < steps; ++i) {
-            hipError_t e = launch_step_tiled(F->mp, F->tp, in, out, rule, grid, s);
+            hipError_t e = launch_step_tiled(F->mp, F->tp, in, out, rule, F->cu_count, s);
             if (e != hipSuccess) return hip_fail(e, "tiled step launch");
             std::swap(in, out);
         }

@@ -25,6 +25,11 @@ __device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t
     return __builtin_amdgcn_alignbyte(hi, lo, sh);
 }
 
+// Bit j of the 4-bit nibble -> byte j (value 0 or 1) of a dword.
+__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
+    return __umul24(nib, 0x00204081u) & 0x01010101u;
+}
+
 // Work-group -> work-item mapping that keeps a contiguous range of items on
 // each XCD.  Work-groups are dispatched round-robin over the 8 XCDs
 // (blockIdx % 8), so group x of every 8 gets the x-th slice of the items and
@@ -206,10 +211,6 @@ __device__ __forceinline__ uint32_t box_member16(const BoxParams &B, const BoxLa
     if (L.straddle && B.high[size_t(yh) * B.NH + L.xh + 1]) m |= (row[0] << L.straddle_shift) & 0xFFFFu;
     return m & L.colmask;
 }
-// Bit j of the 4-bit nibble -> byte j (value 0 or 1) of a dword.
-__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
-    return __umul24(nib, 0x00204081u) & 0x01010101u;
-}
 
 __global__ __launch_bounds__(256) void k_init_box(BoxParams B, uint8_t *__restrict__ st,
                                                   uint64_t seed, uint32_t thr) {
@@ -310,150 +311,232 @@ __global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_w
 //   3. stores the staging row to global memory with aligned 16-byte stores.
 // Work-groups are persistent and walk an XCD-contiguous range of tiles.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void coarse_lambda(const MapParams &P, uint32_t levels, uint32_t t,
-                                              int32_t &X, int32_t &Y) {
-    uint32_t x = 0, y = 0, scale = 1;
-    for (uint32_t mu = 0; mu < levels; ++mu) {
-        uint32_t q = udiv(P.divk, t);
-        uint32_t d = t - q * P.k;
-        x += P.ox[d] * scale;
-        y += P.oy[d] * scale;
-        scale *= P.s;
-        t = q;
+// Registers holding the next tile's input while the current one computes.
+template <int CPT, int HPT>
+struct TilePrefetch {
+    uint4 v[CPT];      // 16 compact bytes per chunk
+    uint4 e[CPT][2];   // their 16 LDS-box offsets (u16)
+    uint32_t halo[HPT];
+};
+
+template <int CPT, int HPT>
+__device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t *__restrict__ in,
+                                              uint32_t t, const uint32_t *nb, const uint32_t *hsrc,
+                                              TilePrefetch<CPT, HPT> &pf) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t B = t * T.K;
+    const uint32_t ph = B & 15;
+    const uint32_t nchunks = (ph + T.K + 15) >> 4;
+    const uint8_t *gin = in + (B & ~15u);  // uniform; chunk c at gin + 16 c
+    const uint16_t *lut = T.lut0p + ph * T.lut0_stride;
+    // Only the tile holding the last cell of an array whose length is not a
+    // multiple of 16 has a chunk that may not be read whole.
+    const bool tail = (B + T.K == T.cells) && (T.cells & 15);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const uint32_t c = tid + 256 * j;
+        if (c < nchunks) {
+            if (!tail || c + 1 < nchunks) {
+                pf.v[j] = *reinterpret_cast<const uint4 *>(gin + 16 * c);
+            } else {
+                uint32_t v[4] = {0, 0, 0, 0};
+                const uint32_t nb_ = (T.cells & 15);
+                for (uint32_t b = 0; b < nb_; ++b) v[b >> 2] |= uint32_t(gin[16 * c + b]) << (8 * (b & 3));
+                pf.v[j] = make_uint4(v[0], v[1], v[2], v[3]);
+            }
+            pf.e[j][0] = *reinterpret_cast<const uint4 *>(lut + 16 * c);
+            pf.e[j][1] = *reinterpret_cast<const uint4 *>(lut + 16 * c + 8);
+        }
     }
-    X = int32_t(x);
-    Y = int32_t(y);
-}
-__device__ __forceinline__ uint32_t coarse_nu(const MapParams &P, uint32_t levels, uint32_t side,
-                                              int32_t X, int32_t Y) {
-    if (uint32_t(X) >= side || uint32_t(Y) >= side) return kOutside;
-    uint32_t x = uint32_t(X), y = uint32_t(Y), idx = 0, w = 1;
-    for (uint32_t mu = 0; mu < levels; ++mu) {
-        uint32_t qx = udiv(P.divs, x), qy = udiv(P.divs, y);
-        uint32_t h = P.hl[(x - qx * P.s) + P.s * (y - qy * P.s)];
-        if (h == 0xFFu) return kOutside;
-        idx += h * w;
-        w *= P.k;
-        x = qx;
-        y = qy;
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const uint32_t src = hsrc[j];  // kOutside: this thread has no j-th halo cell
+        const uint32_t nt = src != kOutside ? nb[src >> 29] : kOutside;
+        pf.halo[j] = nt != kOutside ? in[nt * T.K + (src & 0x1FFFFFFFu)] : 0u;
     }
-    return idx;
-}
-// Neighbour tile in direction d (0..7 = the Moore directions in row-major
-// order without the centre), or kOutside.
-__device__ __forceinline__ uint32_t neighbour_tile(const MapParams &P, const TileParams &T,
-                                                   uint32_t t, uint32_t d) {
-    int32_t BX, BY;
-    coarse_lambda(P, T.rm, t, BX, BY);
-    uint32_t dc = d < 4 ? d : d + 1;
-    return coarse_nu(P, T.rm, T.Sc, BX + int32_t(dc % 3) - 1, BY + int32_t(dc / 3) - 1);
 }
 
-template <int SS>
-__global__ __launch_bounds__(256) void k_step_tiled(MapParams P, TileParams T,
-                                                    const uint8_t *__restrict__ in,
-                                                    uint8_t *__restrict__ out, uint32_t rule) {
+// Next states of one block (BS x BS square, CB cells consecutive in compact
+// order) as a CB-bit mask in compact order.  The window is BS+2 rows of the
+// LDS box starting one row up and one column left of the block, read as two
+// dwords per row; byte c of H is the 3-sum of window columns c..c+2, byte c of
+// V the 3x3 sum around block column c (self included), and V + 15 * self =
+// live neighbours + 16 * self indexes the rule word.
+template <int BS>
+__device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32_t *box32, uint32_t W4,
+                                               uint32_t base, uint32_t rule) {
+    const uint32_t a0 = base >> 2, sh = base & 3;
+    uint32_t lo[BS + 2], hi[BS + 2], C[BS + 2], H[BS + 2];
+#pragma unroll
+    for (int rr = 0; rr < BS + 2; ++rr) {
+        const uint32_t d0 = box32[a0 + rr * W4], d1 = box32[a0 + rr * W4 + 1];
+        if (BS == 4) {            // corner column is 4-aligned
+            lo[rr] = d0;
+            hi[rr] = d1;
+        } else {
+            lo[rr] = alignbyte(d1, d0, sh);   // window columns 0..3
+            hi[rr] = d1 >> (8 * sh);          // window columns 4..
+        }
+        if (BS == 2) {
+            C[rr] = lo[rr] >> 8;
+            H[rr] = lo[rr] + C[rr] + (lo[rr] >> 16);
+        } else {
+            C[rr] = alignbyte(hi[rr], lo[rr], 1);
+            H[rr] = lo[rr] + C[rr] + alignbyte(hi[rr], lo[rr], 2);
+        }
+    }
+    uint32_t bits = 0;
+#pragma unroll
+    for (int rr = 0; rr < BS; ++rr) {
+        const uint32_t V = H[rr] + H[rr + 1] + H[rr + 2];
+        const uint32_t I = BS == 4 ? V + (C[rr + 1] << 4) - C[rr + 1] : V + __umul24(C[rr + 1], 15u);
+#pragma unroll
+        for (int cc = 0; cc < BS; ++cc) {
+            // v_bfe takes its offset from the low 5 bits of the operand, and
+            // byte cc of I (<= 24) is exactly those bits of I >> 8cc.
+            const uint32_t id = T.bid[cc + BS * rr];
+#if NBB_MEMBER_BRANCH
+            if (id != 0xFFu) {
+                asm volatile("" ::: "memory");
+                bits |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << id;
+            }
+#else
+            // positions outside the fractal carry id 31, a bit dropped below
+            bits |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << (id & 31u);
+#endif
+        }
+    }
+    return bits & T.cbmask;
+}
+
+#ifndef NBB_MEMBER_BRANCH
+#define NBB_MEMBER_BRANCH 0
+#endif
+#ifndef NBB_TILED_WAVES_PER_SIMD
+#define NBB_TILED_WAVES_PER_SIMD 1
+#endif
+// Compact step, tiled (section 3, blocked approach, applied to compact
+// storage).  Tile t = compact cells [t K, (t+1) K), K = k^m: one level-m copy
+// of the fractal, covering the S x S block (S = s^m) of the box whose corner
+// is S * lambda_{r-m}(t).  Since every tile is the same copy of F_m, the
+// position of local cell i inside its block (lut0) and the list of neighbour
+// cells that touch the block (halo) are the same for every tile; only the
+// eight neighbour tiles differ.  Per tile a work-group
+//   1. scatters the tile's K bytes and its halo into an LDS box of
+//      (S+2) x W bytes (cells outside the fractal stay 0),
+//   2. evaluates the rule for each block of CB cells (block_next) and ORs the
+//      result bits into an LDS bit row in compact order,
+//   3. expands the bit row to bytes and stores it with aligned 16-byte stores.
+// Work-groups are persistent and walk an XCD-contiguous range of tiles as a
+// software pipeline: the next tile's bytes and halo are loaded into registers
+// while the current tile computes, and the neighbour tiles are found two
+// tiles ahead by threads that are idle during the stores.
+template <int BS, int CPT, int HPT>
+__global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
+    MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint8_t *box = lds;
-    uint8_t *cout = lds + T.cout_off;
+    uint32_t *bits32 = reinterpret_cast<uint32_t *>(lds + T.bits_off);
+    const uint16_t *bits16 = reinterpret_cast<const uint16_t *>(lds + T.bits_off);
     __shared__ uint32_t nbr[2][8];
     const uint32_t tid = threadIdx.x;
     const uint32_t K = T.K;
-
     const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
-    for (uint32_t o = tid * 16; o < T.cout_off; o += 256 * 16)
-        *reinterpret_cast<uint4 *>(box + o) = make_uint4(0, 0, 0, 0);
-    if (tid < 8 && R.first < R.end) nbr[0][tid] = neighbour_tile(P, T, uint32_t(R.first), tid);
+
+    for (uint32_t o = tid * 16; o < T.lds_total; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(lds + o) = make_uint4(0, 0, 0, 0);
+    uint32_t hsrc[HPT], hdst[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const uint32_t h = tid + 256 * j;
+        const bool ok = h < T.halo_count;
+        hsrc[j] = ok ? T.halo_src[h] : kOutside;
+        hdst[j] = ok ? T.halo_dst[h] : T.dummy;
+    }
+    // Block windows and bit offsets; threads past the last block repeat it and
+    // write their bits past the tile (never stored).
+    uint32_t blk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
+    const uint32_t nbj = (T.nblk + 255) >> 8;
+    // Neighbour tiles go through LDS two tiles ahead: threads 248..255 load
+    // the eight entries of tile it+2 after the first barrier of tile it and
+    // publish them after its second barrier.
+    if (tid >= 248) {
+        if (R.first < R.end) nbr[0][tid - 248] = T.nbr[R.first * 8 + (tid - 248)];
+        if (R.first + R.step < R.end) nbr[1][tid - 248] = T.nbr[(R.first + R.step) * 8 + (tid - 248)];
+    }
     __syncthreads();
 
-    uint32_t buf = 0;
-    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, buf ^= 1) {
-        const uint32_t t = uint32_t(t64);
-        const uint32_t B = t * K;  // first compact cell of the tile (< 2^32)
+    TilePrefetch<CPT, HPT> pf;
+    if (R.first < R.end) tile_prefetch<CPT, HPT>(T, in, uint32_t(R.first), nbr[0], hsrc, pf);
+
+    const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
+    const uint32_t W4 = T.W >> 2;
+    const uint32_t nbits_words = T.bits_bytes >> 4;  // in 16-byte units
+    uint32_t it = 0;
+    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
+        const uint32_t B = uint32_t(t64) * K;  // first compact cell of the tile (< 2^32)
         const uint32_t ph = B & 15;
-        const uint32_t q0 = B >> 4;
         const uint32_t nchunks = (ph + K + 15) >> 4;
 
-        // 1a. own cells -> box
-        const uint16_t *lut = T.lut0p + size_t(ph) * T.lut0_stride;
-        for (uint32_t c = tid; c < nchunks; c += 256) {
-            const uint64_t g = uint64_t(q0 + c) * 16;
-            uint32_t v[4];
-            if (g + 16 <= T.cells) {
-                uint4 w = *reinterpret_cast<const uint4 *>(in + g);
-                v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
-            } else {
-                v[0] = v[1] = v[2] = v[3] = 0;
-                for (uint32_t b = 0; g + b < T.cells; ++b) v[b >> 2] |= uint32_t(in[g + b]) << (8 * (b & 3));
-            }
-            const uint4 e0 = *reinterpret_cast<const uint4 *>(lut + 16 * c);
-            const uint4 e1 = *reinterpret_cast<const uint4 *>(lut + 16 * c + 8);
-            const uint32_t e[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+        // 1. scatter the prefetched tile and halo into the box; clear the bit
+        //    row.  Offsets of bytes outside the tile point at a never-read byte.
 #pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const uint32_t off = (e[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
-                if (off != 0xFFFFu) box[off] = uint8_t(v[b >> 2] >> (8 * (b & 3)));
+        for (int j = 0; j < CPT; ++j) {
+            if (tid + 256 * j < nchunks) {
+                const uint32_t v[4] = {pf.v[j].x, pf.v[j].y, pf.v[j].z, pf.v[j].w};
+                const uint32_t e[8] = {pf.e[j][0].x, pf.e[j][0].y, pf.e[j][0].z, pf.e[j][0].w,
+                                       pf.e[j][1].x, pf.e[j][1].y, pf.e[j][1].z, pf.e[j][1].w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    box[(e[b >> 1] >> (16 * (b & 1))) & 0xFFFFu] = uint8_t(v[b >> 2] >> (8 * (b & 3)));
             }
         }
-        // 1b. halo cells from the neighbour tiles (0 where a neighbour is absent)
-        for (uint32_t h = tid; h < T.halo_count; h += 256) {
-            const uint32_t src = T.halo_src[h];
-            const uint32_t nt = nbr[buf][src >> 29];
-            box[T.halo_dst[h]] = nt != kOutside ? in[uint64_t(nt) * K + (src & 0x1FFFFFFFu)] : uint8_t(0);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) box[hdst[j]] = uint8_t(pf.halo[j]);
+        for (uint32_t o = tid; o < nbits_words; o += 256)
+            reinterpret_cast<uint4 *>(bits32)[o] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+
+        // 2. start loading the next tile
+        if (t64 + R.step < R.end)
+            tile_prefetch<CPT, HPT>(T, in, uint32_t(t64 + R.step), nbr[(it + 1) & 1], hsrc, pf);
+        uint32_t nb2 = kOutside;
+        if (tid >= 248 && t64 + 2 * R.step < R.end) nb2 = T.nbr[(t64 + 2 * R.step) * 8 + (tid - 248)];
+
+        // 3. rule per block -> bit row (bit ph + local cell index)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j < int(nbj)) {
+                const uint32_t bits = block_next<BS>(T, box32, W4, blk[j], rule);
+                const uint32_t o = ph + (tid + 256 * j) * T.CB;
+                const uint32_t w = o >> 5, s = o & 31;
+                atomicOr(&bits32[w], bits << s);
+                if (s + T.CB > 32) atomicOr(&bits32[w + 1], bits >> (32 - s));
+            }
         }
         __syncthreads();
 
-        // 2. rule per level-1 block, results in compact order into cout
-        if (tid < 8) {
-            const uint64_t tn = t64 + R.step;
-            if (tn < R.end) nbr[buf ^ 1][tid] = neighbour_tile(P, T, uint32_t(tn), tid);
-        }
-        const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
-        const uint32_t W4 = T.W >> 2;
-        for (uint32_t a = tid; a < T.nblk; a += 256) {
-            const uint32_t base = T.lut1[a];
-            const uint32_t a0 = base >> 2, sh = base & 3;
-            uint32_t lo[SS + 2], hi[SS + 2], H[SS + 2];
+        // 4. bit row -> bytes -> global; the two edge chunks are shared with
+        //    the neighbouring tiles and written bytewise.
+        uint8_t *gout = out + (B & ~15u);
 #pragma unroll
-            for (int rr = 0; rr < SS + 2; ++rr) {
-                const uint32_t d0 = box32[a0 + rr * W4], d1 = box32[a0 + rr * W4 + 1];
-                lo[rr] = alignbyte(d1, d0, sh);          // window columns 0..3
-                if (SS == 2) {
-                    hi[rr] = 0;
-                    H[rr] = lo[rr] + (lo[rr] >> 8) + (lo[rr] >> 16);
+        for (int j = 0; j < CPT; ++j) {
+            const uint32_t c = tid + 256 * j;
+            if (c < nchunks) {
+                const uint32_t m16 = bits16[c];
+                const uint4 v = make_uint4(nibble_to_bytes(m16 & 0xFu), nibble_to_bytes((m16 >> 4) & 0xFu),
+                                           nibble_to_bytes((m16 >> 8) & 0xFu), nibble_to_bytes(m16 >> 12));
+                if (16 * c >= ph && 16 * c + 16 <= ph + K) {
+                    *reinterpret_cast<uint4 *>(gout + 16 * c) = v;
                 } else {
-                    hi[rr] = d1 >> (8 * sh);             // window columns 4..7
-                    H[rr] = lo[rr] + alignbyte(hi[rr], lo[rr], 1) + alignbyte(hi[rr], lo[rr], 2);
-                }
-            }
-            uint8_t *dst = cout + ph + a * P.k;
-#pragma unroll
-            for (int rr = 0; rr < SS; ++rr) {
-                const uint32_t V = H[rr] + H[rr + 1] + H[rr + 2];  // 3x3 sums incl. self
-                const uint32_t C = SS == 2 ? (lo[rr + 1] >> 8) : alignbyte(hi[rr + 1], lo[rr + 1], 1);
-                // byte c: live neighbours + 16 * self = V + 15 * self
-                const uint32_t I = SS == 4 ? V + (C << 4) - C : V + __umul24(C, 15u);
-#pragma unroll
-                for (int cc = 0; cc < SS; ++cc) {
-                    const uint32_t id = T.hl[cc + SS * rr];
-                    if (id != 0xFFu) dst[id] = uint8_t((rule >> ((I >> (8 * cc)) & 0xFFu)) & 1u);
+                    const uint32_t lo_b = max(16 * c, ph), hi_b = min(16 * c + 16, ph + K);
+                    for (uint32_t b = lo_b; b < hi_b; ++b) gout[b] = uint8_t((m16 >> (b - 16 * c)) & 1u);
                 }
             }
         }
-        __syncthreads();
-
-        // 3. staging -> global, aligned 16-byte stores; the two edge chunks
-        //    are shared with the neighbouring tiles and written bytewise.
-        for (uint32_t c = tid; c < nchunks; c += 256) {
-            const uint64_t g = uint64_t(q0 + c) * 16;
-            const uint32_t lo_b = 16 * c < ph ? ph : 16 * c;
-            const uint32_t hi_b = min(16 * c + 16, ph + K);
-            if (lo_b == 16 * c && hi_b == 16 * c + 16) {
-                *reinterpret_cast<uint4 *>(out + g) = *reinterpret_cast<const uint4 *>(cout + 16 * c);
-            } else {
-                for (uint32_t b = lo_b; b < hi_b; ++b) out[g + (b - 16 * c)] = cout[b];
-            }
-        }
+        if (tid >= 248) nbr[it & 1][tid - 248] = nb2;
     }
 }
 
@@ -578,15 +661,42 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
     hipLaunchKernelGGL(k_step_direct, dim3(grid), dim3(512), lds, st, P, lam_words, nu_halves, in, out, rule);
     return hipGetLastError();
 }
+// Persistent launch: as many work-groups as can be resident at once (the
+// occupancy of this instantiation for its LDS size), capped by the tiles.
+template <int BS, int CPT, int HPT>
+static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                                 uint32_t rule, int cu_count, hipStream_t st) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT>, 256,
+                                                                T.lds_total);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, T.ntiles);
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st, P, T, in,
+                       out, rule);
+    return hipGetLastError();
+}
+template <int BS>
+static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                                 uint32_t rule, int cu_count, hipStream_t st) {
+    const uint32_t cpt = (T.K + 30 + 16 * 256 - 1) / (16 * 256);
+    const uint32_t hpt = (T.halo_count + 255) / 256;
+    if (cpt <= 1 && hpt <= 1) return launch_tiled_t<BS, 1, 1>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 1 && hpt <= 2) return launch_tiled_t<BS, 1, 2>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 1 && hpt <= 4) return launch_tiled_t<BS, 1, 4>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 1) return launch_tiled_t<BS, 2, 1>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 2) return launch_tiled_t<BS, 2, 2>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 4) return launch_tiled_t<BS, 2, 4>(P, T, in, out, rule, cu_count, st);
+    return hipErrorInvalidValue;
+}
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                             uint32_t rule, int grid, hipStream_t st) {
-    switch (P.s) {
-        case 2: hipLaunchKernelGGL(k_step_tiled<2>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
-        case 3: hipLaunchKernelGGL(k_step_tiled<3>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
-        case 4: hipLaunchKernelGGL(k_step_tiled<4>, dim3(grid), dim3(256), T.lds_total, st, P, T, in, out, rule); break;
+                             uint32_t rule, int cu_count, hipStream_t st) {
+    switch (T.BS) {
+        case 2: return launch_tiled_s<2>(P, T, in, out, rule, cu_count, st);
+        case 3: return launch_tiled_s<3>(P, T, in, out, rule, cu_count, st);
+        case 4: return launch_tiled_s<4>(P, T, in, out, rule, cu_count, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st) {
     const uint32_t gx = uint32_t((B.pitch / 16 + 255) / 256);
@@ -597,14 +707,6 @@ hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, 
     else
         hipLaunchKernelGGL(k_step_box<false>, dim3(G), dim3(256), 0, st, B, gx, in, out, rule);
     return hipGetLastError();
-}
-
-// Resident work-groups per CU for a given dynamic LDS size (static parts of
-// the kernels are small).
-int tiled_groups_per_cu(uint32_t lds_total) {
-    const uint32_t lds_cu = 160 * 1024;
-    int g = int(lds_cu / (lds_total + 128));
-    return g < 1 ? 1 : (g > 8 ? 8 : g);
 }
 
 }  // namespace nbb

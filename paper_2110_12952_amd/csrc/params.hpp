@@ -46,12 +46,16 @@ struct MapParams {
 // The tiled compact step: a tile is an aligned run of K = k^m compact cells,
 // i.e. one level-m copy of the fractal occupying an S x S block (S = s^m) of
 // the box.  A work-group stages the tile and the neighbour cells that touch
-// it in an LDS box of (S + 2) rows by W bytes.
+// it in an LDS box of (S + 2) rows by W bytes, then evaluates the rule per
+// level-q block (side BS = s^q, CB = k^q cells, consecutive in compact order).
 struct TileParams {
     uint32_t m, S, K, W;
-    uint32_t nblk;        // k^(m-1) level-1 blocks per tile
+    uint32_t q, BS, CB;   // block level, block side s^q, cells per block k^q
+    uint32_t cbmask;      // (1 << CB) - 1
+    uint32_t nblk;        // k^(m-q) blocks per tile
     uint32_t box_bytes;   // LDS box allocation
-    uint32_t cout_off;    // LDS offset of the compact output staging
+    uint32_t bits_off;    // LDS offset of the result bit row (bit ph + i = local cell i)
+    uint32_t bits_bytes;
     uint32_t lds_total;
     uint32_t rm;          // coarse levels r - m
     uint32_t ntiles;      // k^(r-m)
@@ -59,11 +63,15 @@ struct TileParams {
     uint32_t halo_count;
     uint32_t cells;       // k^r (<= 2^32 - 1)
     uint32_t lut0_stride; // entries per phase copy of lut0
+    uint32_t dummy;       // a never-read LDS byte that absorbs writes of cells outside the tile
     const uint16_t *lut0p;   // 16 phase copies: copy p entry j = box offset of local cell j - p
-    const uint16_t *lut1;    // box offset of the window corner of each level-1 block
+                             // (dummy where j - p is not a cell of the tile)
+    const uint16_t *lut1;    // box offset of the window corner of each block
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
-    uint8_t hl[16];       // digit pair a + s*b -> replica id (s <= 4), 0xFF if none
+    const uint32_t *nbr;     // 8 neighbour tiles per tile (0xFFFFFFFF = none)
+    uint8_t bid[16];      // position c + BS*row inside a block -> cell id in the block, 0xFF if none
+                          // (the kernel reads 0xFF & 31 = 31: a bit outside cbmask)
 };
 
 // The bounding-box step.  Membership splits into the low L levels (an

@@ -175,10 +175,20 @@ static const uint32_t kBoxBudget = 24 * 1024;
 // Below this many tiles a smaller tile level is preferred for parallelism.
 static const uint64_t kMinTiles = 512;
 
+// Blocks evaluated per thread: 4x4 squares (two levels) for s = 2 when the
+// tile allows, s x s squares (one level) otherwise.
+static uint32_t block_level(const Fractal &f, uint32_t m) { return (f.s == 2 && m >= 2) ? 2 : 1; }
+
+static bool fits_group(const Fractal &f, uint32_t m) {
+    const uint64_t S = ipow64(f.s, m), K = ipow64(f.k, m);
+    return box_alloc_bytes(uint32_t(S)) <= kBoxBudget && K + 30 <= 2 * 16 * 256 &&
+           ipow64(f.k, m - block_level(f, m)) <= 4 * 256;
+}
+
 uint32_t auto_tile_level(const Fractal &f) {
     if (!tiled_supported(f)) return 0;
     uint32_t m = 1;
-    while (m + 1 <= f.r && box_alloc_bytes(uint32_t(ipow64(f.s, m + 1))) <= kBoxBudget) ++m;
+    while (m + 1 <= f.r && fits_group(f, m + 1)) ++m;
     while (m > 1 && ipow64(f.k, f.r - m) < kMinTiles) --m;
     return m;
 }
@@ -198,15 +208,29 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
         *msg = "tile level too large for 16-bit LDS offsets";
         return false;
     }
+    const uint32_t q = block_level(f, m);
+    // A work-group of 256 threads holds at most two 16-byte chunks, four halo
+    // cells and four blocks per thread.
+    const uint64_t K = ipow64(f.k, m);
+    if (K + 30 > 2 * 16 * 256 || ipow64(f.k, m - q) > 4 * 256 || 4 * S + 4 > 4 * 256) {
+        *msg = "tile level too large for one work-group";
+        return false;
+    }
     p->m = m;
     p->S = uint32_t(S);
-    p->K = uint32_t(ipow64(f.k, m));
+    p->K = uint32_t(K);
     p->W = box_pitch_bytes(p->S);
-    p->nblk = uint32_t(ipow64(f.k, m - 1));
+    p->q = q;
+    p->BS = uint32_t(ipow64(f.s, q));
+    p->CB = uint32_t(ipow64(f.k, q));
+    p->nblk = uint32_t(ipow64(f.k, m - q));
     p->box_bytes = box_alloc_bytes(p->S);
-    p->cout_off = (p->box_bytes + 15) & ~15u;
-    uint32_t cout_bytes = ((p->K + 16 + 15) & ~15u) + 16;
-    p->lds_total = p->cout_off + cout_bytes;
+    p->bits_off = (p->box_bytes + 15) & ~15u;
+    // bit ph + i (ph < 16) for local cell i; blocks past the last one (evaluated
+    // to keep every thread on the same path) write beyond K.
+    const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
+    p->bits_bytes = uint32_t(((16 + nblk_pad * p->CB + 64) / 8 + 15) & ~uint64_t(15));
+    p->lds_total = p->bits_off + p->bits_bytes;
     p->rm = f.r - m;
     p->ntiles = ipow64(f.k, p->rm);
     p->Sc = uint32_t(ipow64(f.s, p->rm));
@@ -217,15 +241,22 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
         p->lut0[i] = uint16_t((y + 1) * p->W + (x + 1));
     }
     p->lut0_stride = (p->K + 16 + 15) & ~15u;  // >= every 16-entry read of any phase
-    p->lut0p.assign(size_t(16) * p->lut0_stride, 0xFFFF);
+    p->dummy = (p->S + 2) * p->W + 4;          // slack byte past every window read
+    p->lut0p.assign(size_t(16) * p->lut0_stride, uint16_t(p->dummy));
     for (uint32_t ph = 0; ph < 16; ++ph)
         for (uint32_t i = 0; i < p->K; ++i) p->lut0p[size_t(ph) * p->lut0_stride + i + ph] = p->lut0[i];
     p->lut1.resize(p->nblk);
     for (uint32_t b = 0; b < p->nblk; ++b) {
         int64_t X, Y;
-        lambda_levels(f, m - 1, b, &X, &Y);
-        p->lut1[b] = uint16_t(Y * f.s * p->W + X * f.s);
+        lambda_levels(f, m - q, b, &X, &Y);
+        p->lut1[b] = uint16_t(Y * p->BS * p->W + X * p->BS);
     }
+    std::memset(p->bid, 0xFF, sizeof(p->bid));
+    for (uint32_t rr = 0; rr < p->BS; ++rr)
+        for (uint32_t c = 0; c < p->BS; ++c) {
+            int64_t v = nu_levels(f, q, c, rr);
+            if (v >= 0) p->bid[c + p->BS * rr] = uint8_t(v);
+        }
     const int64_t Si = p->S;
     uint32_t dir8 = 0;
     for (int dy = -1; dy <= 1; ++dy)
@@ -241,6 +272,25 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
             }
             ++dir8;
         }
+    // Neighbour tiles: the tiles' block corners are S * lambda_{r-m}(t); the
+    // eight neighbours are nu_{r-m} of the neighbouring coarse coordinates
+    // (section 3.1 at the coarse level), or none outside the fractal.
+    if (p->ntiles * 8 > (uint64_t(1) << 28)) {
+        *msg = "too many tiles for the neighbour table";
+        return false;
+    }
+    p->nbr.resize(p->ntiles * 8);
+    for (uint64_t t = 0; t < p->ntiles; ++t) {
+        int64_t X, Y;
+        lambda_levels(f, p->rm, t, &X, &Y);
+        uint32_t d8 = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                int64_t v = nu_levels(f, p->rm, X + dx, Y + dy);
+                p->nbr[t * 8 + d8++] = v < 0 ? 0xFFFFFFFFu : uint32_t(v);
+            }
+    }
     p->ok = true;
     return true;
 }

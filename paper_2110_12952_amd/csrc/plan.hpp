@@ -40,13 +40,16 @@ void build_map_tables(const Fractal &f, MapTables *t);
 
 struct TilePlan {
     bool ok = false;
-    uint32_t m = 0, S = 0, K = 0, W = 0, nblk = 0, box_bytes = 0, cout_off = 0, lds_total = 0;
-    uint32_t rm = 0, Sc = 0, lut0_stride = 0;
+    uint32_t m = 0, S = 0, K = 0, W = 0, q = 0, BS = 0, CB = 0, nblk = 0;
+    uint32_t box_bytes = 0, bits_off = 0, bits_bytes = 0, lds_total = 0;
+    uint32_t rm = 0, Sc = 0, lut0_stride = 0, dummy = 0;
+    uint8_t bid[16];
     uint64_t ntiles = 0;
     std::vector<uint16_t> lut0;   // phase 0, K entries
     std::vector<uint16_t> lut0p;  // 16 phase copies
     std::vector<uint16_t> lut1;
     std::vector<uint32_t> halo_src, halo_dst;
+    std::vector<uint32_t> nbr;    // 8 per tile: nu_{r-m} of the neighbouring coarse coordinates
 };
 // True if the tiled step supports this fractal (2 <= s <= 4, r >= 1).
 bool tiled_supported(const Fractal &f);

@@ -16,7 +16,8 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnbbfrac.so")
+# NBB_LIBRARY may name another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("NBB_LIBRARY") or os.path.join(HERE, "libnbbfrac.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "nbbfrac.h")
 
 NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
@@ -45,12 +46,14 @@ class Info(ctypes.Structure):
 
 class PlanView(ctypes.Structure):
     _fields_ = [("tile_level", ctypes.c_uint32), ("tile_side", ctypes.c_uint32),
-                ("tile_cells", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("tile_cells", ctypes.c_uint32), ("block_level", ctypes.c_uint32),
+                ("block_side", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
                 ("halo_count", ctypes.c_uint32), ("box_pitch", ctypes.c_uint32),
                 ("box_rows", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32),
                 ("tiles", ctypes.c_uint64),
                 ("lut0", ctypes.POINTER(ctypes.c_uint16)), ("lut1", ctypes.POINTER(ctypes.c_uint16)),
-                ("halo_src", ctypes.POINTER(ctypes.c_uint32)), ("halo_dst", ctypes.POINTER(ctypes.c_uint32))]
+                ("halo_src", ctypes.POINTER(ctypes.c_uint32)), ("halo_dst", ctypes.POINTER(ctypes.c_uint32)),
+                ("nbr", ctypes.POINTER(ctypes.c_uint32))]
 
 
 _lib = None
@@ -128,7 +131,8 @@ def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: 
     _check(lib().nbb_plan_build(len(offsets), s, offs.ctypes.data, r, tile_level, ctypes.byref(h),
                                 ctypes.byref(v)))
     try:
-        out = {f: getattr(v, f) for f in ("tile_level", "tile_side", "tile_cells", "blocks", "halo_count",
+        out = {f: getattr(v, f) for f in ("tile_level", "tile_side", "tile_cells", "block_level",
+                                          "block_side", "blocks", "halo_count",
                                           "box_pitch", "box_rows", "lds_bytes", "tiles")}
         out["lut0"] = np.ctypeslib.as_array(v.lut0, (v.tile_cells,)).copy()
         out["lut1"] = np.ctypeslib.as_array(v.lut1, (v.blocks,)).copy()
@@ -136,6 +140,7 @@ def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: 
             np.zeros(0, np.uint32)
         out["halo_dst"] = np.ctypeslib.as_array(v.halo_dst, (v.halo_count,)).copy() if v.halo_count else \
             np.zeros(0, np.uint32)
+        out["nbr"] = np.ctypeslib.as_array(v.nbr, (int(v.tiles) * 8,)).copy()
         return out
     finally:
         lib().nbb_plan_free(h)

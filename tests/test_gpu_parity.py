@@ -140,11 +140,15 @@ def test_init_compact_and_box(N, name, r):
 
 # ------------------------------------------------------------ compact step --
 def tile_levels(fd, r):
+    """Every tile level the library accepts for this fractal, plus auto and direct."""
+    from paper_2110_12952_amd import nbbfrac
     out = [("auto", 0)]
     for m in range(1, r + 1):
-        S = fd.s ** m
-        if 2 <= fd.s <= 4 and S <= 250 and (S + 2) * ((S + 5) & ~3) + 8 <= 65535:
-            out.append(("tiled", m))
+        try:
+            nbbfrac.plan_tables(fd.s, fd.offsets, r, m)
+        except nbbfrac.NbbError:
+            continue
+        out.append(("tiled", m))
     out.append(("direct", 0))
     return out
 

@@ -113,9 +113,11 @@ def test_plan_tables_match_oracle(name, r):
         fm = O.Fractal(fd.s, fd.offsets, m)
         xs, ys = fm.lam_many(np.arange(fm.cells))
         np.testing.assert_array_equal(p["lut0"], (ys + 1) * Wp + (xs + 1))
-        fb = O.Fractal(fd.s, fd.offsets, m - 1)
+        q, BS = p["block_level"], p["block_side"]
+        assert BS == fd.s ** q and q in (1, 2) and q <= m
+        fb = O.Fractal(fd.s, fd.offsets, m - q)
         bx, by = fb.lam_many(np.arange(fb.cells))
-        np.testing.assert_array_equal(p["lut1"], by * fd.s * Wp + bx * fd.s)
+        np.testing.assert_array_equal(p["lut1"], by * BS * Wp + bx * BS)
         # halo: every member of each neighbouring level-m copy that lands in
         # the ring [-1, S]^2 around the tile, with its local index
         want = set()
@@ -133,6 +135,12 @@ def test_plan_tables_match_oracle(name, r):
         got = set(zip(p["halo_src"].tolist(), p["halo_dst"].tolist()))
         assert got == want
         assert len(got) == p["halo_count"]
+        # neighbour tiles: the tile whose block is next to tile t's in direction d
+        fc = O.Fractal(fd.s, fd.offsets, r - m)
+        cx, cy = fc.lam_many(np.arange(fc.cells))
+        dirs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dx or dy]
+        want_nbr = np.stack([fc.nu_many(cx + dx, cy + dy) for dx, dy in dirs], axis=1).ravel()
+        np.testing.assert_array_equal(p["nbr"].astype(np.int64), np.where(want_nbr < 0, 2**32 - 1, want_nbr))
 
 
 @pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier", "vicsek", "grid4_12"])
