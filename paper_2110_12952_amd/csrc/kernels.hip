@@ -431,13 +431,11 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
 // software pipeline: the next tile's bytes and halo are loaded into registers
 // while the current tile computes, and the neighbour tiles are found two
 // tiles ahead by threads that are idle during the stores.
-template <int BS, int CPT, int HPT>
+template <int BS, int CPT, int HPT, int BPT>
 __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint8_t *box = lds;
-    uint32_t *bits32 = reinterpret_cast<uint32_t *>(lds + T.bits_off);
-    const uint16_t *bits16 = reinterpret_cast<const uint16_t *>(lds + T.bits_off);
     __shared__ uint32_t nbr[2][8];
     const uint32_t tid = threadIdx.x;
     const uint32_t K = T.K;
@@ -455,10 +453,9 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     }
     // Block windows and bit offsets; threads past the last block repeat it and
     // write their bits past the tile (never stored).
-    uint32_t blk[4];
+    uint32_t blk[BPT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
-    const uint32_t nbj = (T.nblk + 255) >> 8;
+    for (int j = 0; j < BPT; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
     // Neighbour tiles go through LDS two tiles ahead: threads 248..255 load
     // the eight entries of tile it+2 after the first barrier of tile it and
     // publish them after its second barrier.
@@ -479,6 +476,12 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         const uint32_t B = uint32_t(t64) * K;  // first compact cell of the tile (< 2^32)
         const uint32_t ph = B & 15;
         const uint32_t nchunks = (ph + K + 15) >> 4;
+        // Two bit rows, alternating by tile: the row cleared here was last
+        // read by the stores of tile it-2, which every thread finished before
+        // the first barrier of tile it-1.
+        uint8_t *bits = lds + T.bits_off + (it & 1) * T.bits_bytes;
+        uint32_t *bits32 = reinterpret_cast<uint32_t *>(bits);
+        const uint16_t *bits16 = reinterpret_cast<const uint16_t *>(bits);
 
         // 1. scatter the prefetched tile and halo into the box; clear the bit
         //    row.  Offsets of bytes outside the tile point at a never-read byte.
@@ -507,14 +510,12 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
         // 3. rule per block -> bit row (bit ph + local cell index)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j < int(nbj)) {
-                const uint32_t bits = block_next<BS>(T, box32, W4, blk[j], rule);
-                const uint32_t o = ph + (tid + 256 * j) * T.CB;
-                const uint32_t w = o >> 5, s = o & 31;
-                atomicOr(&bits32[w], bits << s);
-                if (s + T.CB > 32) atomicOr(&bits32[w + 1], bits >> (32 - s));
-            }
+        for (int j = 0; j < BPT; ++j) {
+            const uint32_t bits = block_next<BS>(T, box32, W4, blk[j], rule);
+            const uint32_t o = ph + (tid + 256 * j) * T.CB;
+            const uint32_t w = o >> 5, s = o & 31;
+            atomicOr(&bits32[w], bits << s);
+            if (s + T.CB > 32) atomicOr(&bits32[w + 1], bits >> (32 - s));
         }
         __syncthreads();
 
@@ -663,30 +664,39 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
 }
 // Persistent launch: as many work-groups as can be resident at once (the
 // occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT>
+template <int BS, int CPT, int HPT, int BPT>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, int cu_count, hipStream_t st) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT>, 256,
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT, BPT>, 256,
                                                                 T.lds_total);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, T.ntiles);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st, P, T, in,
-                       out, rule);
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st, P, T,
+                       in, out, rule);
     return hipGetLastError();
+}
+template <int BS, int CPT, int HPT>
+static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                                 uint32_t rule, int cu_count, hipStream_t st) {
+    const uint32_t bpt = (T.nblk + 255) / 256;
+    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1>(P, T, in, out, rule, cu_count, st);
+    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2>(P, T, in, out, rule, cu_count, st);
+    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4>(P, T, in, out, rule, cu_count, st);
+    return hipErrorInvalidValue;
 }
 template <int BS>
 static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, int cu_count, hipStream_t st) {
     const uint32_t cpt = (T.K + 30 + 16 * 256 - 1) / (16 * 256);
     const uint32_t hpt = (T.halo_count + 255) / 256;
-    if (cpt <= 1 && hpt <= 1) return launch_tiled_t<BS, 1, 1>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 1 && hpt <= 2) return launch_tiled_t<BS, 1, 2>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 1 && hpt <= 4) return launch_tiled_t<BS, 1, 4>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 1) return launch_tiled_t<BS, 2, 1>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 2) return launch_tiled_t<BS, 2, 2>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 4) return launch_tiled_t<BS, 2, 4>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 1 && hpt <= 1) return launch_tiled_b<BS, 1, 1>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 1 && hpt <= 2) return launch_tiled_b<BS, 1, 2>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 1 && hpt <= 4) return launch_tiled_b<BS, 1, 4>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 1) return launch_tiled_b<BS, 2, 1>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 2) return launch_tiled_b<BS, 2, 2>(P, T, in, out, rule, cu_count, st);
+    if (cpt <= 2 && hpt <= 4) return launch_tiled_b<BS, 2, 4>(P, T, in, out, rule, cu_count, st);
     return hipErrorInvalidValue;
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,

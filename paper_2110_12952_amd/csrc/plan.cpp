@@ -230,7 +230,7 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     // to keep every thread on the same path) write beyond K.
     const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
     p->bits_bytes = uint32_t(((16 + nblk_pad * p->CB + 64) / 8 + 15) & ~uint64_t(15));
-    p->lds_total = p->bits_off + p->bits_bytes;
+    p->lds_total = p->bits_off + 2 * p->bits_bytes;  // two alternating bit rows
     p->rm = f.r - m;
     p->ntiles = ipow64(f.k, p->rm);
     p->Sc = uint32_t(ipow64(f.s, p->rm));

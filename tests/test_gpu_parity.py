@@ -313,3 +313,17 @@ def test_large_carpet_and_h_workloads(N, wname):
     box = g.init_bbox(w.seeds[0], w.p)
     resb = g.step_bbox(box, torch.empty_like(box), w.steps)
     assert torch.equal(g.gather(resb), res)
+
+
+@pytest.mark.parametrize("name,r,steps", [("triangle", 12, 300), ("carpet", 6, 200), ("hfractal", 7, 200),
+                                          ("chandelier", 9, 200), ("grid4_12", 5, 150)])
+def test_long_runs_against_oracle(N, name, r, steps):
+    # Many generations over many tiles: a result that depends on the order
+    # in which work-groups or waves run would show up as a mismatch here.
+    fd, o, g = pair(name, r, N)
+    st0 = o.init_compact(4242 + r, 0.4)
+    want = o.compact_steps(st0, B3S23, steps)
+    for rep in range(2):
+        a = dev(st0)
+        res = g.step_compact(a, torch.empty_like(a), steps)
+        np.testing.assert_array_equal(host(res), want, err_msg=f"{name} r={r} repeat {rep}")
