@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bbox", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (reference for byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -112,6 +114,13 @@ def main():
     rule = W.rule_mask(wl.rule)
     K, Wu = args.steps, args.warmup
     log(f"{wl.name}: n={g.n} cells={g.cells} strategy={info.strategy} tile_level={info.tile_level}")
+
+    if args.copy_probe_mib:
+        src = torch.zeros(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- compact step -----------------------------------------------------
     a = g.init_compact(wl.seeds[0], wl.p)
