@@ -193,6 +193,63 @@ uint32_t auto_tile_level(const Fractal &f) {
     return m;
 }
 
+// LDS bank model: 32 banks of 4 bytes, 32 lanes served per cycle; an
+// instruction costs, per half-wave, the largest number of distinct dwords that
+// fall in one bank.  Used to pick the box pitch for a tile shape: the byte
+// scatter of compact cells (lane c writes byte b of 16-byte chunk c) and the
+// two-dword window reads of the blocks.
+static uint64_t bank_cost(const uint32_t *addr, int lanes) {
+    uint64_t cost = 0;
+    for (int g = 0; g < lanes; g += 32) {
+        uint32_t dw[32];
+        int nd = 0;
+        for (int l = g; l < lanes && l < g + 32; ++l) {
+            uint32_t d = addr[l] >> 2;
+            bool seen = false;
+            for (int e = 0; e < nd; ++e) seen |= dw[e] == d;
+            if (!seen) dw[nd++] = d;
+        }
+        uint32_t per_bank[32] = {};
+        uint32_t worst = 0;
+        for (int e = 0; e < nd; ++e) worst = std::max(worst, ++per_bank[dw[e] & 31]);
+        cost += worst;
+    }
+    return cost;
+}
+
+static uint64_t box_pitch_cost(const Fractal &f, uint32_t m, uint32_t q, uint32_t W) {
+    const uint32_t K = uint32_t(ipow64(f.k, m)), BS = uint32_t(ipow64(f.s, q));
+    std::vector<uint32_t> pos(K);
+    for (uint32_t i = 0; i < K; ++i) {
+        int64_t x, y;
+        lambda_levels(f, m, i, &x, &y);
+        pos[i] = uint32_t((y + 1) * W + (x + 1));
+    }
+    uint64_t cost = 0;
+    uint32_t addr[64];
+    const uint32_t nch = (K + 15) / 16;
+    for (uint32_t c0 = 0; c0 < nch; c0 += 64)
+        for (uint32_t b = 0; b < 16; ++b) {
+            int lanes = 0;
+            for (uint32_t c = c0; c < std::min(c0 + 64, nch); ++c)
+                if (16 * c + b < K) addr[lanes++] = pos[16 * c + b];
+            cost += bank_cost(addr, lanes);
+        }
+    const uint32_t nb = uint32_t(ipow64(f.k, m - q));
+    for (uint32_t a0 = 0; a0 < nb; a0 += 64)
+        for (uint32_t rr = 0; rr < BS + 2; ++rr)
+            for (uint32_t half = 0; half < 2; ++half) {
+                int lanes = 0;
+                for (uint32_t a = a0; a < std::min(a0 + 64, nb); ++a) {
+                    int64_t X, Y;
+                    lambda_levels(f, m - q, a, &X, &Y);
+                    addr[lanes++] = (uint32_t((Y * BS) * W + X * BS) & ~3u) + rr * W + 4 * half;
+                }
+                cost += bank_cost(addr, lanes);
+            }
+    return cost;
+}
+
 bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg) {
     *p = TilePlan();
     if (!tiled_supported(f)) {
@@ -219,12 +276,26 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->m = m;
     p->S = uint32_t(S);
     p->K = uint32_t(K);
+    // Box pitch: the multiple of 4 in [S+2, S+2+64) with the fewest modelled
+    // LDS bank conflicts whose box still fits the budget (the smallest pitch
+    // when none fits, as for large requested tile levels).
     p->W = box_pitch_bytes(p->S);
+    {
+        uint64_t best = box_pitch_cost(f, m, q, p->W);
+        for (uint32_t W = p->W + 4; W < p->W + 64; W += 4) {
+            if ((p->S + 2) * W + 8 > std::max(kBoxBudget, box_alloc_bytes(p->S))) break;
+            const uint64_t c = box_pitch_cost(f, m, q, W);
+            if (c < best) {
+                best = c;
+                p->W = W;
+            }
+        }
+    }
     p->q = q;
     p->BS = uint32_t(ipow64(f.s, q));
     p->CB = uint32_t(ipow64(f.k, q));
     p->nblk = uint32_t(ipow64(f.k, m - q));
-    p->box_bytes = box_alloc_bytes(p->S);
+    p->box_bytes = (p->S + 2) * p->W + 8;
     p->bits_off = (p->box_bytes + 15) & ~15u;
     // bit ph + i (ph < 16) for local cell i; blocks past the last one (evaluated
     // to keep every thread on the same path) write beyond K.
