@@ -171,8 +171,9 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->cbmask = p.CB >= 32 ? 0xFFFFFFFFu : ((1u << p.CB) - 1u);
     T->nblk = p.nblk;
     T->box_bytes = p.box_bytes;
-    T->bits_off = p.bits_off;
-    T->bits_bytes = p.bits_bytes;
+    T->slot_off = p.slot_off;
+    T->nslot = p.nslot;
+    T->divCB = make_udiv(p.CB);
     T->lds_total = p.lds_total;
     T->rm = p.rm;
     T->ntiles = uint32_t(p.ntiles);

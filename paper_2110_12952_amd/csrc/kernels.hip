@@ -470,21 +470,14 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
     const uint32_t W4 = T.W >> 2;
-    const uint32_t nbits_words = T.bits_bytes >> 4;  // in 16-byte units
+    uint16_t *slots = reinterpret_cast<uint16_t *>(lds + T.slot_off);
     uint32_t it = 0;
     for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
         const uint32_t B = uint32_t(t64) * K;  // first compact cell of the tile (< 2^32)
         const uint32_t ph = B & 15;
         const uint32_t nchunks = (ph + K + 15) >> 4;
-        // Two bit rows, alternating by tile: the row cleared here was last
-        // read by the stores of tile it-2, which every thread finished before
-        // the first barrier of tile it-1.
-        uint8_t *bits = lds + T.bits_off + (it & 1) * T.bits_bytes;
-        uint32_t *bits32 = reinterpret_cast<uint32_t *>(bits);
-        const uint16_t *bits16 = reinterpret_cast<const uint16_t *>(bits);
-
-        // 1. scatter the prefetched tile and halo into the box; clear the bit
-        //    row.  Offsets of bytes outside the tile point at a never-read byte.
+        // 1. scatter the prefetched tile and halo into the box.  Offsets of
+        //    bytes outside the tile point at a never-read byte.
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             if (tid + 256 * j < nchunks) {
@@ -498,8 +491,6 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) box[hdst[j]] = uint8_t(pf.halo[j]);
-        for (uint32_t o = tid; o < nbits_words; o += 256)
-            reinterpret_cast<uint4 *>(bits32)[o] = make_uint4(0, 0, 0, 0);
         __syncthreads();
 
         // 2. start loading the next tile
@@ -508,25 +499,29 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         uint32_t nb2 = kOutside;
         if (tid >= 248 && t64 + 2 * R.step < R.end) nb2 = T.nbr[(t64 + 2 * R.step) * 8 + (tid - 248)];
 
-        // 3. rule per block -> bit row (bit ph + local cell index)
+        // 3. rule per block -> slot (the stores of the previous tile, the
+        //    only readers, all finished before this tile's first barrier)
 #pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const uint32_t bits = block_next<BS>(T, box32, W4, blk[j], rule);
-            const uint32_t o = ph + (tid + 256 * j) * T.CB;
-            const uint32_t w = o >> 5, s = o & 31;
-            atomicOr(&bits32[w], bits << s);
-            if (s + T.CB > 32) atomicOr(&bits32[w + 1], bits >> (32 - s));
-        }
+        for (int j = 0; j < BPT; ++j)
+            slots[tid + 256 * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
         __syncthreads();
 
-        // 4. bit row -> bytes -> global; the two edge chunks are shared with
-        //    the neighbouring tiles and written bytewise.
+        // 4. slots -> 16 next states per chunk -> bytes -> global; the two
+        //    edge chunks are shared with the neighbouring tiles and written
+        //    bytewise.  Byte t of chunk c holds local cell 16 c - ph + t.
         uint8_t *gout = out + (B & ~15u);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const uint32_t c = tid + 256 * j;
             if (c < nchunks) {
-                const uint32_t m16 = bits16[c];
+                const uint32_t lo = 16 * c > ph ? 16 * c - ph : 0u;  // first local cell in the chunk
+                const uint32_t a0 = udiv(T.divCB, lo);
+                const uint32_t r0 = lo - a0 * T.CB;
+                uint32_t acc = uint32_t(slots[a0]) >> r0;
+                uint32_t sh = T.CB - r0;
+                for (uint32_t e = 1; e < T.nslot; ++e, sh += T.CB)
+                    if (sh < 16) acc |= uint32_t(slots[a0 + e]) << sh;
+                const uint32_t m16 = (acc << (lo + ph - 16 * c)) & 0xFFFFu;
                 const uint4 v = make_uint4(nibble_to_bytes(m16 & 0xFu), nibble_to_bytes((m16 >> 4) & 0xFu),
                                            nibble_to_bytes((m16 >> 8) & 0xFu), nibble_to_bytes(m16 >> 12));
                 if (16 * c >= ph && 16 * c + 16 <= ph + K) {

@@ -54,8 +54,9 @@ struct TileParams {
     uint32_t cbmask;      // (1 << CB) - 1
     uint32_t nblk;        // k^(m-q) blocks per tile
     uint32_t box_bytes;   // LDS box allocation
-    uint32_t bits_off;    // LDS offset of two result bit rows (bit ph + i = local cell i)
-    uint32_t bits_bytes;  // bytes of one bit row
+    uint32_t slot_off;    // LDS offset of the result slots: u16 slot b = next states of block b
+    uint32_t nslot;       // slots that cover any 16 consecutive cells: 1 + ceil(15 / CB)
+    UDiv divCB;           // division by CB
     uint32_t lds_total;
     uint32_t rm;          // coarse levels r - m
     uint32_t ntiles;      // k^(r-m)

@@ -296,12 +296,13 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->CB = uint32_t(ipow64(f.k, q));
     p->nblk = uint32_t(ipow64(f.k, m - q));
     p->box_bytes = (p->S + 2) * p->W + 8;
-    p->bits_off = (p->box_bytes + 15) & ~15u;
-    // bit ph + i (ph < 16) for local cell i; blocks past the last one (evaluated
-    // to keep every thread on the same path) write beyond K.
+    p->slot_off = (p->box_bytes + 15) & ~15u;
+    // one u16 slot per block (blocks past the last one, evaluated to keep
+    // every thread on the same path, included), plus the slots a 16-cell
+    // chunk at the end of the tile may read past them.
+    p->nslot = 1 + (15 + p->CB - 1) / p->CB;
     const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
-    p->bits_bytes = uint32_t(((16 + nblk_pad * p->CB + 64) / 8 + 15) & ~uint64_t(15));
-    p->lds_total = p->bits_off + 2 * p->bits_bytes;  // two alternating bit rows
+    p->lds_total = p->slot_off + uint32_t(((nblk_pad + p->nslot + 1) * 2 + 15) & ~uint64_t(15));
     p->rm = f.r - m;
     p->ntiles = ipow64(f.k, p->rm);
     p->Sc = uint32_t(ipow64(f.s, p->rm));

@@ -41,7 +41,7 @@ void build_map_tables(const Fractal &f, MapTables *t);
 struct TilePlan {
     bool ok = false;
     uint32_t m = 0, S = 0, K = 0, W = 0, q = 0, BS = 0, CB = 0, nblk = 0;
-    uint32_t box_bytes = 0, bits_off = 0, bits_bytes = 0, lds_total = 0;
+    uint32_t box_bytes = 0, slot_off = 0, nslot = 0, lds_total = 0;
     uint32_t rm = 0, Sc = 0, lut0_stride = 0, dummy = 0;
     uint8_t bid[16];
     uint64_t ntiles = 0;
