@@ -172,7 +172,21 @@ def main():
             "nu_items_per_s": g.cells * args.map_reps / (msn * 1e-3),
             "nu_gbps": 12 * g.cells * args.map_reps / (msn * 1e-3) / 1e9,
             "nu_of_lambda_is_identity": maps_ok}
-    log(f"maps: lambda {maps['lambda_gbps']:.0f} GB/s, nu {maps['nu_gbps']:.0f} GB/s, round trip ok={maps_ok}")
+    # The same maps one level per step (the paper's per-thread maps) and the
+    # lambda sum on the matrix cores (the paper's tensor-core encoding).
+    x2, y2 = torch.empty_like(x), torch.empty_like(y)
+    for name, method in (("digits", N.MAP_DIGITS), ("mfma", N.MAP_MFMA)):
+        try:
+            g.lam(out=(x2, y2), method=method)
+        except N.NbbError:
+            continue
+        ms_m, _ = time_events(torch, lambda: g.lam(out=(x2, y2), method=method), args.map_reps)
+        maps[f"lambda_{name}_gbps"] = 8 * g.cells * args.map_reps / (ms_m * 1e-3) / 1e9
+        maps[f"lambda_{name}_matches_lut"] = bool(torch.equal(x2, x) and torch.equal(y2, y))
+    msd, _ = time_events(torch, lambda: g.nu(x, y, out=idx, method=N.MAP_DIGITS), args.map_reps)
+    maps["nu_digits_gbps"] = 12 * g.cells * args.map_reps / (msd * 1e-3) / 1e9
+    del x2, y2
+    log("maps: " + ", ".join(f"{k} {v:.0f}" if isinstance(v, float) else f"{k} {v}" for k, v in maps.items()))
     del x, y, idx
 
     cpu = None

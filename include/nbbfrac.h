@@ -132,6 +132,24 @@ nbb_status nbb_nu(const nbb_fractal *f, const int32_t *x, const int32_t *y, uint
                   uint32_t *idx, void *stream);
 
 /*
+ * The same maps evaluated three ways (results identical):
+ *   NBB_MAP_LUT    chunked look-up tables (the default of nbb_lambda / nbb_nu);
+ *   NBB_MAP_DIGITS one level per step, as the per-thread maps of section 3.1;
+ *   NBB_MAP_MFMA   lambda only: digits per item as NBB_MAP_DIGITS, the
+ *                  per-level sum as an int8 matrix-core contraction (the
+ *                  matrix encoding of section 3.1 on gfx950 matrix cores;
+ *                  needs r*k <= 192 and n <= 2^28, else NBB_E_INVALID).
+ * Same arguments, results and errors as nbb_lambda / nbb_nu otherwise.
+ */
+#define NBB_MAP_LUT 0u
+#define NBB_MAP_DIGITS 1u
+#define NBB_MAP_MFMA 2u
+nbb_status nbb_lambda_method(const nbb_fractal *f, uint32_t method, const uint32_t *idx, uint64_t count,
+                             int32_t *x, int32_t *y, void *stream);
+nbb_status nbb_nu_method(const nbb_fractal *f, uint32_t method, const int32_t *x, const int32_t *y,
+                         uint64_t count, uint32_t *idx, void *stream);
+
+/*
  * Bernoulli(p) initial state.  Cell (x, y) of the fractal is alive iff the top
  * 24 bits of SplitMix64 output number key = y*n + x of the stream seeded with
  * `seed` (Steele, Lea & Flood 2014: mix(seed + (key+1)*0x9E3779B97F4A7C15))

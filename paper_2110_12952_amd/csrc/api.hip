@@ -41,10 +41,12 @@ struct nbb_fractal {
     MapTables maps;
     TilePlan tile;
     BoxTables box;
+    MfmaTables mfma;
     uint32_t strategy = NBB_STRATEGY_DIRECT;
     int device = 0;
     int cu_count = 256;
-    DevBlob dmap, dtile, dbox;
+    DevBlob dmap, dtile, dbox, dmfma;
+    MfmaLambda ml{};
     MapParams mp{};
     TileParams tp{};
     BoxParams bp{};
@@ -188,6 +190,18 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->halo_dst = static_cast<const uint32_t *>(dst[3]);
     T->nbr = static_cast<const uint32_t *>(dst[4]);
     std::memcpy(T->bid, p.bid, sizeof(T->bid));
+    return NBB_OK;
+}
+
+nbb_status upload_mfma(nbb_fractal *F) {
+    if (!F->mfma.ktiles) return NBB_OK;
+    const void *src[1] = {F->mfma.A.data()};
+    size_t bytes[1] = {F->mfma.A.size()};
+    void *dst[1];
+    nbb_status s = upload(&F->dmfma, src, bytes, 1, dst);
+    if (s != NBB_OK) return s;
+    F->ml.ktiles = F->mfma.ktiles;
+    F->ml.A = static_cast<const int8_t *>(dst[0]);
     return NBB_OK;
 }
 
@@ -335,8 +349,10 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
         F->cu_count = cus;
     build_map_tables(F->f, &F->maps);
     build_box_tables(F->f, &F->box);
+    build_mfma_tables(F->f, &F->mfma);
     nbb_status st = upload_maps(F);
     if (st == NBB_OK) st = upload_box(F);
+    if (st == NBB_OK) st = upload_mfma(F);
     if (st == NBB_OK) {
         if (tiled_supported(F->f)) {
             if (build_tile_plan(F->f, auto_tile_level(F->f), &F->tile, &msg)) {
@@ -349,6 +365,7 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
         blob_free(&F->dmap);
         blob_free(&F->dbox);
         blob_free(&F->dtile);
+        blob_free(&F->dmfma);
         delete F;
         return st;
     }
@@ -361,6 +378,7 @@ void nbb_destroy(nbb_fractal *F) {
     blob_free(&F->dmap);
     blob_free(&F->dbox);
     blob_free(&F->dtile);
+    blob_free(&F->dmfma);
     delete F;
 }
 
@@ -385,7 +403,7 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
         info->tile_side = 1;
     }
     info->bbox_pitch = box_pitch(F->f);
-    info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes;
+    info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes + F->dmfma.bytes;
     return NBB_OK;
 }
 
@@ -419,28 +437,54 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
 
 uint64_t nbb_bbox_pitch(const nbb_fractal *F) { return F ? box_pitch(F->f) : 0; }
 
-nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count, int32_t *x, int32_t *y,
-                      void *stream) {
+nbb_status nbb_lambda_method(const nbb_fractal *F, uint32_t method, const uint32_t *idx, uint64_t count,
+                             int32_t *x, int32_t *y, void *stream) {
     if (!F) return fail(NBB_E_INVALID, "null descriptor");
+    if (method > NBB_MAP_MFMA) return fail(NBB_E_INVALID, "unknown map method");
+    if (method == NBB_MAP_MFMA && !F->ml.ktiles)
+        return fail(NBB_E_INVALID, "the matrix-core lambda needs r*k <= 192 and n <= 2^28");
     if (count == 0) return NBB_OK;
     if (!x || !y) return fail(NBB_E_INVALID, "null argument");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
-    return launched(launch_lambda(F->mp, F->lam_words, idx, count, x, y, map_grid(F, count),
-                                  static_cast<hipStream_t>(stream)),
-                    "lambda launch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (method) {
+        case NBB_MAP_LUT:
+            return launched(launch_lambda(F->mp, F->lam_words, idx, count, x, y, map_grid(F, count), s),
+                            "lambda launch");
+        case NBB_MAP_DIGITS:
+            return launched(launch_lambda_digits(F->mp, idx, count, x, y, map_grid(F, count), s), "lambda launch");
+        default: {
+            const uint64_t groups = (count + 255) / 256;
+            const int grid = int(std::max<uint64_t>(1, std::min<uint64_t>(groups, uint64_t(F->cu_count) * 8)));
+            return launched(launch_lambda_mfma(F->mp, F->ml, idx, count, x, y, grid, s), "lambda launch");
+        }
+    }
 }
 
-nbb_status nbb_nu(const nbb_fractal *F, const int32_t *x, const int32_t *y, uint64_t count, uint32_t *idx,
-                  void *stream) {
+nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count, int32_t *x, int32_t *y,
+                      void *stream) {
+    return nbb_lambda_method(F, NBB_MAP_LUT, idx, count, x, y, stream);
+}
+
+nbb_status nbb_nu_method(const nbb_fractal *F, uint32_t method, const int32_t *x, const int32_t *y, uint64_t count,
+                         uint32_t *idx, void *stream) {
     if (!F) return fail(NBB_E_INVALID, "null descriptor");
+    if (method != NBB_MAP_LUT && method != NBB_MAP_DIGITS)
+        return fail(NBB_E_INVALID, "nu supports the look-up-table and digit methods");
     if (count == 0) return NBB_OK;
     if (!x || !y || !idx) return fail(NBB_E_INVALID, "null argument");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
-    return launched(launch_nu(F->mp, F->nu_halves, x, y, count, idx, map_grid(F, count),
-                              static_cast<hipStream_t>(stream)),
-                    "nu launch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (method == NBB_MAP_DIGITS)
+        return launched(launch_nu_digits(F->mp, x, y, count, idx, map_grid(F, count), s), "nu launch");
+    return launched(launch_nu(F->mp, F->nu_halves, x, y, count, idx, map_grid(F, count), s), "nu launch");
+}
+
+nbb_status nbb_nu(const nbb_fractal *F, const int32_t *x, const int32_t *y, uint64_t count, uint32_t *idx,
+                  void *stream) {
+    return nbb_nu_method(F, NBB_MAP_LUT, x, y, count, idx, stream);
 }
 
 static uint32_t threshold24(double p) {

@@ -142,6 +142,141 @@ __global__ __launch_bounds__(512) void k_nu(MapParams P, uint32_t nu_halves,
         idx[t] = nu_lut(P, smem_n, x[t], y[t]);
 }
 
+// lambda with one digit per step, the paper's per-thread map (section 3.1,
+// evaluated level by level): d_mu = i mod k, i /= k, x += o_{d_mu}.x s^mu.
+__device__ __forceinline__ void lam_digits(const MapParams &P, const uint8_t *sox, const uint8_t *soy,
+                                           uint32_t i, uint32_t &x, uint32_t &y) {
+    uint32_t px = 0, py = 0, scale = 1;
+    for (uint32_t mu = 0; mu < P.r; ++mu) {
+        const uint32_t q = udiv(P.divk, i);
+        const uint32_t d = i - q * P.k;
+        px += sox[d] * scale;
+        py += soy[d] * scale;
+        scale *= P.s;
+        i = q;
+    }
+    x = px;
+    y = py;
+}
+// nu one level per step (eqs. 6-8 in compact-index form): the level-mu digit
+// pair gives H_mu, idx += H_mu k^mu; any pair outside the offsets -> outside.
+__device__ __forceinline__ uint32_t nu_digits(const MapParams &P, const uint8_t *shl, int32_t X, int32_t Y) {
+    if (uint32_t(X) >= P.n || uint32_t(Y) >= P.n) return kOutside;
+    uint32_t x = uint32_t(X), y = uint32_t(Y), idx = 0, w = 1, bad = 0;
+    for (uint32_t mu = 0; mu < P.r; ++mu) {
+        const uint32_t qx = udiv(P.divs, x), qy = udiv(P.divs, y);
+        const uint32_t h = shl[(x - qx * P.s) + P.s * (y - qy * P.s)];
+        bad |= (h == 0xFFu);
+        idx += h * w;
+        w *= P.k;
+        x = qx;
+        y = qy;
+    }
+    return bad ? kOutside : idx;
+}
+
+__device__ __forceinline__ void load_small_tables(const MapParams &P, uint8_t *sox, uint8_t *soy, uint8_t *shl) {
+    for (uint32_t t = threadIdx.x; t < 256; t += blockDim.x) {
+        sox[t] = t < P.k ? P.ox[t] : 0;
+        soy[t] = t < P.k ? P.oy[t] : 0;
+        shl[t] = P.hl[t];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_lambda_digits(MapParams P, const uint32_t *__restrict__ idx,
+                                                       uint64_t count, int32_t *__restrict__ x,
+                                                       int32_t *__restrict__ y) {
+    __shared__ uint8_t sox[256], soy[256], shl[256];
+    load_small_tables(P, sox, soy, shl);
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride) {
+        const uint64_t i = idx ? uint64_t(idx[t]) : t;
+        int32_t ox = -1, oy = -1;
+        if (i <= P.cells_m1) {
+            uint32_t ux, uy;
+            lam_digits(P, sox, soy, uint32_t(i), ux, uy);
+            ox = int32_t(ux);
+            oy = int32_t(uy);
+        }
+        x[t] = ox;
+        y[t] = oy;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_nu_digits(MapParams P, const int32_t *__restrict__ x,
+                                                   const int32_t *__restrict__ y, uint64_t count,
+                                                   uint32_t *__restrict__ idx) {
+    __shared__ uint8_t sox[256], soy[256], shl[256];
+    load_small_tables(P, sox, soy, shl);
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride)
+        idx[t] = nu_digits(P, shl, x[t], y[t]);
+}
+
+// lambda with the per-level sum on the matrix cores (v_mfma_i32_16x16x32_i8).
+// Each lane takes one item, extracts its r digits (as k_lambda_digits) and
+// writes their one-hot bytes, item-major, to LDS; each 16-item group is then
+// one B operand (lane j + 16 q holds item j's K bytes 8q..8q+7 of a K tile),
+// multiplied by the constant A.  In D, lanes 0-15 hold the x planes (rows
+// 0-3) and lanes 16-31 the y planes (rows 4-7) of items 0-15.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_lambda_mfma(MapParams P, MfmaLambda M, const uint32_t *__restrict__ idx,
+                                                     uint64_t count, int32_t *__restrict__ x,
+                                                     int32_t *__restrict__ y) {
+    __shared__ uint8_t sox[256], soy[256], shl[256];
+    extern __shared__ __align__(16) uint8_t onehot[];  // 256 items x 32 * ktiles bytes
+    load_small_tables(P, sox, soy, shl);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t KB = 32 * M.ktiles;
+    // A fragments for every K tile: lane holds A[lane % 16][8 (lane / 16) + 32 kt ..+8]
+    long afrag[8];
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt)
+        afrag[kt] = kt < int(M.ktiles)
+                        ? *reinterpret_cast<const long *>(M.A + (lane % 16) * KB + 8 * (lane / 16) + 32 * kt)
+                        : 0;
+    uint8_t *row = onehot + tid * KB;
+    const uint64_t ngroups = (count + 255) / 256;
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const uint64_t t = g * 256 + tid;
+        const bool valid = t < count;
+        const uint64_t i = valid ? (idx ? uint64_t(idx[t]) : t) : 0;
+        const bool inr = valid && i <= P.cells_m1;
+        // one-hot digits: byte mu * k + d_mu = 1
+        for (uint32_t o = 0; o < KB; o += 16) *reinterpret_cast<uint4 *>(row + o) = make_uint4(0, 0, 0, 0);
+        uint32_t ii = inr ? uint32_t(i) : 0;
+        for (uint32_t mu = 0; mu < P.r; ++mu) {
+            const uint32_t q = udiv(P.divk, ii);
+            row[mu * P.k + (ii - q * P.k)] = 1;
+            ii = q;
+        }
+        __syncthreads();
+        // the wave's 64 items = 4 groups of 16
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            v4i32 acc = {0, 0, 0, 0};
+            const uint8_t *col = onehot + (wave * 64 + grp * 16 + lane % 16) * KB + 8 * (lane / 16);
+#pragma unroll
+            for (int kt = 0; kt < 8; ++kt)
+                if (kt < int(M.ktiles))
+                    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(afrag[kt], *reinterpret_cast<const long *>(col + 32 * kt),
+                                                               acc, 0, 0, 0);
+            // rows 4 q + r of item lane % 16 in lane (lane % 16) + 16 q
+            const uint32_t v = uint32_t(acc[0]) + (uint32_t(acc[1]) << 7) + (uint32_t(acc[2]) << 14) +
+                               (uint32_t(acc[3]) << 21);
+            const uint64_t item = g * 256 + wave * 64 + grp * 16 + lane % 16;
+            if (lane < 32 && item < count) {
+                const uint64_t ir = idx ? uint64_t(idx[item]) : item;
+                const int32_t out = ir <= P.cells_m1 ? int32_t(v) : -1;
+                if (lane < 16) x[item] = out;
+                else y[item] = out;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Initial state: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) output number
 // key = y*n + x of the stream seeded with `seed`; alive iff its top 24 bits
@@ -617,6 +752,21 @@ __global__ __launch_bounds__(256) void k_step_box(BoxParams B, uint32_t gx,
 hipError_t launch_lambda(const MapParams &P, uint32_t lam_words, const uint32_t *idx, uint64_t count,
                          int32_t *x, int32_t *y, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_lambda, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, idx, count, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_lambda_digits(const MapParams &P, const uint32_t *idx, uint64_t count, int32_t *x, int32_t *y,
+                                int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_lambda_digits, dim3(grid), dim3(512), 0, st, P, idx, count, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_nu_digits(const MapParams &P, const int32_t *x, const int32_t *y, uint64_t count, uint32_t *idx,
+                            int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_nu_digits, dim3(grid), dim3(512), 0, st, P, x, y, count, idx);
+    return hipGetLastError();
+}
+hipError_t launch_lambda_mfma(const MapParams &P, const MfmaLambda &M, const uint32_t *idx, uint64_t count,
+                              int32_t *x, int32_t *y, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_lambda_mfma, dim3(grid), dim3(256), size_t(256) * 32 * M.ktiles, st, P, M, idx, count, x, y);
     return hipGetLastError();
 }
 hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, const int32_t *y,

@@ -43,6 +43,16 @@ struct MapParams {
     const uint8_t *hl;   // digit pair a + s*b -> replica id, 0xFF if none
 };
 
+// lambda as in the paper's per-thread map (section 3.1: one term per level)
+// and its matrix-core form: the per-level sum sum_mu o_{d_mu} s^mu as an int8
+// contraction D = A B with B[(mu, j)][item] = [d_mu(item) == j] (one-hot
+// digits) and A[row][(mu, j)] = 7-bit plane p of o_j.c * s^mu; rows 0-3 hold
+// the four x planes, rows 4-7 the four y planes (coordinates < 2^28).
+struct MfmaLambda {
+    uint32_t ktiles;        // K = 32 * ktiles >= r * k
+    const int8_t *A;        // 16 x (32 * ktiles), row-major
+};
+
 // The tiled compact step: a tile is an aligned run of K = k^m compact cells,
 // i.e. one level-m copy of the fractal occupying an S x S block (S = s^m) of
 // the box.  A work-group stages the tile and the neighbour cells that touch

@@ -367,6 +367,22 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     return true;
 }
 
+void build_mfma_tables(const Fractal &f, MfmaTables *t) {
+    *t = MfmaTables();
+    const uint64_t K = uint64_t(f.r) * f.k;
+    if (f.r == 0 || K > 192 || f.n > (uint64_t(1) << 28)) return;
+    t->ktiles = uint32_t((K + 31) / 32);
+    const uint32_t KB = 32 * t->ktiles;
+    t->A.assign(size_t(16) * KB, 0);
+    int64_t scale = 1;
+    for (uint32_t mu = 0; mu < f.r; ++mu, scale *= f.s)
+        for (uint32_t j = 0; j < f.k; ++j)
+            for (uint32_t p = 0; p < 4; ++p) {
+                t->A[p * KB + mu * f.k + j] = int8_t(((f.ox[j] * scale) >> (7 * p)) & 127);
+                t->A[(4 + p) * KB + mu * f.k + j] = int8_t(((f.oy[j] * scale) >> (7 * p)) & 127);
+            }
+}
+
 uint64_t box_pitch(const Fractal &f) { return std::max<uint64_t>(16, (f.n + 15) & ~uint64_t(15)); }
 
 void build_box_tables(const Fractal &f, BoxTables *b) {

@@ -58,6 +58,14 @@ uint32_t auto_tile_level(const Fractal &f);
 // Builds the plan at tile level m (1 <= m <= r); false if it does not fit.
 bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg);
 
+// Matrix-core lambda: A (16 x 32*ktiles int8), see MfmaLambda in params.hpp.
+// ktiles == 0 when unsupported (r*k > 192 or n > 2^28).
+struct MfmaTables {
+    uint32_t ktiles = 0;
+    std::vector<int8_t> A;
+};
+void build_mfma_tables(const Fractal &f, MfmaTables *t);
+
 struct BoxTables {
     uint32_t L = 0, SL = 0, LW = 0, NH = 0;
     std::vector<uint32_t> low;

@@ -24,6 +24,7 @@ NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
 NBB_OUTSIDE = 0xFFFFFFFF
 NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
 STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT = 0, 1, 2
+MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 
 
 class NbbError(RuntimeError):
@@ -82,6 +83,10 @@ def lib() -> ctypes.CDLL:
     L.nbb_lambda.restype = st
     L.nbb_nu.argtypes = [vp, vp, vp, u64, vp, vp]
     L.nbb_nu.restype = st
+    L.nbb_lambda_method.argtypes = [vp, u32, vp, u64, vp, vp, vp]
+    L.nbb_lambda_method.restype = st
+    L.nbb_nu_method.argtypes = [vp, u32, vp, vp, u64, vp, vp]
+    L.nbb_nu_method.restype = st
     L.nbb_init_compact.argtypes = [vp, vp, u64, u64, ctypes.c_double, vp]
     L.nbb_init_compact.restype = st
     L.nbb_init_bbox.argtypes = [vp, vp, u64, u64, u64, ctypes.c_double, vp]
@@ -198,7 +203,7 @@ class Fractal:
         _check(lib().nbb_configure(self._h, strategy, tile_level))
 
     # ---- maps ------------------------------------------------------------
-    def lam(self, idx=None, count: Optional[int] = None, out=None, stream=None):
+    def lam(self, idx=None, count: Optional[int] = None, out=None, stream=None, method: int = MAP_LUT):
         import torch
         if idx is not None:
             count = idx.numel()
@@ -209,16 +214,16 @@ class Fractal:
         dev = torch.device("cuda", torch.cuda.current_device())
         x, y = out if out is not None else (torch.empty(count, dtype=torch.int32, device=dev),
                                              torch.empty(count, dtype=torch.int32, device=dev))
-        _check(lib().nbb_lambda(self._h, ip, count, _dev_ptr(x, "int32", count), _dev_ptr(y, "int32", count),
-                                _stream(stream)))
+        _check(lib().nbb_lambda_method(self._h, method, ip, count, _dev_ptr(x, "int32", count),
+                                       _dev_ptr(y, "int32", count), _stream(stream)))
         return x, y
 
-    def nu(self, x, y, out=None, stream=None):
+    def nu(self, x, y, out=None, stream=None, method: int = MAP_LUT):
         import torch
         count = x.numel()
         idx = out if out is not None else torch.empty(count, dtype=torch.int32, device=x.device)
-        _check(lib().nbb_nu(self._h, _dev_ptr(x, "int32", count), _dev_ptr(y, "int32", count), count,
-                            _dev_ptr(idx, "int32", count), _stream(stream)))
+        _check(lib().nbb_nu_method(self._h, method, _dev_ptr(x, "int32", count), _dev_ptr(y, "int32", count),
+                                   count, _dev_ptr(idx, "int32", count), _stream(stream)))
         return idx  # int32 view of the uint32 result: NBB_OUTSIDE reads as -1
 
     # ---- states ----------------------------------------------------------

@@ -88,6 +88,42 @@ def test_nu_whole_box_and_ring(N, name, r):
     assert (host(g.nu(dev(gx), dev(gy))) == -1).all()
 
 
+@pytest.mark.parametrize("name,r", SMALL)
+def test_map_methods_agree(N, name, r):
+    # the per-level digit maps and the matrix-core lambda against the oracle
+    fd, o, g = pair(name, r, N)
+    ox, oy = o.lam_many(np.arange(o.cells))
+    methods = [N.MAP_DIGITS] + ([N.MAP_MFMA] if r >= 1 and r * fd.k <= 192 else [])
+    for m in methods:
+        x, y = g.lam(method=m)
+        np.testing.assert_array_equal(host(x), ox, err_msg=f"lambda method {m}")
+        np.testing.assert_array_equal(host(y), oy, err_msg=f"lambda method {m}")
+        idx = np.concatenate([W.random_indices(r + 5, 777, o.cells), [o.cells, 2**32 - 1]]).astype(np.uint32)
+        x, y = g.lam(dev(idx.view(np.int32)), method=m)
+        ok = idx < o.cells
+        lx, ly = o.lam_many(idx[ok].astype(np.int64))
+        np.testing.assert_array_equal(host(x)[ok], lx)
+        assert (host(x)[~ok] == -1).all() and (host(y)[~ok] == -1).all()
+    yy, xx = np.mgrid[-1:o.n + 1, -1:o.n + 1]
+    xs, ys = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
+    np.testing.assert_array_equal(host(g.nu(dev(xs), dev(ys), method=N.MAP_DIGITS)).astype(np.int64),
+                                  o.nu_many(xs, ys))
+    if r == 0 or r * fd.k > 192:
+        with pytest.raises(N.NbbError):
+            g.lam(method=N.MAP_MFMA)
+    with pytest.raises(N.NbbError):
+        g.nu(dev(xs), dev(ys), method=N.MAP_MFMA)
+
+
+def test_map_methods_full_size(N):
+    fd, o, g = pair("triangle", 16, N)
+    x0, y0 = g.lam()
+    for m in (N.MAP_DIGITS, N.MAP_MFMA):
+        x, y = g.lam(method=m)
+        assert torch.equal(x, x0) and torch.equal(y, y0)
+    assert torch.equal(g.nu(x0, y0, method=N.MAP_DIGITS), g.nu(x0, y0))
+
+
 def test_maps_empty_count(N):
     g = N.Fractal(2, W.TRIANGLE.offsets, 4)
     e = torch.empty(0, dtype=torch.int32, device="cuda")
