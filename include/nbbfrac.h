@@ -192,6 +192,67 @@ nbb_status nbb_expand(const nbb_fractal *f, const uint8_t *compact, uint8_t *bbo
 nbb_status nbb_gather(const nbb_fractal *f, const uint8_t *bbox, uint64_t pitch, uint8_t *compact,
                       uint64_t len, void *stream);
 
+/*
+ * Autotuner.  The paper picks its block size per method by measurement
+ * (section 4: the best rho differs between methods); this does the same for
+ * the compact step.  Times `steps` generations (after one untimed one) of
+ * each candidate -- TILED at every tile level m whose tile holds at least 128
+ * cells, plus the largest level that fits, and DIRECT -- on the caller's
+ * buffers a and b (their contents are overwritten: pass a copy of a
+ * representative state), then configures the fastest, as nbb_configure would.
+ * Waits for `stream`.  Arguments as nbb_step_compact; steps >= 1.  If info is
+ * not NULL it receives nbb_query's result for the chosen plan.  Must not
+ * overlap other calls on the same descriptor.
+ */
+nbb_status nbb_autotune(nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                        uint32_t rule, void *stream, nbb_info *info);
+
+/*
+ * Batches: many independent automata, each on a fractal of its own (own k, s,
+ * offsets and r), stepped together.  All states live in one device arena per
+ * buffer: instance i occupies bytes [offsets[i], offsets[i] + k_i^r_i) of
+ * both arenas passed to nbb_batch_step.  Instances whose descriptors use the
+ * TILED strategy at the same tile level for the same (k, s, offsets) form one
+ * group and are stepped by one launch per generation over all their tiles
+ * (configure a common tile level with nbb_configure to group instances of
+ * different r); instances with the DIRECT strategy are stepped one launch
+ * each.
+ *
+ * nbb_batch_create: fractals[i] (may repeat) must outlive the batch and keep
+ * their configuration while it exists; offsets[i] must be multiples of 16,
+ * the ranges must not overlap, and every offset must be below 2^36.  Builds
+ * the batch's tile tables on the current device (the descriptors' device)
+ * with work enqueued on `stream`.  count == 0 gives an empty batch.
+ * NBB_E_INVALID for NULL pointers, a descriptor of another device, misaligned
+ * or overlapping ranges; NBB_E_RANGE beyond the limits above or 2^28 tiles in
+ * one group.  Free with nbb_batch_destroy (no enqueued work may still use it).
+ */
+typedef struct nbb_batch nbb_batch;
+typedef struct {
+    uint32_t instances;
+    uint32_t groups;          /* one launch per generation each */
+    uint32_t direct;          /* instances stepped by their own launch */
+    uint32_t reserved;
+    uint64_t cells;           /* sum of k_i^r_i */
+    uint64_t tiles;           /* tiles over all groups */
+    uint64_t arena_bytes;     /* smallest arena: max(offset + cells) rounded up to 16 */
+    uint64_t device_table_bytes;
+} nbb_batch_info;
+nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                            void *stream, nbb_batch **out);
+void nbb_batch_destroy(nbb_batch *batch);
+nbb_status nbb_batch_query(const nbb_batch *batch, nbb_batch_info *info);
+
+/*
+ * `steps` generations of `rule` for every instance of the batch, states
+ * starting in arena a, alternating with arena b as nbb_step_compact does
+ * (*result_in_b = steps & 1).  Both arenas must be 16-byte aligned, at least
+ * arena_bytes long (arena_len), and must not overlap; bytes outside the
+ * instances' ranges are neither read nor written.
+ */
+nbb_status nbb_batch_step(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
+                          uint32_t rule, int *result_in_b, void *stream);
+
 /* Smallest box pitch for this descriptor: n rounded up to a multiple of 16. */
 uint64_t nbb_bbox_pitch(const nbb_fractal *f);
 

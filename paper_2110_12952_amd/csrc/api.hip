@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
+#include <vector>
 
 #include "../../include/nbbfrac.h"
 #include "kernels.hpp"
@@ -56,6 +58,26 @@ struct nbb_fractal {
 struct nbb_plan {
     Fractal f;
     TilePlan tile;
+};
+
+// A batch: groups of instances that share a tile plan, each stepped by one
+// launch over the group's tiles, and instances stepped one by one.
+struct BatchGroup {
+    TileParams tp;           // the plan of the group's first descriptor; nbr / ntiles are the batch's
+    const uint32_t *rec = nullptr;
+};
+struct BatchDirect {
+    const nbb_fractal *f;
+    uint64_t offset;
+};
+struct nbb_batch {
+    int device = 0;
+    int cu_count = 256;
+    uint32_t count = 0;
+    uint64_t cells = 0, tiles = 0, arena_bytes = 0;
+    std::vector<BatchGroup> groups;
+    std::vector<BatchDirect> direct;
+    DevBlob dtab;
 };
 
 namespace {
@@ -432,6 +454,251 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     F->tile = std::move(plan);
     F->tp = T;
     F->strategy = NBB_STRATEGY_TILED;
+    return NBB_OK;
+}
+
+nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps, uint32_t rule,
+                        void *stream, nbb_info *info) {
+    if (!F || !a || !b) return fail(NBB_E_INVALID, "null argument");
+    if (steps == 0) return fail(NBB_E_INVALID, "steps must be >= 1");
+    if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "state buffers must be 16-byte aligned");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    // Candidates: (strategy, level).  Tile levels whose plan fits a
+    // work-group, keeping those with >= 128 cells per tile and the largest.
+    std::vector<std::pair<uint32_t, uint32_t>> cand;
+    if (tiled_supported(F->f)) {
+        std::vector<uint32_t> fit;
+        for (uint32_t m = 1; m <= F->f.r; ++m) {
+            uint64_t K = 1, S = 1;
+            for (uint32_t i = 0; i < m; ++i) {
+                K *= F->f.k;
+                S *= F->f.s;
+            }
+            if (K + 30 > 2 * 16 * 256 || S > 250) break;
+            fit.push_back(m);
+        }
+        for (size_t i = 0; i < fit.size(); ++i) {
+            uint64_t K = 1;
+            for (uint32_t j = 0; j < fit[i]; ++j) K *= F->f.k;
+            if (K >= 128 || i + 1 == fit.size()) cand.push_back({NBB_STRATEGY_TILED, fit[i]});
+        }
+    }
+    cand.push_back({NBB_STRATEGY_DIRECT, 0});
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    float best_ms = -1.0f;
+    std::pair<uint32_t, uint32_t> best{0, 0};
+    for (const auto &c : cand) {
+        if (nbb_configure(F, c.first, c.second) != NBB_OK) continue;  // plan does not fit: skip it
+        st = nbb_step_compact(F, a, b, len, 1, rule, nullptr, stream);
+        if (st == NBB_OK && (e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+        if (st == NBB_OK) st = nbb_step_compact(F, b, a, len, steps, rule, nullptr, stream);
+        if (st == NBB_OK && (e = hipEventRecord(e1, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+        if (st == NBB_OK && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+        float ms = 0.0f;
+        if (st == NBB_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+        if (st != NBB_OK) break;
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != NBB_OK) return st;
+    if (best_ms < 0.0f) return fail(NBB_E_INVALID, "no strategy could be configured");
+    st = nbb_configure(F, best.first, best.second);
+    if (st == NBB_OK && info) st = nbb_query(F, info);
+    return st;
+}
+
+nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                            void *stream, nbb_batch **out) {
+    if (!out) return fail(NBB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count && (!fractals || !offsets)) return fail(NBB_E_INVALID, "null argument");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const uint64_t kArenaLimit = uint64_t(1) << 36;
+    for (uint32_t i = 0; i < count; ++i) {
+        const nbb_fractal *F = fractals[i];
+        if (!F) return fail(NBB_E_INVALID, "null descriptor in the batch");
+        if (F->device != dev) return fail(NBB_E_INVALID, "descriptor belongs to another device");
+        if (offsets[i] % 16) return fail(NBB_E_INVALID, "instance offsets must be multiples of 16");
+        if (offsets[i] >= kArenaLimit || F->f.cells > kArenaLimit)
+            return fail(NBB_E_RANGE, "instance offset beyond 2^36");
+    }
+    // Ranges must not overlap: check them in offset order, which is also the
+    // order the instances take in each group (tiles of neighbouring states
+    // then sit next to each other in a launch).
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return offsets[x] < offsets[y]; });
+    nbb_batch *B = new (std::nothrow) nbb_batch;
+    if (!B) return fail(NBB_E_NOMEM, "host allocation failed");
+    B->device = dev;
+    B->count = count;
+    for (uint32_t j = 0; j < count; ++j) {
+        const uint32_t i = order[j];
+        const uint64_t end = offsets[i] + fractals[i]->f.cells;
+        if (j + 1 < count && end > offsets[order[j + 1]]) {
+            delete B;
+            return fail(NBB_E_INVALID, "instance ranges overlap");
+        }
+        B->cells += fractals[i]->f.cells;
+        B->arena_bytes = std::max(B->arena_bytes, (end + 15) & ~uint64_t(15));
+    }
+    // Group the tiled instances by (k, s, offsets, tile plan).
+    auto same_plan = [](const nbb_fractal *x, const nbb_fractal *y) {
+        if (x->f.k != y->f.k || x->f.s != y->f.s) return false;
+        for (uint32_t j = 0; j < x->f.k; ++j)
+            if (x->f.ox[j] != y->f.ox[j] || x->f.oy[j] != y->f.oy[j]) return false;
+        const TileParams &a = x->tp, &b = y->tp;
+        return a.m == b.m && a.W == b.W && a.lds_total == b.lds_total && a.halo_count == b.halo_count;
+    };
+    std::vector<const nbb_fractal *> reps;
+    std::vector<std::vector<BatchInstance>> members;
+    for (uint32_t j = 0; j < count; ++j) {
+        const uint32_t i = order[j];
+        const nbb_fractal *F = fractals[i];
+        if (F->strategy != NBB_STRATEGY_TILED) {
+            B->direct.push_back({F, offsets[i]});
+            continue;
+        }
+        size_t g = 0;
+        while (g < reps.size() && !same_plan(reps[g], F)) ++g;
+        if (g == reps.size()) {
+            reps.push_back(F);
+            members.emplace_back();
+        }
+        BatchInstance I{};
+        I.nbr = F->tp.nbr;
+        I.base16 = uint32_t(offsets[i] >> 4);
+        I.ntiles = F->tp.ntiles;
+        I.tail_partial = (F->f.cells & 15) ? 1u : 0u;
+        members[g].push_back(I);
+    }
+    // One device allocation: per group the instance table, the records
+    // (2 words per tile) and the neighbour table (8 words per tile).
+    std::vector<size_t> off_inst(reps.size()), off_rec(reps.size()), off_nbr(reps.size()), ntiles(reps.size());
+    size_t total = 0;
+    for (size_t g = 0; g < reps.size(); ++g) {
+        uint64_t t = 0;
+        for (BatchInstance &I : members[g]) {
+            I.tile0 = uint32_t(t);
+            t += I.ntiles;
+        }
+        if (t * 8 > (uint64_t(1) << 31)) {
+            delete B;
+            return fail(NBB_E_RANGE, "too many tiles in one group of the batch");
+        }
+        ntiles[g] = t;
+        B->tiles += t;
+        off_inst[g] = total;
+        total += align256(members[g].size() * sizeof(BatchInstance));
+        off_rec[g] = total;
+        total += align256(std::max<size_t>(t * 8, 1));
+        off_nbr[g] = total;
+        total += align256(std::max<size_t>(t * 32, 1));
+    }
+    if (total) {
+        e = hipMalloc(&B->dtab.ptr, total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete B;
+            return e == hipErrorOutOfMemory ? fail(NBB_E_NOMEM, "batch table allocation failed")
+                                            : hip_fail(e, "hipMalloc");
+        }
+        B->dtab.bytes = total;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(B->dtab.ptr);
+    for (size_t g = 0; g < reps.size(); ++g) {
+        auto *inst = reinterpret_cast<BatchInstance *>(base + off_inst[g]);
+        auto *rec = reinterpret_cast<uint32_t *>(base + off_rec[g]);
+        auto *nbr = reinterpret_cast<uint32_t *>(base + off_nbr[g]);
+        e = hipMemcpyAsync(inst, members[g].data(), members[g].size() * sizeof(BatchInstance),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table goes out of scope
+        if (e == hipSuccess)
+            e = launch_batch_tiles(inst, uint32_t(members[g].size()), uint32_t(ntiles[g]), rec, nbr, s);
+        if (e != hipSuccess) {
+            blob_free(&B->dtab);
+            delete B;
+            return hip_fail(e, "batch table build");
+        }
+        BatchGroup G;
+        G.tp = reps[g]->tp;
+        G.tp.nbr = nbr;
+        G.tp.ntiles = uint32_t(ntiles[g]);
+        G.tp.cells = 0;  // per instance, from the records
+        G.rec = rec;
+        B->groups.push_back(G);
+        B->cu_count = reps[g]->cu_count;
+    }
+    for (const BatchDirect &d : B->direct) B->cu_count = d.f->cu_count;
+    *out = B;
+    return NBB_OK;
+}
+
+void nbb_batch_destroy(nbb_batch *B) {
+    if (!B) return;
+    blob_free(&B->dtab);
+    delete B;
+}
+
+nbb_status nbb_batch_query(const nbb_batch *B, nbb_batch_info *info) {
+    if (!B || !info) return fail(NBB_E_INVALID, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->instances = B->count;
+    info->groups = uint32_t(B->groups.size());
+    info->direct = uint32_t(B->direct.size());
+    info->cells = B->cells;
+    info->tiles = B->tiles;
+    info->arena_bytes = B->arena_bytes;
+    info->device_table_bytes = B->dtab.bytes;
+    return NBB_OK;
+}
+
+nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
+                          uint32_t rule, int *result_in_b, void *stream) {
+    if (!B) return fail(NBB_E_INVALID, "null batch");
+    if (B->count && (!a || !b)) return fail(NBB_E_INVALID, "null arena");
+    if (arena_len < B->arena_bytes) return fail(NBB_E_INVALID, "arena shorter than the batch needs");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
+    if (B->count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != B->device) return fail(NBB_E_INVALID, "batch belongs to another device");
+    if (result_in_b) *result_in_b = int(steps & 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *in = a, *out = b;
+    for (uint32_t i = 0; i < steps; ++i) {
+        for (const BatchGroup &G : B->groups) {
+            e = launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, s);
+            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+        }
+        for (const BatchDirect &d : B->direct) {
+            const nbb_fractal *F = d.f;
+            e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + d.offset, out + d.offset, rule,
+                                   map_grid(F, F->f.cells), s);
+            if (e != hipSuccess) return hip_fail(e, "batch direct step launch");
+        }
+        std::swap(in, out);
+    }
     return NBB_OK;
 }
 

@@ -430,21 +430,8 @@ __global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_w
 }
 
 // ---------------------------------------------------------------------------
-// Compact step, tiled (section 3, blocked approach, applied to compact
-// storage).  Tile t = compact cells [t K, (t+1) K), K = k^m: one level-m copy
-// of the fractal, covering the S x S block (S = s^m) of the box whose corner
-// is S * lambda_{r-m}(t).  Since every tile is the same copy of F_m, the
-// position of local cell i inside its block (lut0) and the list of neighbour
-// cells that touch the block (halo) are the same for every tile; only the
-// eight neighbour tiles differ, found with nu_{r-m} of the neighbouring
-// coarse coordinates.  A work-group:
-//   1. scatters the tile's K bytes and its halo into an LDS box of
-//      (S+2) x W bytes (dead cells stay 0),
-//   2. evaluates the rule for each level-1 block (k cells inside an s x s
-//      square) from an (s+2) x (s+2) window, four columns per SWAR dword,
-//      writing results in compact order to an LDS staging row,
-//   3. stores the staging row to global memory with aligned 16-byte stores.
-// Work-groups are persistent and walk an XCD-contiguous range of tiles.
+// Compact step, tiled: the kernel and its helpers (the kernel's comment
+// describes the scheme).
 // ---------------------------------------------------------------------------
 // Registers holding the next tile's input while the current one computes.
 template <int CPT, int HPT>
@@ -454,19 +441,19 @@ struct TilePrefetch {
     uint32_t halo[HPT];
 };
 
+// Loads tile t (local index within the state array `in` of cells `cells`)
+// and its halo.  `tail`: the tile holds the last cell of an array whose
+// length is not a multiple of 16, so its last chunk may not be read whole.
 template <int CPT, int HPT>
 __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t *__restrict__ in,
-                                              uint32_t t, const uint32_t *nb, const uint32_t *hsrc,
-                                              TilePrefetch<CPT, HPT> &pf) {
+                                              uint32_t t, bool tail, uint32_t cells, const uint32_t *nb,
+                                              const uint32_t *hsrc, TilePrefetch<CPT, HPT> &pf) {
     const uint32_t tid = threadIdx.x;
     const uint32_t B = t * T.K;
     const uint32_t ph = B & 15;
     const uint32_t nchunks = (ph + T.K + 15) >> 4;
     const uint8_t *gin = in + (B & ~15u);  // uniform; chunk c at gin + 16 c
     const uint16_t *lut = T.lut0p + ph * T.lut0_stride;
-    // Only the tile holding the last cell of an array whose length is not a
-    // multiple of 16 has a chunk that may not be read whole.
-    const bool tail = (B + T.K == T.cells) && (T.cells & 15);
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const uint32_t c = tid + 256 * j;
@@ -475,7 +462,7 @@ __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t
                 pf.v[j] = *reinterpret_cast<const uint4 *>(gin + 16 * c);
             } else {
                 uint32_t v[4] = {0, 0, 0, 0};
-                const uint32_t nb_ = (T.cells & 15);
+                const uint32_t nb_ = cells & 15;
                 for (uint32_t b = 0; b < nb_; ++b) v[b >> 2] |= uint32_t(gin[16 * c + b]) << (8 * (b & 3));
                 pf.v[j] = make_uint4(v[0], v[1], v[2], v[3]);
             }
@@ -566,15 +553,29 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
 // software pipeline: the next tile's bytes and halo are loaded into registers
 // while the current tile computes, and the neighbour tiles are found two
 // tiles ahead by threads that are idle during the stores.
-template <int BS, int CPT, int HPT, int BPT>
+//
+// BATCH: the tiles of many independent fractals that share the tile plan
+// (same k, s, offsets and m, any r), each state at its own place in one
+// arena.  Batch tile g is local tile rec[2g+1] (bit 31: the tail flag of
+// tile_prefetch) of the state at byte 16 rec[2g] of the arena, and T.nbr
+// holds its eight neighbours as local tiles of the same state.  The record
+// travels through LDS with the neighbour tiles, two tiles ahead.
+template <int BS, int CPT, int HPT, int BPT, bool BATCH>
 __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
-    MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule) {
+    MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule,
+    const uint32_t *__restrict__ rec) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint8_t *box = lds;
-    __shared__ uint32_t nbr[2][8];
+    constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
+    constexpr uint32_t kLane0 = 256 - kLanes;
+    __shared__ uint32_t nbr[2][kLanes];
     const uint32_t tid = threadIdx.x;
     const uint32_t K = T.K;
     const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
+    // word l of the per-tile LDS entry of tile t
+    auto entry = [&](uint64_t t, uint32_t l) -> uint32_t {
+        return (!BATCH || l < 8) ? T.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
+    };
 
     for (uint32_t o = tid * 16; o < T.lds_total; o += 256 * 16)
         *reinterpret_cast<uint4 *>(lds + o) = make_uint4(0, 0, 0, 0);
@@ -586,29 +587,52 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         hsrc[j] = ok ? T.halo_src[h] : kOutside;
         hdst[j] = ok ? T.halo_dst[h] : T.dummy;
     }
-    // Block windows and bit offsets; threads past the last block repeat it and
-    // write their bits past the tile (never stored).
+    // Block window corners (the same for every tile).
     uint32_t blk[BPT];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
-    // Neighbour tiles go through LDS two tiles ahead: threads 248..255 load
-    // the eight entries of tile it+2 after the first barrier of tile it and
+    // Neighbour tiles go through LDS two tiles ahead: the last kLanes threads
+    // load the entries of tile it+2 after the first barrier of tile it and
     // publish them after its second barrier.
-    if (tid >= 248) {
-        if (R.first < R.end) nbr[0][tid - 248] = T.nbr[R.first * 8 + (tid - 248)];
-        if (R.first + R.step < R.end) nbr[1][tid - 248] = T.nbr[(R.first + R.step) * 8 + (tid - 248)];
+    if (tid >= kLane0) {
+        if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
+        if (R.first + R.step < R.end) nbr[1][tid - kLane0] = entry(R.first + R.step, tid - kLane0);
     }
     __syncthreads();
 
+    // Where tile t lives: its state array, local index and tail flag.
+    const uint8_t *src = in;
+    uint8_t *dst = out;
+    uint32_t local = 0, cells = T.cells;
+    bool tail = false;
+    auto locate = [&](uint64_t t, const uint32_t *e) {
+        if (BATCH) {
+            const uint64_t base = uint64_t(__builtin_amdgcn_readfirstlane(e[8])) << 4;
+            const uint32_t w = __builtin_amdgcn_readfirstlane(e[9]);
+            src = in + base;
+            dst = out + base;
+            local = w & 0x7FFFFFFFu;
+            tail = (w >> 31) != 0;
+            cells = (local + 1) * K;  // only read when tail is set: the tile is the last one
+        } else {
+            local = uint32_t(t);
+            tail = (local * K + K == T.cells) && (T.cells & 15);
+        }
+    };
+
     TilePrefetch<CPT, HPT> pf;
-    if (R.first < R.end) tile_prefetch<CPT, HPT>(T, in, uint32_t(R.first), nbr[0], hsrc, pf);
+    if (R.first < R.end) {
+        locate(R.first, nbr[0]);
+        tile_prefetch<CPT, HPT>(T, src, local, tail, cells, nbr[0], hsrc, pf);
+    }
 
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
     const uint32_t W4 = T.W >> 2;
     uint16_t *slots = reinterpret_cast<uint16_t *>(lds + T.slot_off);
     uint32_t it = 0;
     for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
-        const uint32_t B = uint32_t(t64) * K;  // first compact cell of the tile (< 2^32)
+        const uint32_t B = local * K;  // first cell of the tile in its state array (< 2^32)
+        uint8_t *gout = dst + (B & ~15u);
         const uint32_t ph = B & 15;
         const uint32_t nchunks = (ph + K + 15) >> 4;
         // 1. scatter the prefetched tile and halo into the box.  Offsets of
@@ -629,22 +653,25 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         __syncthreads();
 
         // 2. start loading the next tile
-        if (t64 + R.step < R.end)
-            tile_prefetch<CPT, HPT>(T, in, uint32_t(t64 + R.step), nbr[(it + 1) & 1], hsrc, pf);
+        if (t64 + R.step < R.end) {
+            const uint32_t *e = nbr[(it + 1) & 1];
+            locate(t64 + R.step, e);
+            tile_prefetch<CPT, HPT>(T, src, local, tail, cells, e, hsrc, pf);
+        }
         uint32_t nb2 = kOutside;
-        if (tid >= 248 && t64 + 2 * R.step < R.end) nb2 = T.nbr[(t64 + 2 * R.step) * 8 + (tid - 248)];
+        if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
 
         // 3. rule per block -> slot (the stores of the previous tile, the
         //    only readers, all finished before this tile's first barrier)
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
-            slots[tid + 256 * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
+            if (tid + 256 * j < T.nblk)  // waves with no block left skip the work
+                slots[tid + 256 * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
         __syncthreads();
 
         // 4. slots -> 16 next states per chunk -> bytes -> global; the two
         //    edge chunks are shared with the neighbouring tiles and written
         //    bytewise.  Byte t of chunk c holds local cell 16 c - ph + t.
-        uint8_t *gout = out + (B & ~15u);
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
             const uint32_t c = tid + 256 * j;
@@ -667,7 +694,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 }
             }
         }
-        if (tid >= 248) nbr[it & 1][tid - 248] = nb2;
+        if (tid >= kLane0) nbr[it & 1][tid - kLane0] = nb2;
     }
 }
 
@@ -809,49 +836,91 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
 }
 // Persistent launch: as many work-groups as can be resident at once (the
 // occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT, int BPT>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, int cu_count, hipStream_t st) {
+                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT, BPT>, 256,
-                                                                T.lds_total);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH>,
+                                                                256, T.lds_total);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, T.ntiles);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st, P, T,
-                       in, out, rule);
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st,
+                       P, T, in, out, rule, rec);
     return hipGetLastError();
 }
-template <int BS, int CPT, int HPT>
+template <int BS, int CPT, int HPT, bool BATCH>
 static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, int cu_count, hipStream_t st) {
+                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t bpt = (T.nblk + 255) / 256;
-    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1>(P, T, in, out, rule, cu_count, st);
-    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2>(P, T, in, out, rule, cu_count, st);
-    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4>(P, T, in, out, rule, cu_count, st);
+    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
-template <int BS>
+template <int BS, bool BATCH>
 static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, int cu_count, hipStream_t st) {
+                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t cpt = (T.K + 30 + 16 * 256 - 1) / (16 * 256);
     const uint32_t hpt = (T.halo_count + 255) / 256;
-    if (cpt <= 1 && hpt <= 1) return launch_tiled_b<BS, 1, 1>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 1 && hpt <= 2) return launch_tiled_b<BS, 1, 2>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 1 && hpt <= 4) return launch_tiled_b<BS, 1, 4>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 1) return launch_tiled_b<BS, 2, 1>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 2) return launch_tiled_b<BS, 2, 2>(P, T, in, out, rule, cu_count, st);
-    if (cpt <= 2 && hpt <= 4) return launch_tiled_b<BS, 2, 4>(P, T, in, out, rule, cu_count, st);
+#define NBB_TILED_CASE(C, H) \
+    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH>(P, T, in, out, rule, rec, cu_count, st)
+    NBB_TILED_CASE(1, 1);
+    NBB_TILED_CASE(1, 2);
+    NBB_TILED_CASE(1, 4);
+    NBB_TILED_CASE(2, 1);
+    NBB_TILED_CASE(2, 2);
+    NBB_TILED_CASE(2, 4);
+#undef NBB_TILED_CASE
     return hipErrorInvalidValue;
+}
+template <bool BATCH>
+static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                                   uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+    switch (T.BS) {
+        case 2: return launch_tiled_s<2, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+        case 3: return launch_tiled_s<3, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+        case 4: return launch_tiled_s<4, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                              uint32_t rule, int cu_count, hipStream_t st) {
-    switch (T.BS) {
-        case 2: return launch_tiled_s<2>(P, T, in, out, rule, cu_count, st);
-        case 3: return launch_tiled_s<3>(P, T, in, out, rule, cu_count, st);
-        case 4: return launch_tiled_s<4>(P, T, in, out, rule, cu_count, st);
-        default: return hipErrorInvalidValue;
+    return launch_tiled_any<false>(P, T, in, out, rule, nullptr, cu_count, st);
+}
+hipError_t launch_step_tiled_batch(const TileParams &T, const uint32_t *rec, const uint8_t *arena_in,
+                                   uint8_t *arena_out, uint32_t rule, int cu_count, hipStream_t st) {
+    return launch_tiled_any<true>(MapParams{}, T, arena_in, arena_out, rule, rec, cu_count, st);
+}
+// One thread per batch tile: find the instance holding batch tile g (the
+// last one whose first tile is <= g) and write the tile's record and its
+// eight neighbours, copied from the instance's own neighbour table.
+__global__ __launch_bounds__(256) void k_batch_tiles(const BatchInstance *__restrict__ inst, uint32_t ninst,
+                                                     uint32_t total, uint32_t *__restrict__ rec,
+                                                     uint32_t *__restrict__ nbr) {
+    for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < total; g += gridDim.x * 256) {
+        uint32_t lo = 0, hi = ninst - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (inst[mid].tile0 <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchInstance &I = inst[lo];
+        const uint32_t t = g - I.tile0;
+        rec[2 * uint64_t(g)] = I.base16;
+        rec[2 * uint64_t(g) + 1] = t | ((I.tail_partial && t + 1 == I.ntiles) ? 0x80000000u : 0u);
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(I.nbr + 8 * uint64_t(t));
+        uint4 *d4 = reinterpret_cast<uint4 *>(nbr + 8 * uint64_t(g));
+        d4[0] = s4[0];
+        d4[1] = s4[1];
     }
+}
+hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_t total, uint32_t *rec,
+                              uint32_t *nbr, hipStream_t st) {
+    if (!total || !ninst) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_batch_tiles, dim3(grid), dim3(256), 0, st, inst, ninst, total, rec, nbr);
+    return hipGetLastError();
 }
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st) {
     const uint32_t gx = uint32_t((B.pitch / 16 + 255) / 256);

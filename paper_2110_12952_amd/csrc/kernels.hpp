@@ -30,6 +30,13 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
 // Persistent launch sized to the resident capacity of cu_count CUs.
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                              uint32_t rule, int cu_count, hipStream_t st);
+// The tiled step over the tiles of a batch (tables from launch_batch_tiles,
+// T.ntiles = batch tiles, T.nbr = the batch neighbour table).
+hipError_t launch_step_tiled_batch(const TileParams &T, const uint32_t *rec, const uint8_t *arena_in,
+                                   uint8_t *arena_out, uint32_t rule, int cu_count, hipStream_t st);
+// Builds the per-tile record and neighbour tables of a batch on the device.
+hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_t total, uint32_t *rec,
+                              uint32_t *nbr, hipStream_t st);
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st);
 
 }  // namespace nbb

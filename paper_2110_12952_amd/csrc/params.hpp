@@ -85,6 +85,17 @@ struct TileParams {
                           // (the kernel reads 0xFF & 31 = 31: a bit outside cbmask)
 };
 
+// One instance of a batch (device table, sorted by tile0): its state starts
+// at byte 16 * base16 of the arena; its tiles are batch tiles
+// [tile0, tile0 + ntiles); nbr is its own 8-per-tile neighbour table.
+struct BatchInstance {
+    const uint32_t *nbr;
+    uint32_t base16;
+    uint32_t tile0;
+    uint32_t ntiles;
+    uint32_t tail_partial;  // 1 if k^r is not a multiple of 16
+};
+
 // The bounding-box step.  Membership splits into the low L levels (an
 // SL x SL bitmap, SL = s^L, one row of LW words per y) and the high r - L
 // levels (an NH x NH byte map, NH = s^(r-L)).

@@ -57,6 +57,12 @@ class PlanView(ctypes.Structure):
                 ("nbr", ctypes.POINTER(ctypes.c_uint32))]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("direct", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("cells", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("device_table_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -99,6 +105,16 @@ def lib() -> ctypes.CDLL:
     L.nbb_expand.restype = st
     L.nbb_gather.argtypes = [vp, vp, u64, vp, u64, vp]
     L.nbb_gather.restype = st
+    L.nbb_autotune.argtypes = [vp, vp, vp, u64, u32, u32, vp, ctypes.POINTER(Info)]
+    L.nbb_autotune.restype = st
+    L.nbb_batch_create.argtypes = [vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.nbb_batch_create.restype = st
+    L.nbb_batch_destroy.argtypes = [vp]
+    L.nbb_batch_destroy.restype = None
+    L.nbb_batch_query.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.nbb_batch_query.restype = st
+    L.nbb_batch_step.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_batch_step.restype = st
     L.nbb_bbox_pitch.argtypes = [vp]
     L.nbb_bbox_pitch.restype = u64
     L.nbb_last_error.restype = ctypes.c_char_p
@@ -202,6 +218,13 @@ class Fractal:
     def configure(self, strategy: int = STRATEGY_AUTO, tile_level: int = 0) -> None:
         _check(lib().nbb_configure(self._h, strategy, tile_level))
 
+    def autotune(self, a, b, steps: int = 5, rule: int = NBB_RULE_B3S23, stream=None) -> Info:
+        """Time each candidate plan on a and b (both overwritten) and keep the fastest."""
+        inf = Info()
+        _check(lib().nbb_autotune(self._h, _dev_ptr(a, "uint8", self.cells), _dev_ptr(b, "uint8", self.cells),
+                                  self.cells, int(steps), int(rule), _stream(stream), ctypes.byref(inf)))
+        return inf
+
     # ---- maps ------------------------------------------------------------
     def lam(self, idx=None, count: Optional[int] = None, out=None, stream=None, method: int = MAP_LUT):
         import torch
@@ -274,3 +297,93 @@ class Fractal:
         _check(lib().nbb_gather(self._h, _dev_ptr(box, "uint8"), box.shape[-1], _dev_ptr(c, "uint8", self.cells),
                                 self.cells, _stream(stream)))
         return c
+
+
+def shared_descriptors(specs: Sequence[Tuple[int, Sequence[Tuple[int, int]], int]]) -> list:
+    """Descriptors for the instances (s, offsets, r) of a batch: one per
+    distinct instance kind, shared by the instances of that kind.  Every
+    descriptor of one fractal is configured to the automatic tile level of
+    that fractal at its largest r (capped by its own r), so the batch steps
+    all instances of a fractal with one launch per generation."""
+    desc, top = {}, {}
+    for s, offsets, r in specs:
+        key = (int(s), tuple((int(a), int(b)) for a, b in offsets), int(r))
+        if key not in desc:
+            desc[key] = Fractal(key[0], key[1], key[2])
+        fk = key[:2]
+        if fk not in top or key[2] > top[fk][0]:
+            top[fk] = (key[2], desc[key])
+    for (s, offs, r), f in desc.items():
+        big_r, big = top[(s, offs)]
+        inf = big.info()
+        if inf.strategy == STRATEGY_TILED and f.info().strategy == STRATEGY_TILED:
+            f.configure(STRATEGY_TILED, min(r, int(inf.tile_level)))
+    return [desc[(int(s), tuple((int(a), int(b)) for a, b in o), int(r))] for s, o, r in specs]
+
+
+def pack_offsets(cells: Sequence[int]) -> Tuple[list, int]:
+    """Consecutive 16-byte-aligned arena offsets for states of these sizes,
+    and the arena length they need."""
+    offs, o = [], 0
+    for c in cells:
+        offs.append(o)
+        o += (int(c) + 15) & ~15
+    return offs, max(o, 16)
+
+
+class Batch:
+    """Many automata stepped together (nbb_batch_create / nbb_batch_step).
+
+    Instance i is the fractal fractals[i] with its state at byte offsets[i] of
+    each arena (default: packed one after another).  The descriptors must stay
+    alive and keep their configuration while the batch exists; the batch
+    holds references to them."""
+
+    def __init__(self, fractals: Sequence[Fractal], offsets: Optional[Sequence[int]] = None, stream=None):
+        self.fractals = list(fractals)
+        cells = [f.cells for f in self.fractals]
+        if offsets is None:
+            offsets, _ = pack_offsets(cells)
+        self.offsets = [int(o) for o in offsets]
+        self.cells = cells
+        n = len(self.fractals)
+        hs = (ctypes.c_void_p * max(n, 1))(*[f._h.value for f in self.fractals])
+        offs = (ctypes.c_uint64 * max(n, 1))(*self.offsets)
+        h = ctypes.c_void_p()
+        _check(lib().nbb_batch_create(hs, offs, n, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.arena_bytes = int(self.info().arena_bytes)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().nbb_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> BatchInfo:
+        inf = BatchInfo()
+        _check(lib().nbb_batch_query(self._h, ctypes.byref(inf)))
+        return inf
+
+    def new_arena(self):
+        import torch
+        return torch.zeros(max(self.arena_bytes, 16), dtype=torch.uint8,
+                           device=torch.device("cuda", torch.cuda.current_device()))
+
+    def state(self, arena, i: int):
+        """Instance i's state inside an arena (a view)."""
+        return arena[self.offsets[i]:self.offsets[i] + self.cells[i]]
+
+    def step(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        """Returns the arena (a or b) that holds the result."""
+        if a.numel() != b.numel():
+            raise ValueError("arenas differ in length")
+        res = ctypes.c_int(0)
+        _check(lib().nbb_batch_step(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
+                                    int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a

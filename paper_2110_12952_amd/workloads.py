@@ -121,6 +121,50 @@ WORKLOADS: Dict[str, Workload] = {
 }
 
 
+# Batched workload: 512 independent instances stepped together for 500
+# generations.  Each instance draws its fractal uniformly from four types and
+# its level uniformly from the levels of that type with k^r in [1e3, 1e7];
+# Bernoulli p uniform in [0.2, 0.6]; instance i is initialised from seed i.
+BATCH_LEVELS = {"triangle": tuple(range(7, 15)), "carpet": tuple(range(4, 8)),
+                "hfractal": tuple(range(4, 9)), "chandelier": tuple(range(5, 12))}
+
+
+@dataclass(frozen=True)
+class BatchItem:
+    fractal: FractalDef
+    r: int
+    p: float
+    seed: int
+
+    @property
+    def cells(self) -> int:
+        return self.fractal.k ** self.r
+
+
+@dataclass(frozen=True)
+class BatchWorkload:
+    name: str
+    count: int
+    steps: int
+    draw_seed: int
+    levels: Tuple[Tuple[str, Tuple[int, ...]], ...]
+    p_range: Tuple[float, float] = (0.2, 0.6)
+    rule: str = "B3/S23"
+
+    def items(self) -> List[BatchItem]:
+        rng = np.random.default_rng(self.draw_seed)
+        out = []
+        for i in range(self.count):
+            name, lv = self.levels[int(rng.integers(len(self.levels)))]
+            r = int(lv[int(rng.integers(len(lv)))])
+            p = float(rng.uniform(*self.p_range))
+            out.append(BatchItem(FRACTALS[name], r, p, i))
+        return out
+
+
+BATCH512 = BatchWorkload("batch512", 512, 500, 2110, tuple(BATCH_LEVELS.items()))
+
+
 def random_offsets(rng: np.random.Generator, s: int, k: int) -> Offsets:
     """k distinct digit pairs in [0,s)^2 in random order (a random NBB fractal)."""
     cells = rng.choice(s * s, size=k, replace=False)

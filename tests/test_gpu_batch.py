@@ -1,0 +1,226 @@
+"""GPU parity of the batched compact step and the autotuner.
+
+Every instance of a batch must end exactly where the oracle's compact step
+(and the library's own single-instance step) puts it; bytes of the arenas
+outside the instances' ranges must not change.  Inputs are seeded and
+synthetic; expected values come from oracle/ only.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2110_12952_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B3S23 = W.rule_mask("B3/S23")
+
+
+@pytest.fixture(scope="module")
+def N():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2110_12952_amd import nbbfrac
+    nbbfrac.lib()
+    return nbbfrac
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# An s = 5 fractal: no tiled plan, so its instances take the per-cell step.
+PLUS5 = W.FractalDef("plus5", 5, ((2, 0), (0, 2), (2, 2), (4, 2), (2, 4), (1, 1)))
+
+MIXED = [("triangle", 3), ("triangle", 5), ("triangle", 7), ("carpet", 2), ("carpet", 3),
+         ("hfractal", 2), ("hfractal", 3), ("chandelier", 3), ("chandelier", 4), ("grid4_12", 3),
+         ("cantor", 6), ("triangle", 0), ("vicsek", 3), ("triangle", 6), ("carpet", 3)]
+
+
+def _mixed(N, with_direct=True, common_level=True):
+    fds = [W.FRACTALS[n] for n, _ in MIXED] + ([PLUS5] if with_direct else [])
+    rs = [r for _, r in MIXED] + ([2] if with_direct else [])
+    frs = [N.Fractal(fd.s, fd.offsets, r) for fd, r in zip(fds, rs)]
+    if common_level:
+        # one tile level per fractal type, capped by r, so instances group
+        for f in frs:
+            if f.r >= 1 and f.s <= 4:
+                f.configure(N.STRATEGY_TILED, min(f.r, 2))
+    return fds, rs, frs
+
+
+def _spread_offsets(cells, seed):
+    """Offsets with random 16-byte-multiple gaps between instances."""
+    rng = np.random.default_rng(seed)
+    offs, o = [], 0
+    for c in cells:
+        o += 16 * int(rng.integers(0, 4))
+        offs.append(o)
+        o += (c + 15) & ~15
+    return offs, o + 32
+
+
+@pytest.mark.parametrize("rule", ["B3/S23", "B36/S23", "B1357/S02468", "B2/S"])
+@pytest.mark.parametrize("steps", [1, 6])
+def test_batch_mixed_vs_oracle(N, rule, steps):
+    fds, rs, frs = _mixed(N)
+    offs, total = _spread_offsets([f.cells for f in frs], 7 + steps)
+    batch = N.Batch(frs, offs)
+    inf = batch.info()
+    assert inf.instances == len(frs) and inf.direct >= 2  # triangle r = 0 and the s = 5 fractal
+    a = torch.full((total,), 0xA5, dtype=torch.uint8, device="cuda")
+    b = torch.full((total,), 0x5A, dtype=torch.uint8, device="cuda")
+    want = []
+    for i, (fd, r, f) in enumerate(zip(fds, rs, frs)):
+        f.init_compact(100 + i, 0.45, out=batch.state(a, i))
+        o = O.Fractal(fd.s, fd.offsets, r)
+        want.append(o.compact_steps(o.init_compact(100 + i, 0.45), W.rule_mask(rule), steps))
+    res = batch.step(a, b, steps, W.rule_mask(rule))
+    assert (res is b) == bool(steps & 1)
+    got = host(res)
+    for i in range(len(frs)):
+        np.testing.assert_array_equal(got[offs[i]:offs[i] + frs[i].cells], want[i],
+                                      err_msg=f"instance {i} {MIXED[i] if i < len(MIXED) else 'plus5'}")
+    # bytes outside every instance keep their fill in both arenas
+    inside = np.zeros(total, bool)
+    for o, c in zip(offs, [f.cells for f in frs]):
+        inside[o:o + c] = True
+    assert (host(a)[~inside] == 0xA5).all() and (host(b)[~inside] == 0x5A).all()
+
+
+def test_batch_groups_by_plan(N):
+    _, _, frs = _mixed(N, with_direct=False)
+    inf = N.Batch(frs).info()
+    kinds = {(f.s, f.offsets, f.info().tile_level) for f in frs if f.info().strategy == N.STRATEGY_TILED}
+    assert inf.groups == len(kinds)
+    assert inf.tiles == sum(f.info().tiles for f in frs if f.info().strategy == N.STRATEGY_TILED)
+    assert inf.cells == sum(f.cells for f in frs)
+
+
+def test_batch_default_levels_vs_single(N):
+    # descriptors at their automatic levels (different levels, several groups
+    # per fractal); every instance must match its own single-instance run
+    fds, rs, frs = _mixed(N, common_level=False)
+    batch = N.Batch(frs)
+    a, b = batch.new_arena(), batch.new_arena()
+    singles = []
+    for i, f in enumerate(frs):
+        f.init_compact(7 * i + 1, 0.5, out=batch.state(a, i))
+        s0 = f.init_compact(7 * i + 1, 0.5)
+        singles.append(f.step_compact(s0, torch.empty_like(s0), 9))
+    res = host(batch.step(a, b, 9))
+    for i, f in enumerate(frs):
+        np.testing.assert_array_equal(res[batch.offsets[i]:batch.offsets[i] + f.cells], host(singles[i]))
+
+
+def test_batch_empty_and_single(N):
+    e = N.Batch([])
+    assert e.info().instances == 0 and e.info().tiles == 0
+    a, b = e.new_arena(), e.new_arena()
+    assert e.step(a, b, 3) is b
+    fd = W.TRIANGLE
+    o = O.Fractal(fd.s, fd.offsets, 8)
+    f = N.Fractal(fd.s, fd.offsets, 8)
+    one = N.Batch([f])
+    a, b = one.new_arena(), one.new_arena()
+    f.init_compact(5, 0.5, out=one.state(a, 0))
+    got = host(one.state(one.step(a, b, 11), 0))
+    np.testing.assert_array_equal(got, o.compact_steps(o.init_compact(5, 0.5), B3S23, 11))
+
+
+def test_batch_zero_steps(N):
+    _, _, frs = _mixed(N)
+    batch = N.Batch(frs)
+    a, b = batch.new_arena(), batch.new_arena()
+    a.random_(0, 2)
+    b.fill_(3)
+    a0 = host(a).copy()
+    assert batch.step(a, b, 0) is a
+    np.testing.assert_array_equal(host(a), a0)
+    assert (host(b) == 3).all()
+
+
+def test_batch_rejects_bad_arguments(N):
+    fd = W.CARPET
+    f = N.Fractal(fd.s, fd.offsets, 3)
+    g = N.Fractal(fd.s, fd.offsets, 2)
+    with pytest.raises(N.NbbError, match="overlap"):
+        N.Batch([f, g], [0, 496])          # f holds 512 bytes
+    with pytest.raises(N.NbbError, match="multiples of 16"):
+        N.Batch([f, g], [0, 520])
+    with pytest.raises(N.NbbError) as ei:
+        N.Batch([f], [1 << 36])
+    assert ei.value.status == N.NBB_E_RANGE
+    batch = N.Batch([f, g], [0, 512])
+    a = torch.zeros(512 + 64, dtype=torch.uint8, device="cuda")
+    short = torch.zeros(512 + 48, dtype=torch.uint8, device="cuda")
+    with pytest.raises(N.NbbError, match="shorter"):
+        batch.step(short, torch.zeros_like(short), 1)
+    with pytest.raises(N.NbbError, match="overlap"):
+        batch.step(a, a, 1)
+    with pytest.raises(N.NbbError, match="bits outside"):
+        batch.step(a, torch.zeros_like(a), 1, rule=1 << 9)
+    big = torch.zeros(1200, dtype=torch.uint8, device="cuda")
+    with pytest.raises(N.NbbError, match="aligned"):
+        batch.step(big[1:577], big[600:1176], 1)
+
+
+def _c4(N, items):
+    return N.shared_descriptors([(it.fractal.s, it.fractal.offsets, it.r) for it in items])
+
+
+def test_batch512_equals_single_runs_and_oracle(N):
+    # the full batched workload, fewer generations: the batch against each
+    # instance's own single-instance run (whole states), and the smallest
+    # instances against the oracle
+    items = W.BATCH512.items()
+    frs = _c4(N, items)
+    batch = N.Batch(frs)
+    inf = batch.info()
+    assert inf.groups == 4 and inf.direct == 0
+    a, b = batch.new_arena(), batch.new_arena()
+    for i, (it, f) in enumerate(zip(items, frs)):
+        f.init_compact(it.seed, it.p, out=batch.state(a, i))
+    T = 24
+    ref = torch.empty_like(a)
+    tmp = torch.empty(max(f.cells for f in frs), dtype=torch.uint8, device="cuda")
+    for i, (it, f) in enumerate(zip(items, frs)):
+        s0 = batch.state(a, i).clone()
+        out = f.step_compact(s0, tmp[:f.cells], T)
+        batch.state(ref, i).copy_(out)
+    res = batch.step(a, b, T)
+    got, want = host(res), host(ref)
+    for i, f in enumerate(frs):
+        sl = slice(batch.offsets[i], batch.offsets[i] + f.cells)
+        np.testing.assert_array_equal(got[sl], want[sl], err_msg=f"instance {i}")
+    small = sorted(range(len(items)), key=lambda i: items[i].cells)[:4]
+    for i in small:
+        it = items[i]
+        o = O.Fractal(it.fractal.s, it.fractal.offsets, it.r)
+        exp = o.compact_steps(o.init_compact(it.seed, it.p), B3S23, T)
+        np.testing.assert_array_equal(got[batch.offsets[i]:batch.offsets[i] + frs[i].cells], exp)
+
+
+# ------------------------------------------------------------- autotuner --
+@pytest.mark.parametrize("name,r", [("triangle", 10), ("carpet", 5), ("chandelier", 6), ("hfractal", 2)])
+def test_autotune_then_step_matches_oracle(N, name, r):
+    fd = W.FRACTALS[name]
+    f = N.Fractal(fd.s, fd.offsets, r)
+    o = O.Fractal(fd.s, fd.offsets, r)
+    a, b = f.new_compact(), f.new_compact()
+    f.init_compact(3, 0.5, out=a)
+    inf = f.autotune(a, b, steps=2)
+    assert inf.strategy in (N.STRATEGY_TILED, N.STRATEGY_DIRECT)
+    got = f.info()
+    assert (got.strategy, got.tile_level) == (inf.strategy, inf.tile_level)
+    s0 = f.init_compact(3, 0.5)
+    res = host(f.step_compact(s0, torch.empty_like(s0), 13))
+    np.testing.assert_array_equal(res, o.compact_steps(o.init_compact(3, 0.5), B3S23, 13))
+
+
+def test_autotune_rejects_zero_steps(N):
+    f = N.Fractal(2, W.TRIANGLE.offsets, 5)
+    a, b = f.new_compact(), f.new_compact()
+    with pytest.raises(N.NbbError, match="steps"):
+        f.autotune(a, b, steps=0)

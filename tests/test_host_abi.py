@@ -173,3 +173,34 @@ def test_auto_tile_levels_for_the_workloads():
     got = {w.name: N.plan_tables(w.fractal.s, w.fractal.offsets, w.r)["tile_level"]
            for w in W.WORKLOADS.values()}
     assert got["triangle_r16"] == 7 and got["carpet_r9"] == 4 and got["hfractal_r10"] == 4
+
+
+def test_batch_workload_items_are_seeded():
+    items = W.BATCH512.items()
+    assert len(items) == 512 and items == W.BATCH512.items()
+    for it in items:
+        assert 1e3 <= it.cells <= 1e7 and 0.2 <= it.p <= 0.6
+        assert it.r in W.BATCH_LEVELS[it.fractal.name]
+    assert [it.seed for it in items] == list(range(512))
+    assert {it.fractal.name for it in items} == set(W.BATCH_LEVELS)
+
+
+def test_pack_offsets():
+    offs, total = N.pack_offsets([1, 16, 17, 0, 5])
+    assert offs == [0, 16, 32, 64, 64] and total == 80
+    assert all(o % 16 == 0 for o in offs)
+    assert N.pack_offsets([]) == ([], 16)
+
+
+def test_batch_create_without_device_reports_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = N.lib()
+    h = ctypes.c_void_p()
+    assert L.nbb_batch_create(None, None, 0, None, ctypes.byref(h)) == N.NBB_E_DEVICE
+    assert L.nbb_batch_create(None, None, 0, None, None) == N.NBB_E_INVALID
+    assert L.nbb_batch_step(None, None, None, 0, 1, N.NBB_RULE_B3S23, None, None) == N.NBB_E_INVALID
+    assert L.nbb_batch_query(None, None) == N.NBB_E_INVALID
+    L.nbb_batch_destroy(None)
+    assert L.nbb_autotune(None, None, None, 0, 1, 0, None, None) == N.NBB_E_INVALID
