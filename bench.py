@@ -7,7 +7,9 @@ Game of Life B3/S23.  A timed step is one generation of the compact step
 over the whole fractal (one kernel launch).  The same run also times the
 bounding-box step over the full 65,536^2 box (the paper's baseline) and the
 lambda / nu maps over all 43M indices, checks that the compact and box
-results agree, and times the CPU oracle on a bounded sample.
+results agree, times the 512-instance batched workload against one launch
+per instance, serves Poisson-arriving requests for p50/p99 latency, and
+times the CPU oracle on a bounded sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -23,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+STRATEGY_NAMES = {1: "tiled", 2: "direct", 3: "tiled_wave"}
 COUNTERS = os.path.join(ROOT, "profiles", "compact_step_triangle_r16_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_12952_amd", "csrc", "kernels.hip")
 
@@ -82,6 +85,76 @@ def cpu_baseline(W, wl, seconds):
                       f"the full {o.cells}-cell state, {t:.1f} s"}
 
 
+def batch_run(torch, N, W, args):
+    """The 512-instance batched workload: all instances stepped together, one
+    launch per fractal group per generation, against one launch per instance
+    per generation."""
+    bw = W.BATCH512
+    items = bw.items()
+    frs = N.shared_descriptors([(it.fractal.s, it.fractal.offsets, it.r) for it in items])
+    batch = N.Batch(frs)
+    inf = batch.info()
+    rule = W.rule_mask(bw.rule)
+    a, b = batch.new_arena(), batch.new_arena()
+    for i, (it, f) in enumerate(zip(items, frs)):
+        f.init_compact(it.seed, it.p, out=batch.state(a, i))
+    init = a.clone()
+    Kb = args.batch_steps or bw.steps
+    batch.step(a.clone(), b, 2, rule)
+    ms, _ = time_events(torch, lambda: batch.step(a, b, Kb, rule))
+    ms_step = ms / Kb
+    # one launch per instance and generation, from the same initial states
+    Ts = args.batch_seq_steps
+    sa, sb = init.clone(), torch.empty_like(init)
+    va = [batch.state(sa, i) for i in range(len(frs))]
+    vb = [batch.state(sb, i) for i in range(len(frs))]
+
+    def sequential():
+        for f, x, y in zip(frs, va, vb):
+            f.step_compact(x, y, Ts, rule)
+    ms_seq, _ = time_events(torch, sequential)
+    seq_res = sb if Ts & 1 else sa
+    ba = init.clone()
+    bres = batch.step(ba, torch.empty_like(ba), Ts, rule)
+    same = all(torch.equal(batch.state(bres, i), batch.state(seq_res, i)) for i in range(len(frs)))
+    levels = sorted({(it.fractal.name, f.info().tile_level, STRATEGY_NAMES[f.info().strategy])
+                     for it, f in zip(items, frs)})
+    out = {"workload": bw.name, "instances": len(items), "cells": int(inf.cells), "groups": int(inf.groups),
+           "tiles": int(inf.tiles), "plans": [list(x) for x in levels], "steps": Kb, "ms_per_step": ms_step,
+           "cell_updates_per_s": inf.cells * Kb / (ms * 1e-3),
+           "alg_gbps": 2 * inf.cells / (ms_step * 1e-3) / 1e9,
+           "sequential_ms_per_step": ms_seq / Ts, "sequential_steps": Ts,
+           "speedup_vs_sequential": (ms_seq / Ts) / ms_step, "matches_sequential": bool(same)}
+    out["roofline_frac"] = out["alg_gbps"] / HBM_PEAK_GBPS
+    log(f"batch: {ms_step * 1e3:.1f} us/step, {out['cell_updates_per_s']:.3e} cell-updates/s, "
+        f"{out['alg_gbps']:.0f} GB/s; one launch per instance {ms_seq / Ts * 1e3:.1f} us/step; same={same}")
+    return out
+
+
+def serve_run(torch, W, args):
+    """The served workload: Poisson arrivals (2000 per second), each request
+    one automaton run on a carpet or H fractal, served from states resident
+    in HBM by the request loop; p50/p99 latency from arrival to the result
+    being in HBM."""
+    from paper_2110_12952_amd.serve import Server
+    sw = W.SERVE2000
+    reqs = sw.requests(args.serve_seconds)
+    srv = Server(8 << 30, rule=W.rule_mask(sw.rule), deadline_s=args.serve_deadline, round_s=0.02,
+                 max_gens=64, throughput0=1.5e12, tile_levels={"carpet": 4, "hfractal": 4})
+    # warm the descriptor cache and the kernels outside the measured run
+    srv.run([type(q)(q.rid, 0.0, q.fractal, q.r, 10, q.p, q.seed) for q in reqs[:64]])
+    st = srv.run(reqs, log=log)
+    out = {"workload": sw.name, "rate_per_s": sw.rate, "arrival_window_s": args.serve_seconds,
+           "deadline_s": args.serve_deadline,
+           "offered_cell_updates_per_s": sum(q.cells * q.steps for q in reqs) / args.serve_seconds}
+    out.update(st.summary())
+    log(f"serve: {out['completed']}/{out['offered']} completed, p50 {out['latency_p50_ms']:.1f} ms, "
+        f"p99 {out['latency_p99_ms']:.1f} ms, {out['cell_updates_per_s']:.3e} cell-updates/s")
+    del srv
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +166,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bbox", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=None,
+                    help="generations of the 512-instance batch (default: the workload's 500)")
+    ap.add_argument("--batch-seq-steps", type=int, default=10,
+                    help="generations of the one-launch-per-instance comparison")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="arrival window of the served workload (its full length is 60 s); 0 skips it")
+    ap.add_argument("--serve-deadline", type=float, default=0.5,
+                    help="admission: predicted drain time limit, seconds")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -189,6 +271,9 @@ def main():
     log("maps: " + ", ".join(f"{k} {v:.0f}" if isinstance(v, float) else f"{k} {v}" for k, v in maps.items()))
     del x, y, idx
 
+    batch = None if args.no_batch else batch_run(torch, N, W, args)
+    serve = serve_run(torch, W, args) if args.serve_seconds > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W, wl, args.cpu_seconds)
@@ -210,11 +295,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "fractal": f"F^{{{fd.k},{fd.s}}} {fd.name}", "r": wl.r, "n": g.n,
                    "cells": g.cells, "p": wl.p, "seed": wl.seeds[0], "rule": wl.rule,
-                   "strategy": "tiled" if info.strategy == N.STRATEGY_TILED else "direct",
+                   "strategy": STRATEGY_NAMES[info.strategy],
                    "tile_level": info.tile_level},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_step_tiled" if info.strategy == N.STRATEGY_TILED else "k_step_direct",
+                     "kernel": "k_step_direct" if info.strategy == N.STRATEGY_DIRECT else "k_step_tiled",
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "bbox": bbox,
@@ -222,6 +307,8 @@ def main():
         "compact_equals_bbox": parity,
         "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
         "maps": maps,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -70,6 +70,7 @@ typedef enum {
 #define NBB_STRATEGY_AUTO 0u   /* TILED when the fractal allows it, else DIRECT */
 #define NBB_STRATEGY_TILED 1u  /* level-m tiles staged in LDS with their halo */
 #define NBB_STRATEGY_DIRECT 2u /* one thread per cell: lambda, 8 x nu, rule */
+#define NBB_STRATEGY_TILED_WAVE 3u /* TILED with one wavefront per tile: for small tiles */
 
 typedef struct nbb_fractal nbb_fractal;
 
@@ -78,7 +79,7 @@ typedef struct {
     uint64_t cells;        /* k^r */
     uint64_t tiles;        /* k^(r - tile_level) */
     uint32_t k, s, r;
-    uint32_t strategy;     /* NBB_STRATEGY_TILED or NBB_STRATEGY_DIRECT */
+    uint32_t strategy;     /* NBB_STRATEGY_TILED, _TILED_WAVE or _DIRECT */
     uint32_t tile_level;   /* m: a tile is an aligned run of k^m compact cells */
     uint32_t tile_side;    /* s^m */
     uint32_t halo_cells;   /* neighbour cells staged per tile */
@@ -107,10 +108,12 @@ void nbb_destroy(nbb_fractal *f);
 nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
 
 /*
- * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED,
- * the tile level m (0 = automatic; otherwise 1 <= m <= r).  TILED needs
- * 2 <= s <= 4 and r >= 1; NBB_E_INVALID when the request cannot be met (the
- * descriptor keeps its previous plan).  Rebuilds and re-uploads the tile
+ * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED
+ * and TILED_WAVE, the tile level m (0 = automatic; otherwise 1 <= m <= r).
+ * Both need 2 <= s <= 4 and r >= 1; TILED_WAVE also needs a tile small
+ * enough for one wavefront (k^m + 30 <= 2048 cells, at most 256 halo cells
+ * and blocks, four LDS boxes within 64 KiB).  NBB_E_INVALID when the request
+ * cannot be met (the descriptor keeps its previous plan).  Rebuilds and re-uploads the tile
  * tables; must not overlap other calls on the same descriptor.
  */
 nbb_status nbb_configure(nbb_fractal *f, uint32_t strategy, uint32_t tile_level);
@@ -196,8 +199,9 @@ nbb_status nbb_gather(const nbb_fractal *f, const uint8_t *bbox, uint64_t pitch,
  * Autotuner.  The paper picks its block size per method by measurement
  * (section 4: the best rho differs between methods); this does the same for
  * the compact step.  Times `steps` generations (after one untimed one) of
- * each candidate -- TILED at every tile level m whose tile holds at least 128
- * cells, plus the largest level that fits, and DIRECT -- on the caller's
+ * each candidate -- TILED and TILED_WAVE at every tile level m whose tile
+ * holds at least 128 cells, plus the largest level that fits, and DIRECT --
+ * on the caller's
  * buffers a and b (their contents are overwritten: pass a copy of a
  * representative state), then configures the fastest, as nbb_configure would.
  * Waits for `stream`.  Arguments as nbb_step_compact; steps >= 1.  If info is
@@ -212,7 +216,7 @@ nbb_status nbb_autotune(nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, ui
  * offsets and r), stepped together.  All states live in one device arena per
  * buffer: instance i occupies bytes [offsets[i], offsets[i] + k_i^r_i) of
  * both arenas passed to nbb_batch_step.  Instances whose descriptors use the
- * TILED strategy at the same tile level for the same (k, s, offsets) form one
+ * same tiled strategy at the same tile level for the same (k, s, offsets) form one
  * group and are stepped by one launch per generation over all their tiles
  * (configure a common tile level with nbb_configure to group instances of
  * different r); instances with the DIRECT strategy are stepped one launch
@@ -253,6 +257,18 @@ nbb_status nbb_batch_query(const nbb_batch *batch, nbb_batch_info *info);
 nbb_status nbb_batch_step(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
                           uint32_t rule, int *result_in_b, void *stream);
 
+/*
+ * As nbb_batch_step, but instance i (numbered as in nbb_batch_create) takes
+ * steps[i] generations: generation g runs only the instances with
+ * steps[i] > g, so instance i's result ends in b iff steps[i] is odd and an
+ * instance with 0 steps is left untouched.  Within each group the step
+ * counts must not increase in the order the instances were given to
+ * nbb_batch_create (NBB_E_INVALID otherwise): list instances by decreasing
+ * step count.  steps is a host array of nbb_batch_info.instances entries.
+ */
+nbb_status nbb_batch_step_each(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len,
+                               const uint32_t *steps, uint32_t rule, void *stream);
+
 /* Smallest box pitch for this descriptor: n rounded up to a multiple of 16. */
 uint64_t nbb_bbox_pitch(const nbb_fractal *f);
 
@@ -270,8 +286,12 @@ const char *nbb_status_string(nbb_status s);
  *   lut0[i], i < tile_cells: byte offset in the tile's LDS box of local cell i
  *   lut1[b], b < blocks: offset of the window corner (one row up, one column
  *   left) of block b, a level-block_level square of side block_side
+ *   The box has box_rows rows of box_pitch bytes; tile cell (x, y) sits at
+ *   row y+1, column x+1.  Rows and columns that no block window reaches are
+ *   left out (box_rows <= tile_side + 2).
  *   halo_src[h] = (direction << 29) | local index in that neighbour tile,
- *   direction = (dy+1)*3 + (dx+1) skipping the centre (0..7);
+ *   direction = (dy+1)*3 + (dx+1) skipping the centre (0..7), for every cell
+ *   of a neighbouring tile that lands inside the box;
  *   halo_dst[h] = byte offset in the LDS box;
  *   nbr[8 t + d] = tile in direction d of tile t (same numbering), or
  *   0xFFFFFFFF where that block of the box holds no fractal cell.

@@ -65,10 +65,13 @@ struct nbb_plan {
 struct BatchGroup {
     TileParams tp;           // the plan of the group's first descriptor; nbr / ntiles are the batch's
     const uint32_t *rec = nullptr;
+    std::vector<uint32_t> index;      // the group's instances (caller's numbering), in tile order
+    std::vector<uint64_t> tiles_end;  // tiles of the first j+1 of them
 };
 struct BatchDirect {
     const nbb_fractal *f;
     uint64_t offset;
+    uint32_t index;
 };
 struct nbb_batch {
     int device = 0;
@@ -185,6 +188,7 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     nbb_status s = upload(blob, src, bytes, 5, dst);
     if (s != NBB_OK) return s;
     *T = TileParams{};
+    T->team = p.team;
     T->m = p.m;
     T->S = p.S;
     T->K = p.K;
@@ -335,7 +339,7 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->blocks = t.nblk;
     view->halo_count = uint32_t(t.halo_src.size());
     view->box_pitch = t.W;
-    view->box_rows = t.S + 2;
+    view->box_rows = t.rows;
     view->lds_bytes = t.lds_total;
     view->tiles = t.ntiles;
     view->lut0 = t.lut0.data();
@@ -413,7 +417,7 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
     info->s = F->f.s;
     info->r = F->f.r;
     info->strategy = F->strategy;
-    if (F->strategy == NBB_STRATEGY_TILED) {
+    if (F->strategy != NBB_STRATEGY_DIRECT) {
         info->tiles = F->tile.ntiles;
         info->tile_level = F->tile.m;
         info->tile_side = F->tile.S;
@@ -439,11 +443,13 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
         F->strategy = NBB_STRATEGY_DIRECT;
         return NBB_OK;
     }
-    if (strategy != NBB_STRATEGY_TILED) return fail(NBB_E_INVALID, "unknown strategy");
+    if (strategy != NBB_STRATEGY_TILED && strategy != NBB_STRATEGY_TILED_WAVE)
+        return fail(NBB_E_INVALID, "unknown strategy");
+    const uint32_t team = strategy == NBB_STRATEGY_TILED_WAVE ? 64u : 256u;
     std::string msg;
     TilePlan plan;
     uint32_t m = tile_level ? tile_level : auto_tile_level(F->f);
-    if (!tiled_supported(F->f) || !build_tile_plan(F->f, m, &plan, &msg))
+    if (!tiled_supported(F->f) || !build_tile_plan(F->f, m, &plan, &msg, team))
         return fail(NBB_E_INVALID, msg.empty() ? "the tiled step does not support this fractal" : msg);
     DevBlob blob;
     TileParams T;
@@ -453,7 +459,7 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     F->dtile = blob;
     F->tile = std::move(plan);
     F->tp = T;
-    F->strategy = NBB_STRATEGY_TILED;
+    F->strategy = strategy;
     return NBB_OK;
 }
 
@@ -484,7 +490,10 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
         for (size_t i = 0; i < fit.size(); ++i) {
             uint64_t K = 1;
             for (uint32_t j = 0; j < fit[i]; ++j) K *= F->f.k;
-            if (K >= 128 || i + 1 == fit.size()) cand.push_back({NBB_STRATEGY_TILED, fit[i]});
+            if (K >= 128 || i + 1 == fit.size()) {
+                cand.push_back({NBB_STRATEGY_TILED, fit[i]});
+                cand.push_back({NBB_STRATEGY_TILED_WAVE, fit[i]});  // skipped where it does not fit
+            }
         }
     }
     cand.push_back({NBB_STRATEGY_DIRECT, 0});
@@ -539,9 +548,7 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         if (offsets[i] >= kArenaLimit || F->f.cells > kArenaLimit)
             return fail(NBB_E_RANGE, "instance offset beyond 2^36");
     }
-    // Ranges must not overlap: check them in offset order, which is also the
-    // order the instances take in each group (tiles of neighbouring states
-    // then sit next to each other in a launch).
+    // Ranges must not overlap: check them in offset order.
     std::vector<uint32_t> order(count);
     std::iota(order.begin(), order.end(), 0u);
     std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return offsets[x] < offsets[y]; });
@@ -565,15 +572,18 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         for (uint32_t j = 0; j < x->f.k; ++j)
             if (x->f.ox[j] != y->f.ox[j] || x->f.oy[j] != y->f.oy[j]) return false;
         const TileParams &a = x->tp, &b = y->tp;
-        return a.m == b.m && a.W == b.W && a.lds_total == b.lds_total && a.halo_count == b.halo_count;
+        return x->strategy == y->strategy && a.team == b.team && a.m == b.m && a.W == b.W &&
+               a.lds_total == b.lds_total && a.halo_count == b.halo_count;
     };
+    // Instances keep the caller's order inside each group (nbb_batch_step_each
+    // relies on it).
     std::vector<const nbb_fractal *> reps;
     std::vector<std::vector<BatchInstance>> members;
-    for (uint32_t j = 0; j < count; ++j) {
-        const uint32_t i = order[j];
+    std::vector<std::vector<uint32_t>> member_index;
+    for (uint32_t i = 0; i < count; ++i) {
         const nbb_fractal *F = fractals[i];
-        if (F->strategy != NBB_STRATEGY_TILED) {
-            B->direct.push_back({F, offsets[i]});
+        if (F->strategy == NBB_STRATEGY_DIRECT) {
+            B->direct.push_back({F, offsets[i], i});
             continue;
         }
         size_t g = 0;
@@ -581,7 +591,9 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         if (g == reps.size()) {
             reps.push_back(F);
             members.emplace_back();
+            member_index.emplace_back();
         }
+        member_index[g].push_back(i);
         BatchInstance I{};
         I.nbr = F->tp.nbr;
         I.base16 = uint32_t(offsets[i] >> 4);
@@ -644,7 +656,10 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         G.tp.ntiles = uint32_t(ntiles[g]);
         G.tp.cells = 0;  // per instance, from the records
         G.rec = rec;
-        B->groups.push_back(G);
+        G.index = member_index[g];
+        uint64_t acc = 0;
+        for (const BatchInstance &I : members[g]) G.tiles_end.push_back(acc += I.ntiles);
+        B->groups.push_back(std::move(G));
         B->cu_count = reps[g]->cu_count;
     }
     for (const BatchDirect &d : B->direct) B->cu_count = d.f->cu_count;
@@ -692,6 +707,55 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
         }
         for (const BatchDirect &d : B->direct) {
+            const nbb_fractal *F = d.f;
+            e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + d.offset, out + d.offset, rule,
+                                   map_grid(F, F->f.cells), s);
+            if (e != hipSuccess) return hip_fail(e, "batch direct step launch");
+        }
+        std::swap(in, out);
+    }
+    return NBB_OK;
+}
+
+nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len,
+                               const uint32_t *steps, uint32_t rule, void *stream) {
+    if (!B) return fail(NBB_E_INVALID, "null batch");
+    if (B->count && (!a || !b || !steps)) return fail(NBB_E_INVALID, "null argument");
+    if (arena_len < B->arena_bytes) return fail(NBB_E_INVALID, "arena shorter than the batch needs");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
+    if (B->count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != B->device) return fail(NBB_E_INVALID, "batch belongs to another device");
+    uint32_t most = 0;
+    for (const BatchGroup &G : B->groups)
+        for (size_t j = 0; j < G.index.size(); ++j) {
+            if (j && steps[G.index[j]] > steps[G.index[j - 1]])
+                return fail(NBB_E_INVALID, "step counts must not increase within a group of the batch");
+            most = std::max(most, steps[G.index[j]]);
+        }
+    for (const BatchDirect &d : B->direct) most = std::max(most, steps[d.index]);
+    // Generation g steps, in each group, the prefix of instances with more
+    // than g steps; instance i's state alternates a -> b -> a ... like the
+    // whole batch's, so its result ends in b iff steps[i] is odd.
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<size_t> live(B->groups.size());
+    for (size_t k = 0; k < B->groups.size(); ++k) live[k] = B->groups[k].index.size();
+    uint8_t *in = a, *out = b;
+    for (uint32_t g = 0; g < most; ++g) {
+        for (size_t k = 0; k < B->groups.size(); ++k) {
+            const BatchGroup &G = B->groups[k];
+            while (live[k] && steps[G.index[live[k] - 1]] <= g) --live[k];
+            if (!live[k]) continue;
+            TileParams T = G.tp;
+            T.ntiles = uint32_t(G.tiles_end[live[k] - 1]);
+            e = launch_step_tiled_batch(T, G.rec, in, out, rule, B->cu_count, s);
+            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+        }
+        for (const BatchDirect &d : B->direct) {
+            if (steps[d.index] <= g) continue;
             const nbb_fractal *F = d.f;
             e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + d.offset, out + d.offset, rule,
                                    map_grid(F, F->f.cells), s);
@@ -798,7 +862,7 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     if (result_in_b) *result_in_b = int(steps & 1);
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *in = a, *out = b;
-    if (F->strategy == NBB_STRATEGY_TILED) {
+    if (F->strategy != NBB_STRATEGY_DIRECT) {
         for (uint32_t i = 0; i < steps; ++i) {
             hipError_t e = launch_step_tiled(F->mp, F->tp, in, out, rule, F->cu_count, s);
             if (e != hipSuccess) return hip_fail(e, "tiled step launch");

@@ -37,20 +37,23 @@ __device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
 struct XcdRange {
     uint64_t first, end, step;
 };
-__device__ __forceinline__ XcdRange xcd_range(uint32_t wg, uint32_t G, uint64_t T) {
+// With `sub` workers per work-group (worker w of group wg), the XCD's slice
+// is shared by all workers of its work-groups.
+__device__ __forceinline__ XcdRange xcd_range(uint32_t wg, uint32_t G, uint64_t T, uint32_t w = 0,
+                                              uint32_t sub = 1) {
     XcdRange r;
     if (G >= 8) {
-        uint32_t x = wg & 7, slot = wg >> 3;
+        uint32_t x = wg & 7, slot = (wg >> 3) * sub + w;
         uint32_t cnt = (G - x + 7) >> 3;
         uint64_t before = uint64_t(x) * (G >> 3) + min(x, G & 7);
         uint64_t start = T * before / G;
         r.end = T * (before + cnt) / G;
         r.first = start + slot;
-        r.step = cnt;
+        r.step = uint64_t(cnt) * sub;
     } else {
-        r.first = wg;
+        r.first = uint64_t(wg) * sub + w;
         r.end = T;
-        r.step = G;
+        r.step = uint64_t(G) * sub;
     }
     return r;
 }
@@ -444,11 +447,11 @@ struct TilePrefetch {
 // Loads tile t (local index within the state array `in` of cells `cells`)
 // and its halo.  `tail`: the tile holds the last cell of an array whose
 // length is not a multiple of 16, so its last chunk may not be read whole.
-template <int CPT, int HPT>
+template <int TEAM, int CPT, int HPT>
 __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t *__restrict__ in,
                                               uint32_t t, bool tail, uint32_t cells, const uint32_t *nb,
                                               const uint32_t *hsrc, TilePrefetch<CPT, HPT> &pf) {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x % TEAM;
     const uint32_t B = t * T.K;
     const uint32_t ph = B & 15;
     const uint32_t nchunks = (ph + T.K + 15) >> 4;
@@ -456,7 +459,7 @@ __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t
     const uint16_t *lut = T.lut0p + ph * T.lut0_stride;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        const uint32_t c = tid + 256 * j;
+        const uint32_t c = tid + TEAM * j;
         if (c < nchunks) {
             if (!tail || c + 1 < nchunks) {
                 pf.v[j] = *reinterpret_cast<const uint4 *>(gin + 16 * c);
@@ -560,29 +563,54 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
 // tile_prefetch) of the state at byte 16 rec[2g] of the arena, and T.nbr
 // holds its eight neighbours as local tiles of the same state.  The record
 // travels through LDS with the neighbour tiles, two tiles ahead.
-template <int BS, int CPT, int HPT, int BPT, bool BATCH>
+//
+// TEAM: threads per tile.  256 = the whole work-group works on one tile at a
+// time.  64 = each wavefront is a worker of its own with its own LDS box and
+// its own range of tiles, synchronising only within the wavefront; for small
+// tiles, whose few chunks, halo cells and blocks leave most of a work-group
+// idle, four independent pipelines per work-group hide more memory latency.
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+    if (TEAM == 256) {
+        __syncthreads();
+    } else {
+        // one wavefront: its LDS accesses complete in program order, so only
+        // the compiler must be kept from moving them across this point
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
 __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule,
     const uint32_t *__restrict__ rec) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    uint8_t *box = lds;
+    extern __shared__ __align__(16) uint8_t lds_all[];
+    constexpr uint32_t kTeams = 256 / TEAM;
     constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
-    constexpr uint32_t kLane0 = 256 - kLanes;
-    __shared__ uint32_t nbr[2][kLanes];
-    const uint32_t tid = threadIdx.x;
+    constexpr uint32_t kLane0 = TEAM - kLanes;
+    __shared__ uint32_t nbr_all[kTeams][2][kLanes];
+    // the team index is uniform across a wavefront: keep it (and every tile
+    // index derived from it) in scalar registers
+    const uint32_t team = TEAM == 256 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x / TEAM);
+    const uint32_t tid = TEAM == 256 ? threadIdx.x : threadIdx.x % TEAM;
+    uint8_t *lds = lds_all + team * T.lds_total;
+    uint8_t *box = lds;
+    uint32_t (*nbr)[kLanes] = nbr_all[team];
     const uint32_t K = T.K;
-    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
+    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles, team, kTeams);
     // word l of the per-tile LDS entry of tile t
     auto entry = [&](uint64_t t, uint32_t l) -> uint32_t {
         return (!BATCH || l < 8) ? T.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
     };
 
-    for (uint32_t o = tid * 16; o < T.lds_total; o += 256 * 16)
-        *reinterpret_cast<uint4 *>(lds + o) = make_uint4(0, 0, 0, 0);
+    for (uint32_t o = threadIdx.x * 16; o < kTeams * T.lds_total; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(lds_all + o) = make_uint4(0, 0, 0, 0);
     uint32_t hsrc[HPT], hdst[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
-        const uint32_t h = tid + 256 * j;
+        const uint32_t h = tid + TEAM * j;
         const bool ok = h < T.halo_count;
         hsrc[j] = ok ? T.halo_src[h] : kOutside;
         hdst[j] = ok ? T.halo_dst[h] : T.dummy;
@@ -590,10 +618,10 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     // Block window corners (the same for every tile).
     uint32_t blk[BPT];
 #pragma unroll
-    for (int j = 0; j < BPT; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
+    for (int j = 0; j < BPT; ++j) blk[j] = T.lut1[min(tid + TEAM * j, T.nblk - 1)];
     // Neighbour tiles go through LDS two tiles ahead: the last kLanes threads
-    // load the entries of tile it+2 after the first barrier of tile it and
-    // publish them after its second barrier.
+    // of the team load the entries of tile it+2 after the first barrier of
+    // tile it and publish them after its second barrier.
     if (tid >= kLane0) {
         if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
         if (R.first + R.step < R.end) nbr[1][tid - kLane0] = entry(R.first + R.step, tid - kLane0);
@@ -623,7 +651,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     TilePrefetch<CPT, HPT> pf;
     if (R.first < R.end) {
         locate(R.first, nbr[0]);
-        tile_prefetch<CPT, HPT>(T, src, local, tail, cells, nbr[0], hsrc, pf);
+        tile_prefetch<TEAM, CPT, HPT>(T, src, local, tail, cells, nbr[0], hsrc, pf);
     }
 
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
@@ -639,7 +667,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         //    bytes outside the tile point at a never-read byte.
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            if (tid + 256 * j < nchunks) {
+            if (tid + TEAM * j < nchunks) {
                 const uint32_t v[4] = {pf.v[j].x, pf.v[j].y, pf.v[j].z, pf.v[j].w};
                 const uint32_t e[8] = {pf.e[j][0].x, pf.e[j][0].y, pf.e[j][0].z, pf.e[j][0].w,
                                        pf.e[j][1].x, pf.e[j][1].y, pf.e[j][1].z, pf.e[j][1].w};
@@ -650,13 +678,13 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) box[hdst[j]] = uint8_t(pf.halo[j]);
-        __syncthreads();
+        team_sync<TEAM>();
 
         // 2. start loading the next tile
         if (t64 + R.step < R.end) {
             const uint32_t *e = nbr[(it + 1) & 1];
             locate(t64 + R.step, e);
-            tile_prefetch<CPT, HPT>(T, src, local, tail, cells, e, hsrc, pf);
+            tile_prefetch<TEAM, CPT, HPT>(T, src, local, tail, cells, e, hsrc, pf);
         }
         uint32_t nb2 = kOutside;
         if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
@@ -665,16 +693,16 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         //    only readers, all finished before this tile's first barrier)
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
-            if (tid + 256 * j < T.nblk)  // waves with no block left skip the work
-                slots[tid + 256 * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
-        __syncthreads();
+            if (tid + TEAM * j < T.nblk)  // waves with no block left skip the work
+                slots[tid + TEAM * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
+        team_sync<TEAM>();
 
         // 4. slots -> 16 next states per chunk -> bytes -> global; the two
         //    edge chunks are shared with the neighbouring tiles and written
         //    bytewise.  Byte t of chunk c holds local cell 16 c - ph + t.
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const uint32_t c = tid + 256 * j;
+            const uint32_t c = tid + TEAM * j;
             if (c < nchunks) {
                 const uint32_t lo = 16 * c > ph ? 16 * c - ph : 0u;  // first local cell in the chunk
                 const uint32_t a0 = udiv(T.divCB, lo);
@@ -836,35 +864,37 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
 }
 // Persistent launch: as many work-groups as can be resident at once (the
 // occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT, int BPT, bool BATCH>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+    constexpr uint32_t kTeams = 256 / TEAM;
+    const size_t lds = size_t(kTeams) * T.lds_total;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH>,
-                                                                256, T.lds_total);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>, 256, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
-    const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, T.ntiles);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH>), dim3(uint32_t(grid)), dim3(256), T.lds_total, st,
+    const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, (T.ntiles + kTeams - 1) / kTeams);
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>), dim3(uint32_t(grid)), dim3(256), lds, st,
                        P, T, in, out, rule, rec);
     return hipGetLastError();
 }
-template <int BS, int CPT, int HPT, bool BATCH>
+template <int BS, int CPT, int HPT, bool BATCH, int TEAM>
 static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    const uint32_t bpt = (T.nblk + 255) / 256;
-    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH>(P, T, in, out, rule, rec, cu_count, st);
+    const uint32_t bpt = (T.nblk + TEAM - 1) / TEAM;
+    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
-template <int BS, bool BATCH>
+template <int BS, bool BATCH, int TEAM>
 static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    const uint32_t cpt = (T.K + 30 + 16 * 256 - 1) / (16 * 256);
-    const uint32_t hpt = (T.halo_count + 255) / 256;
+    const uint32_t cpt = (T.K + 30 + 16 * TEAM - 1) / (16 * TEAM);
+    const uint32_t hpt = (T.halo_count + TEAM - 1) / TEAM;
 #define NBB_TILED_CASE(C, H) \
-    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH>(P, T, in, out, rule, rec, cu_count, st)
+    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st)
     NBB_TILED_CASE(1, 1);
     NBB_TILED_CASE(1, 2);
     NBB_TILED_CASE(1, 4);
@@ -874,15 +904,22 @@ static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const 
 #undef NBB_TILED_CASE
     return hipErrorInvalidValue;
 }
+template <bool BATCH, int TEAM>
+static hipError_t launch_tiled_bs(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
+                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+    switch (T.BS) {
+        case 2: return launch_tiled_s<2, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+        case 3: return launch_tiled_s<3, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+        case 4: return launch_tiled_s<4, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 template <bool BATCH>
 static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                    uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    switch (T.BS) {
-        case 2: return launch_tiled_s<2, BATCH>(P, T, in, out, rule, rec, cu_count, st);
-        case 3: return launch_tiled_s<3, BATCH>(P, T, in, out, rule, rec, cu_count, st);
-        case 4: return launch_tiled_s<4, BATCH>(P, T, in, out, rule, rec, cu_count, st);
-        default: return hipErrorInvalidValue;
-    }
+    if (T.team == 64) return launch_tiled_bs<BATCH, 64>(P, T, in, out, rule, rec, cu_count, st);
+    if (T.team == 256) return launch_tiled_bs<BATCH, 256>(P, T, in, out, rule, rec, cu_count, st);
+    return hipErrorInvalidValue;
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                              uint32_t rule, int cu_count, hipStream_t st) {

@@ -59,6 +59,7 @@ struct MfmaLambda {
 // it in an LDS box of (S + 2) rows by W bytes, then evaluates the rule per
 // level-q block (side BS = s^q, CB = k^q cells, consecutive in compact order).
 struct TileParams {
+    uint32_t team;        // threads per tile: 256 (work-group) or 64 (wavefront)
     uint32_t m, S, K, W;
     uint32_t q, BS, CB;   // block level, block side s^q, cells per block k^q
     uint32_t cbmask;      // (1 << CB) - 1
@@ -67,7 +68,7 @@ struct TileParams {
     uint32_t slot_off;    // LDS offset of the result slots: u16 slot b = next states of block b
     uint32_t nslot;       // slots that cover any 16 consecutive cells: 1 + ceil(15 / CB)
     UDiv divCB;           // division by CB
-    uint32_t lds_total;
+    uint32_t lds_total;   // LDS per team
     uint32_t rm;          // coarse levels r - m
     uint32_t ntiles;      // k^(r-m)
     uint32_t Sc;          // s^(r-m)

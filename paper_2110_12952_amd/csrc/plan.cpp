@@ -171,7 +171,34 @@ static uint32_t box_pitch_bytes(uint32_t S) { return (S + 2 + 3) & ~3u; }
 static uint32_t box_alloc_bytes(uint32_t S) { return (S + 2) * box_pitch_bytes(S) + 8; }
 
 // LDS budget of the tile box: keeps several work-groups resident per CU.
-static const uint32_t kBoxBudget = 24 * 1024;
+static const uint32_t kBoxBudget = 32 * 1024;
+
+static uint32_t block_level(const Fractal &f, uint32_t m);
+
+// Part of the (S+2)-square box that the rule evaluation reads: rows below
+// `rows` and columns below `cols`.  Block b (side BS, level q) reads the BS+2
+// rows from Y*BS and two dwords per row from column (X*BS) & ~3, (X, Y) =
+// lambda_{m-q}(b).  Fractals whose members never reach the bottom or right
+// part of their square (e.g. every y digit in {0, 1}) get a shorter or
+// narrower box; halo cells outside it are never read and are not staged.
+static void box_extent(const Fractal &f, uint32_t m, uint32_t *rows, uint32_t *cols) {
+    const uint32_t q = block_level(f, m), BS = uint32_t(ipow64(f.s, q));
+    const uint64_t nb = ipow64(f.k, m - q);
+    uint32_t rmax = 0, cmax = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        int64_t X, Y;
+        lambda_levels(f, m - q, b, &X, &Y);
+        rmax = std::max(rmax, uint32_t(Y * BS + BS + 2));
+        cmax = std::max(cmax, uint32_t(((X * BS) & ~int64_t(3)) + 8));
+    }
+    *rows = rmax;
+    *cols = cmax;
+}
+static uint32_t trimmed_box_bytes(const Fractal &f, uint32_t m) {
+    uint32_t rows, cols;
+    box_extent(f, m, &rows, &cols);
+    return rows * ((cols + 3) & ~3u) + 8;
+}
 // Below this many tiles a smaller tile level is preferred for parallelism.
 static const uint64_t kMinTiles = 512;
 
@@ -181,8 +208,8 @@ static uint32_t block_level(const Fractal &f, uint32_t m) { return (f.s == 2 && 
 
 static bool fits_group(const Fractal &f, uint32_t m) {
     const uint64_t S = ipow64(f.s, m), K = ipow64(f.k, m);
-    return box_alloc_bytes(uint32_t(S)) <= kBoxBudget && K + 30 <= 2 * 16 * 256 &&
-           ipow64(f.k, m - block_level(f, m)) <= 4 * 256;
+    return S <= 250 && K + 30 <= 2 * 16 * 256 && ipow64(f.k, m - block_level(f, m)) <= 4 * 256 &&
+           trimmed_box_bytes(f, m) <= kBoxBudget;
 }
 
 uint32_t auto_tile_level(const Fractal &f) {
@@ -250,8 +277,12 @@ static uint64_t box_pitch_cost(const Fractal &f, uint32_t m, uint32_t q, uint32_
     return cost;
 }
 
-bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg) {
+bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg, uint32_t team) {
     *p = TilePlan();
+    if (team != 256 && team != 64) {
+        *msg = "team size must be 256 or 64";
+        return false;
+    }
     if (!tiled_supported(f)) {
         *msg = "the tiled step needs 2 <= s <= 4 and r >= 1";
         return false;
@@ -266,24 +297,28 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
         return false;
     }
     const uint32_t q = block_level(f, m);
-    // A work-group of 256 threads holds at most two 16-byte chunks, four halo
-    // cells and four blocks per thread.
+    // A team holds at most two 16-byte chunks, four halo cells and four
+    // blocks per thread.
     const uint64_t K = ipow64(f.k, m);
-    if (K + 30 > 2 * 16 * 256 || ipow64(f.k, m - q) > 4 * 256 || 4 * S + 4 > 4 * 256) {
-        *msg = "tile level too large for one work-group";
+    if (K + 30 > 2 * 16 * team || ipow64(f.k, m - q) > 4 * team) {
+        *msg = team == 256 ? "tile level too large for one work-group" : "tile level too large for one wavefront";
         return false;
     }
+    p->team = team;
     p->m = m;
     p->S = uint32_t(S);
     p->K = uint32_t(K);
-    // Box pitch: the multiple of 4 in [S+2, S+2+64) with the fewest modelled
-    // LDS bank conflicts whose box still fits the budget (the smallest pitch
-    // when none fits, as for large requested tile levels).
-    p->W = box_pitch_bytes(p->S);
+    uint32_t cols;
+    box_extent(f, m, &p->rows, &cols);
+    // Box pitch: the multiple of 4 in [cols, cols+64) with the fewest
+    // modelled LDS bank conflicts whose box still fits the budget (the
+    // smallest pitch when none fits, as for large requested tile levels).
+    p->W = (cols + 3) & ~3u;
     {
+        const uint32_t least = p->rows * p->W + 8;
         uint64_t best = box_pitch_cost(f, m, q, p->W);
         for (uint32_t W = p->W + 4; W < p->W + 64; W += 4) {
-            if ((p->S + 2) * W + 8 > std::max(kBoxBudget, box_alloc_bytes(p->S))) break;
+            if (p->rows * W + 8 > std::max(kBoxBudget, least)) break;
             const uint64_t c = box_pitch_cost(f, m, q, W);
             if (c < best) {
                 best = c;
@@ -295,7 +330,7 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->BS = uint32_t(ipow64(f.s, q));
     p->CB = uint32_t(ipow64(f.k, q));
     p->nblk = uint32_t(ipow64(f.k, m - q));
-    p->box_bytes = (p->S + 2) * p->W + 8;
+    p->box_bytes = p->rows * p->W + 8;
     p->slot_off = (p->box_bytes + 15) & ~15u;
     // one u16 slot per block (blocks past the last one, evaluated to keep
     // every thread on the same path, included), plus the slots a 16-cell
@@ -303,6 +338,10 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->nslot = 1 + (15 + p->CB - 1) / p->CB;
     const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
     p->lds_total = p->slot_off + uint32_t(((nblk_pad + p->nslot + 1) * 2 + 15) & ~uint64_t(15));
+    if (team == 64 && 4 * uint64_t(p->lds_total) > 65536) {
+        *msg = "four wavefront boxes do not fit 64 KiB of LDS";
+        return false;
+    }
     p->rm = f.r - m;
     p->ntiles = ipow64(f.k, p->rm);
     p->Sc = uint32_t(ipow64(f.s, p->rm));
@@ -313,7 +352,7 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
         p->lut0[i] = uint16_t((y + 1) * p->W + (x + 1));
     }
     p->lut0_stride = (p->K + 16 + 15) & ~15u;  // >= every 16-entry read of any phase
-    p->dummy = (p->S + 2) * p->W + 4;          // slack byte past every window read
+    p->dummy = p->rows * p->W + 4;             // slack byte past every window read
     p->lut0p.assign(size_t(16) * p->lut0_stride, uint16_t(p->dummy));
     for (uint32_t ph = 0; ph < 16; ++ph)
         for (uint32_t i = 0; i < p->K; ++i) p->lut0p[size_t(ph) * p->lut0_stride + i + ph] = p->lut0[i];
@@ -339,11 +378,16 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
                 lambda_levels(f, m, i, &x, &y);
                 int64_t tx = x + dx * Si, ty = y + dy * Si;
                 if (tx < -1 || ty < -1 || tx > Si || ty > Si) continue;
+                if (ty + 1 >= int64_t(p->rows) || tx + 1 >= int64_t(p->W)) continue;  // never read
                 p->halo_src.push_back((dir8 << 29) | i);
                 p->halo_dst.push_back(uint32_t((ty + 1) * p->W + (tx + 1)));
             }
             ++dir8;
         }
+    if (p->halo_src.size() > 4 * team) {
+        *msg = team == 256 ? "tile level too large for one work-group" : "tile level too large for one wavefront";
+        return false;
+    }
     // Neighbour tiles: the tiles' block corners are S * lambda_{r-m}(t); the
     // eight neighbours are nu_{r-m} of the neighbouring coarse coordinates
     // (section 3.1 at the coarse level), or none outside the fractal.

@@ -40,7 +40,9 @@ void build_map_tables(const Fractal &f, MapTables *t);
 
 struct TilePlan {
     bool ok = false;
+    uint32_t team = 256;  // threads per tile: 256 (work-group) or 64 (wavefront)
     uint32_t m = 0, S = 0, K = 0, W = 0, q = 0, BS = 0, CB = 0, nblk = 0;
+    uint32_t rows = 0;  // box rows read by the rule (<= S + 2)
     uint32_t box_bytes = 0, slot_off = 0, nslot = 0, lds_total = 0;
     uint32_t rm = 0, Sc = 0, lut0_stride = 0, dummy = 0;
     uint8_t bid[16];
@@ -55,8 +57,9 @@ struct TilePlan {
 bool tiled_supported(const Fractal &f);
 // Largest usable tile level, then reduced while fewer than `min_tiles` tiles.
 uint32_t auto_tile_level(const Fractal &f);
-// Builds the plan at tile level m (1 <= m <= r); false if it does not fit.
-bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg);
+// Builds the plan at tile level m (1 <= m <= r) for teams of `team` threads
+// per tile (256 or 64); false if it does not fit.
+bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg, uint32_t team = 256);
 
 // Matrix-core lambda: A (16 x 32*ktiles int8), see MfmaLambda in params.hpp.
 // ktiles == 0 when unsupported (r*k > 192 or n > 2^28).

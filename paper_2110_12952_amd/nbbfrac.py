@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nbbfrac.h")
 NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
 NBB_OUTSIDE = 0xFFFFFFFF
 NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
-STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE = 0, 1, 2, 3
 MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 
 
@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
     L.nbb_batch_query.restype = st
     L.nbb_batch_step.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
     L.nbb_batch_step.restype = st
+    L.nbb_batch_step_each.argtypes = [vp, vp, vp, u64, vp, u32, vp]
+    L.nbb_batch_step_each.restype = st
     L.nbb_bbox_pitch.argtypes = [vp]
     L.nbb_bbox_pitch.restype = u64
     L.nbb_last_error.restype = ctypes.c_char_p
@@ -316,8 +318,8 @@ def shared_descriptors(specs: Sequence[Tuple[int, Sequence[Tuple[int, int]], int
     for (s, offs, r), f in desc.items():
         big_r, big = top[(s, offs)]
         inf = big.info()
-        if inf.strategy == STRATEGY_TILED and f.info().strategy == STRATEGY_TILED:
-            f.configure(STRATEGY_TILED, min(r, int(inf.tile_level)))
+        if inf.strategy != STRATEGY_DIRECT and f.info().strategy != STRATEGY_DIRECT:
+            f.configure(int(inf.strategy), min(r, int(inf.tile_level)))
     return [desc[(int(s), tuple((int(a), int(b)) for a, b in o), int(r))] for s, o, r in specs]
 
 
@@ -387,3 +389,14 @@ class Batch:
         _check(lib().nbb_batch_step(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
                                     int(rule), ctypes.byref(res), _stream(stream)))
         return b if res.value else a
+
+    def step_each(self, a, b, steps: Sequence[int], rule: int = NBB_RULE_B3S23, stream=None) -> None:
+        """Instance i takes steps[i] generations; its result is in b iff steps[i] is odd."""
+        if a.numel() != b.numel():
+            raise ValueError("arenas differ in length")
+        n = len(self.fractals)
+        if len(steps) != n:
+            raise ValueError(f"expected {n} step counts")
+        arr = np.ascontiguousarray(steps, dtype=np.uint32) if n else np.zeros(1, np.uint32)
+        _check(lib().nbb_batch_step_each(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(),
+                                         arr.ctypes.data, int(rule), _stream(stream)))

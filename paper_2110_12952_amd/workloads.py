@@ -165,6 +165,63 @@ class BatchWorkload:
 BATCH512 = BatchWorkload("batch512", 512, 500, 2110, tuple(BATCH_LEVELS.items()))
 
 
+# Served workload: requests arrive as a Poisson process; each asks for one
+# automaton run on a fresh Bernoulli(p) state.  The fractal is uniform over
+# `fractals`; log10 of the cell count is uniform in [3, 8] and snapped to the
+# nearest level the fractal has among `levels`; the step count is
+# log-uniform in [10, 2000].
+SERVE_LEVELS = {"carpet": tuple(range(4, 9)), "hfractal": tuple(range(4, 10)),
+                "triangle": tuple(range(7, 17)), "chandelier": tuple(range(5, 14))}
+
+
+@dataclass(frozen=True)
+class Request:
+    rid: int
+    t: float            # arrival time, seconds from the start
+    fractal: FractalDef
+    r: int
+    steps: int
+    p: float
+    seed: int
+
+    @property
+    def cells(self) -> int:
+        return self.fractal.k ** self.r
+
+
+@dataclass(frozen=True)
+class ServeWorkload:
+    name: str
+    rate: float                      # mean arrivals per second
+    seconds: float                   # arrival window
+    fractals: Tuple[str, ...]
+    draw_seed: int
+    log10_cells: Tuple[float, float] = (3.0, 8.0)
+    steps: Tuple[int, int] = (10, 2000)
+    p: float = 0.5
+    rule: str = "B3/S23"
+
+    def requests(self, seconds: float = None) -> List[Request]:
+        seconds = self.seconds if seconds is None else seconds
+        rng = np.random.default_rng(self.draw_seed)
+        out, t, rid = [], 0.0, 0
+        while True:
+            t += float(rng.exponential(1.0 / self.rate))
+            if t >= seconds:
+                return out
+            fd = FRACTALS[self.fractals[int(rng.integers(len(self.fractals)))]]
+            u = float(rng.uniform(*self.log10_cells))
+            levels = SERVE_LEVELS[fd.name]
+            r = min(levels, key=lambda lv: abs(lv * np.log10(fd.k) - u))
+            lo, hi = np.log(self.steps[0]), np.log(self.steps[1])
+            steps = int(round(float(np.exp(rng.uniform(lo, hi)))))
+            out.append(Request(rid, t, fd, int(r), steps, self.p, rid))
+            rid += 1
+
+
+SERVE2000 = ServeWorkload("serve2000", 2000.0, 60.0, ("carpet", "hfractal"), 5)
+
+
 def random_offsets(rng: np.random.Generator, s: int, k: int) -> Offsets:
     """k distinct digit pairs in [0,s)^2 in random order (a random NBB fractal)."""
     cells = rng.choice(s * s, size=k, replace=False)

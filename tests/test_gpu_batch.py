@@ -89,12 +89,41 @@ def test_batch_mixed_vs_oracle(N, rule, steps):
     assert (host(a)[~inside] == 0xA5).all() and (host(b)[~inside] == 0x5A).all()
 
 
+@pytest.mark.parametrize("rule", ["B3/S23", "B1357/S02468"])
+def test_batch_wave_and_workgroup_plans_vs_oracle(N, rule):
+    # the same fractals once with one wavefront per tile and once with one
+    # work-group per tile, in one batch: separate groups, same results
+    specs = [("triangle", 5, 3), ("triangle", 8, 4), ("chandelier", 4, 3), ("carpet", 3, 2),
+             ("hfractal", 3, 3), ("grid4_12", 3, 2), ("cantor", 7, 3)]
+    frs, want = [], []
+    rm = W.rule_mask(rule)
+    for j, strategy in enumerate((N.STRATEGY_TILED_WAVE, N.STRATEGY_TILED)):
+        for i, (name, r, m) in enumerate(specs):
+            fd = W.FRACTALS[name]
+            f = N.Fractal(fd.s, fd.offsets, r)
+            f.configure(strategy, m)
+            assert f.info().strategy == strategy
+            frs.append(f)
+            o = O.Fractal(fd.s, fd.offsets, r)
+            want.append(o.compact_steps(o.init_compact(40 + i, 0.5), rm, 9))
+    batch = N.Batch(frs)
+    assert batch.info().groups == 2 * len(specs)
+    a, b = batch.new_arena(), batch.new_arena()
+    for idx, f in enumerate(frs):
+        f.init_compact(40 + idx % len(specs), 0.5, out=batch.state(a, idx))
+    got = host(batch.step(a, b, 9, rm))
+    for idx, f in enumerate(frs):
+        np.testing.assert_array_equal(got[batch.offsets[idx]:batch.offsets[idx] + f.cells], want[idx],
+                                      err_msg=f"instance {idx}")
+
+
 def test_batch_groups_by_plan(N):
     _, _, frs = _mixed(N, with_direct=False)
     inf = N.Batch(frs).info()
-    kinds = {(f.s, f.offsets, f.info().tile_level) for f in frs if f.info().strategy == N.STRATEGY_TILED}
+    tiled = [f for f in frs if f.info().strategy != N.STRATEGY_DIRECT]
+    kinds = {(f.s, f.offsets, f.info().tile_level, f.info().strategy) for f in tiled}
     assert inf.groups == len(kinds)
-    assert inf.tiles == sum(f.info().tiles for f in frs if f.info().strategy == N.STRATEGY_TILED)
+    assert inf.tiles == sum(f.info().tiles for f in tiled)
     assert inf.cells == sum(f.cells for f in frs)
 
 
@@ -211,7 +240,7 @@ def test_autotune_then_step_matches_oracle(N, name, r):
     a, b = f.new_compact(), f.new_compact()
     f.init_compact(3, 0.5, out=a)
     inf = f.autotune(a, b, steps=2)
-    assert inf.strategy in (N.STRATEGY_TILED, N.STRATEGY_DIRECT)
+    assert inf.strategy in (N.STRATEGY_TILED, N.STRATEGY_TILED_WAVE, N.STRATEGY_DIRECT)
     got = f.info()
     assert (got.strategy, got.tile_level) == (inf.strategy, inf.tile_level)
     s0 = f.init_compact(3, 0.5)

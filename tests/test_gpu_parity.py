@@ -185,18 +185,27 @@ def tile_levels(fd, r):
         except nbbfrac.NbbError:
             continue
         out.append(("tiled", m))
+        out.append(("wave", m))  # one wavefront per tile, where the tile fits one
     out.append(("direct", 0))
     return out
 
 
 def configure(N, g, how):
+    """Configure g; False if the plan does not fit (wavefront plans only)."""
     kind, m = how
     if kind == "auto":
         g.configure(N.STRATEGY_AUTO, 0)
     elif kind == "tiled":
         g.configure(N.STRATEGY_TILED, m)
+    elif kind == "wave":
+        try:
+            g.configure(N.STRATEGY_TILED_WAVE, m)
+        except N.NbbError:
+            return False
+        assert g.info().strategy == N.STRATEGY_TILED_WAVE
     else:
         g.configure(N.STRATEGY_DIRECT, 0)
+    return True
 
 
 @pytest.mark.parametrize("name,r", SMALL)
@@ -204,7 +213,8 @@ def test_step_compact_small(N, name, r):
     fd, o, g = pair(name, r, N)
     st0 = o.init_compact(77 + r, 0.45)
     for how in tile_levels(fd, r):
-        configure(N, g, how)
+        if not configure(N, g, how):
+            continue
         for rule in RULES:
             rm = W.rule_mask(rule)
             for steps in (1, 2, 7):
@@ -225,7 +235,8 @@ def test_step_compact_random_fractals(N, seed):
     g = N.Fractal(fd.s, fd.offsets, r)
     st0 = o.init_compact(seed, 0.5)
     for how in tile_levels(fd, r):
-        configure(N, g, how)
+        if not configure(N, g, how):
+            continue
         a = dev(st0)
         res = g.step_compact(a, torch.empty_like(a), 5, B3S23)
         np.testing.assert_array_equal(host(res), o.compact_steps(st0, B3S23, 5), err_msg=str((fd, r, how)))

@@ -96,7 +96,7 @@ def _plan_levels(name, r):
     f = W.FRACTALS[name]
     levels = [0]
     for m in range(1, r + 1):
-        if f.s ** m <= 250 and (f.s ** m + 2) * ((f.s ** m + 5) & ~3) + 8 <= 65535:
+        if f.s ** m <= 250:
             levels.append(m)
     return levels
 
@@ -107,9 +107,8 @@ def test_plan_tables_match_oracle(name, r):
     for m in _plan_levels(name, r):
         p = N.plan_tables(fd.s, fd.offsets, r, m)
         m = p["tile_level"]
-        S, Wp = p["tile_side"], p["box_pitch"]
+        S, Wp, rows = p["tile_side"], p["box_pitch"], p["box_rows"]
         assert S == fd.s ** m and p["tile_cells"] == fd.k ** m and p["tiles"] == fd.k ** (r - m)
-        assert Wp % 4 == 0 and Wp >= S + 2 and p["box_rows"] == S + 2
         fm = O.Fractal(fd.s, fd.offsets, m)
         xs, ys = fm.lam_many(np.arange(fm.cells))
         np.testing.assert_array_equal(p["lut0"], (ys + 1) * Wp + (xs + 1))
@@ -118,8 +117,13 @@ def test_plan_tables_match_oracle(name, r):
         fb = O.Fractal(fd.s, fd.offsets, m - q)
         bx, by = fb.lam_many(np.arange(fb.cells))
         np.testing.assert_array_equal(p["lut1"], by * BS * Wp + bx * BS)
+        # the box holds every block window (BS+2 rows from row Y*BS, two
+        # dwords per row from column (X*BS) & ~3) and nothing beyond
+        assert rows == (by * BS + BS + 2).max() and rows <= S + 2
+        assert Wp % 4 == 0 and Wp >= ((bx * BS) & ~3).max() + 8 and (ys + 2).max() <= rows
         # halo: every member of each neighbouring level-m copy that lands in
-        # the ring [-1, S]^2 around the tile, with its local index
+        # the ring [-1, S]^2 around the tile and inside the box, with its
+        # local index
         want = set()
         d8 = 0
         for dy in (-1, 0, 1):
@@ -128,7 +132,7 @@ def test_plan_tables_match_oracle(name, r):
                     continue
                 for i in range(fm.cells):
                     tx, ty = xs[i] + dx * S, ys[i] + dy * S
-                    if -1 <= tx <= S and -1 <= ty <= S:
+                    if -1 <= tx <= S and -1 <= ty <= S and ty + 1 < rows and tx + 1 < Wp:
                         assert fm.nu(xs[i], ys[i]) == i
                         want.add(((d8 << 29) | i, (ty + 1) * Wp + (tx + 1)))
                 d8 += 1
@@ -204,3 +208,78 @@ def test_batch_create_without_device_reports_device_error():
     assert L.nbb_batch_query(None, None) == N.NBB_E_INVALID
     L.nbb_batch_destroy(None)
     assert L.nbb_autotune(None, None, None, 0, 1, 0, None, None) == N.NBB_E_INVALID
+
+
+# ------------------------------------------------------ request-loop host logic --
+def test_arena_allocator_first_fit_and_merge():
+    from paper_2110_12952_amd.serve import ArenaAllocator
+    a = ArenaAllocator(1000)          # rounded down to 992
+    assert a.capacity == 992
+    x = a.alloc(10)
+    y = a.alloc(17)
+    z = a.alloc(100)
+    assert (x, y, z) == (0, 16, 48) and a.used_bytes == 16 + 32 + 112
+    a.free(y)
+    assert a.alloc(16) == 16            # first fit reuses the hole
+    a.free(16)
+    a.free(x)
+    a.free(z)
+    a.check()
+    assert a.alloc(992) == 0 and a.alloc(1) is None
+
+
+def test_arena_allocator_random_churn():
+    from paper_2110_12952_amd.serve import ArenaAllocator
+    rng = np.random.default_rng(3)
+    a = ArenaAllocator(1 << 16)
+    live = {}
+    for it in range(3000):
+        if live and rng.random() < 0.45:
+            off = list(live)[int(rng.integers(len(live)))]
+            a.free(off)
+            del live[off]
+        else:
+            n = int(rng.integers(1, 3000))
+            off = a.alloc(n)
+            if off is not None:
+                assert off % 16 == 0 and off + n <= a.capacity
+                for o, m in live.items():
+                    assert off + n <= o or o + m <= off
+                live[off] = n
+        if it % 100 == 0:
+            a.check()
+    for off in list(live):
+        a.free(off)
+    a.check()
+    assert a.used_bytes == 0 and a.alloc(a.capacity) == 0
+
+
+def test_plan_round():
+    from paper_2110_12952_amd.serve import plan_round
+    order, G = plan_round([5, 50, 20], [100, 100, 100], 3000, 64)
+    assert order == [1, 2, 0] and G == 10
+    assert plan_round([5, 50], [100, 100], 1e9, 64)[1] == 50        # capped by the largest remaining
+    assert plan_round([500, 500], [100, 100], 1e9, 64)[1] == 64     # and by max_gens
+    assert plan_round([500], [10 ** 9], 10, 64)[1] == 1             # at least one generation
+
+
+def test_serve_workload_requests():
+    wl = W.SERVE2000
+    rq = wl.requests(5.0)
+    assert rq == wl.requests(5.0)
+    n = len(rq)
+    assert abs(n - 5.0 * wl.rate) < 5 * np.sqrt(5.0 * wl.rate)       # Poisson count
+    ts = np.array([q.t for q in rq])
+    assert (np.diff(ts) > 0).all() and ts[-1] < 5.0
+    gaps = np.diff(ts)
+    assert abs(gaps.mean() * wl.rate - 1) < 0.05
+    for q in rq[:2000]:
+        assert q.fractal.name in wl.fractals and q.r in W.SERVE_LEVELS[q.fractal.name]
+        assert 10 <= q.steps <= 2000 and q.p == 0.5 and q.seed == q.rid
+    # snapping: every level of each fractal is reachable, and a level is the
+    # nearest one to log10 of its cell count
+    got = {(q.fractal.name, q.r) for q in rq}
+    assert {(f, r) for f in wl.fractals for r in W.SERVE_LEVELS[f]
+            if 3 - 0.5 <= r * np.log10(W.FRACTALS[f].k) <= 8 + 0.5} <= got
+    st = np.log(np.array([q.steps for q in rq]))
+    assert abs(st.mean() - (np.log(10) + np.log(2000)) / 2) < 0.05
