@@ -181,11 +181,12 @@ nbb_status upload_maps(nbb_fractal *F) {
 }
 
 nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TileParams *T) {
-    const void *src[5] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data()};
-    size_t bytes[5] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
-                       p.nbr.size() * 4};
-    void *dst[5];
-    nbb_status s = upload(blob, src, bytes, 5, dst);
+    const void *src[6] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data(),
+                          p.plut.data()};
+    size_t bytes[6] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
+                       p.nbr.size() * 4, p.plut.size() * 2};
+    void *dst[6];
+    nbb_status s = upload(blob, src, bytes, 6, dst);
     if (s != NBB_OK) return s;
     *T = TileParams{};
     T->team = p.team;
@@ -215,6 +216,7 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->halo_src = static_cast<const uint32_t *>(dst[2]);
     T->halo_dst = static_cast<const uint32_t *>(dst[3]);
     T->nbr = static_cast<const uint32_t *>(dst[4]);
+    T->plut = static_cast<const uint16_t *>(dst[5]);
     std::memcpy(T->bid, p.bid, sizeof(T->bid));
     return NBB_OK;
 }

@@ -481,15 +481,44 @@ __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t
     }
 }
 
+// The rule as two byte tables for v_perm: byte c of born (c = 0..7) is the
+// birth bit for c live neighbours, byte c of surv the survival bit; counts
+// 0-3 sit in the low dword, 4-7 in the high one.  A count of 8 selects a sign
+// byte of the table (0, as every table byte is 0 or 1), so the tables serve
+// exactly the rules without birth or survival at 8 (`perm`).
+struct RuleTables {
+    uint32_t born_lo, born_hi, surv_lo, surv_hi;
+    bool perm;
+};
+__device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
+    RuleTables t{0, 0, 0, 0, (rule & ((1u << 8) | (1u << 24))) == 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        t.born_lo |= ((rule >> c) & 1u) << (8 * c);
+        t.born_hi |= ((rule >> (c + 4)) & 1u) << (8 * c);
+        t.surv_lo |= ((rule >> (c + 16)) & 1u) << (8 * c);
+        t.surv_hi |= ((rule >> (c + 20)) & 1u) << (8 * c);
+    }
+    return t;
+}
+
 // Next states of one block (BS x BS square, CB cells consecutive in compact
 // order) as a CB-bit mask in compact order.  The window is BS+2 rows of the
 // LDS box starting one row up and one column left of the block, read as two
 // dwords per row; byte c of H is the 3-sum of window columns c..c+2, byte c of
-// V the 3x3 sum around block column c (self included), and V + 15 * self =
-// live neighbours + 16 * self indexes the rule word.
+// V the 3x3 sum around block column c (self included).
+//   4 x 4 blocks, perm rules: per block row, N = V - self gives four
+//   neighbour counts, two v_perm look up the birth and survival bytes of all
+//   four at once, self picks between them, and v_dot4 packs the row's bytes
+//   into four bits of a position mask; plut (LDS) turns the position mask
+//   into compact order.
+//   otherwise: V + 15 * self = live neighbours + 16 * self indexes the rule
+//   word bit by bit for every position (member positions only survive the
+//   final mask); for 3 x 3 blocks this is as fast and needs no table.
 template <int BS>
 __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32_t *box32, uint32_t W4,
-                                               uint32_t base, uint32_t rule) {
+                                               uint32_t base, uint32_t rule, const RuleTables &RT,
+                                               const uint16_t *plut) {
     const uint32_t a0 = base >> 2, sh = base & 3;
     uint32_t lo[BS + 2], hi[BS + 2], C[BS + 2], H[BS + 2];
 #pragma unroll
@@ -510,6 +539,23 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
             H[rr] = lo[rr] + C[rr] + alignbyte(hi[rr], lo[rr], 2);
         }
     }
+    if (BS == 4 && RT.perm) {
+        // weights of the block's columns in the packed row (bytes past BS dropped)
+        constexpr uint32_t kWeights = BS == 4 ? 0x08040201u : BS == 3 ? 0x00040201u : 0x00000201u;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int rr = 0; rr < BS; ++rr) {
+            const uint32_t self = C[rr + 1];
+            const uint32_t n = H[rr] + H[rr + 1] + H[rr + 2] - self;   // live neighbours, 0..8 per byte
+            const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
+            const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
+            const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, self);  // 0xFF where alive
+            const uint32_t next = (born & ~smask) | (surv & smask);
+            pos |= __builtin_amdgcn_udot4(next, kWeights, 0u, false) << (BS * rr);
+        }
+        if (BS == 4) return uint32_t(plut[pos & 0xFFu]) | uint32_t(plut[256 + (pos >> 8)]);
+        return plut[pos];
+    }
     uint32_t bits = 0;
 #pragma unroll
     for (int rr = 0; rr < BS; ++rr) {
@@ -519,24 +565,14 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
         for (int cc = 0; cc < BS; ++cc) {
             // v_bfe takes its offset from the low 5 bits of the operand, and
             // byte cc of I (<= 24) is exactly those bits of I >> 8cc.
+            // Positions outside the fractal carry id 31, a bit dropped below.
             const uint32_t id = T.bid[cc + BS * rr];
-#if NBB_MEMBER_BRANCH
-            if (id != 0xFFu) {
-                asm volatile("" ::: "memory");
-                bits |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << id;
-            }
-#else
-            // positions outside the fractal carry id 31, a bit dropped below
             bits |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << (id & 31u);
-#endif
         }
     }
     return bits & T.cbmask;
 }
 
-#ifndef NBB_MEMBER_BRANCH
-#define NBB_MEMBER_BRANCH 0
-#endif
 #ifndef NBB_TILED_WAVES_PER_SIMD
 #define NBB_TILED_WAVES_PER_SIMD 1
 #endif
@@ -607,6 +643,12 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
     for (uint32_t o = threadIdx.x * 16; o < kTeams * T.lds_total; o += 256 * 16)
         *reinterpret_cast<uint4 *>(lds_all + o) = make_uint4(0, 0, 0, 0);
+    // the position-mask table (4 x 4 blocks only), shared by the teams,
+    // after their regions
+    uint16_t *plut = reinterpret_cast<uint16_t *>(lds_all + kTeams * T.lds_total);
+    if (BS == 4)
+        for (uint32_t e = threadIdx.x; e < kPlutEntries; e += 256) plut[e] = T.plut[e];
+    const RuleTables RT = rule_tables(rule);
     uint32_t hsrc[HPT], hdst[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
@@ -694,7 +736,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
             if (tid + TEAM * j < T.nblk)  // waves with no block left skip the work
-                slots[tid + TEAM * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule));
+                slots[tid + TEAM * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule, RT, plut));
         team_sync<TEAM>();
 
         // 4. slots -> 16 next states per chunk -> bytes -> global; the two
@@ -707,10 +749,20 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t lo = 16 * c > ph ? 16 * c - ph : 0u;  // first local cell in the chunk
                 const uint32_t a0 = udiv(T.divCB, lo);
                 const uint32_t r0 = lo - a0 * T.CB;
-                uint32_t acc = uint32_t(slots[a0]) >> r0;
-                uint32_t sh = T.CB - r0;
-                for (uint32_t e = 1; e < T.nslot; ++e, sh += T.CB)
-                    if (sh < 16) acc |= uint32_t(slots[a0 + e]) << sh;
+                uint32_t acc;
+                if (T.nslot <= 4) {
+                    // four independent reads (the slot row is padded past the
+                    // last block), no loop: the usual case, CB >= 5
+                    const uint32_t s0 = slots[a0], s1 = slots[a0 + 1], s2 = slots[a0 + 2], s3 = slots[a0 + 3];
+                    const uint32_t h1 = T.CB - r0, h2 = h1 + T.CB, h3 = h2 + T.CB;
+                    acc = (s0 >> r0) | (h1 < 16 ? s1 << h1 : 0u) | (h2 < 16 ? s2 << h2 : 0u) |
+                          (h3 < 16 ? s3 << h3 : 0u);
+                } else {
+                    acc = uint32_t(slots[a0]) >> r0;
+                    uint32_t sh = T.CB - r0;
+                    for (uint32_t e = 1; e < T.nslot; ++e, sh += T.CB)
+                        if (sh < 16) acc |= uint32_t(slots[a0 + e]) << sh;
+                }
                 const uint32_t m16 = (acc << (lo + ph - 16 * c)) & 0xFFFFu;
                 const uint4 v = make_uint4(nibble_to_bytes(m16 & 0xFu), nibble_to_bytes((m16 >> 4) & 0xFu),
                                            nibble_to_bytes((m16 >> 8) & 0xFu), nibble_to_bytes(m16 >> 12));
@@ -868,7 +920,7 @@ template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     constexpr uint32_t kTeams = 256 / TEAM;
-    const size_t lds = size_t(kTeams) * T.lds_total;
+    const size_t lds = size_t(kTeams) * T.lds_total + (BS == 4 ? kPlutEntries * sizeof(uint16_t) : 0);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>, 256, lds);

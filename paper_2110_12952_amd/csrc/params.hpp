@@ -82,6 +82,8 @@ struct TileParams {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;     // 8 neighbour tiles per tile (0xFFFFFFFF = none)
+    const uint16_t *plut;    // kPlutEntries: block position mask -> the block's next-state bits in
+                             // compact order (BS = 4: two tables of 256, rows 0-1 and rows 2-3)
     uint8_t bid[16];      // position c + BS*row inside a block -> cell id in the block, 0xFF if none
                           // (the kernel reads 0xFF & 31 = 31: a bit outside cbmask)
 };
@@ -96,6 +98,8 @@ struct BatchInstance {
     uint32_t ntiles;
     uint32_t tail_partial;  // 1 if k^r is not a multiple of 16
 };
+
+constexpr uint32_t kPlutEntries = 512;
 
 // The bounding-box step.  Membership splits into the low L levels (an
 // SL x SL bitmap, SL = s^L, one row of LW words per y) and the high r - L

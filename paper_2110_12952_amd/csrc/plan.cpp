@@ -337,7 +337,9 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     // chunk at the end of the tile may read past them.
     p->nslot = 1 + (15 + p->CB - 1) / p->CB;
     const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
-    p->lds_total = p->slot_off + uint32_t(((nblk_pad + p->nslot + 1) * 2 + 15) & ~uint64_t(15));
+    // (at least four past the last block: the store phase reads four slots
+    // unconditionally when nslot <= 4)
+    p->lds_total = p->slot_off + uint32_t(((nblk_pad + std::max(p->nslot, 4u) + 1) * 2 + 15) & ~uint64_t(15));
     if (team == 64 && 4 * uint64_t(p->lds_total) > 65536) {
         *msg = "four wavefront boxes do not fit 64 KiB of LDS";
         return false;
@@ -368,6 +370,25 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
             int64_t v = nu_levels(f, q, c, rr);
             if (v >= 0) p->bid[c + p->BS * rr] = uint8_t(v);
         }
+    // Position mask -> compact bits.  Bit c + BS*row of a position mask is the
+    // next state at column c, row `row` of a block; the table ORs in bit
+    // bid[...] of each set member position.  For BS = 4 the 16-bit mask is
+    // looked up as two bytes (rows 0-1 at entries 0-255, rows 2-3 at 256-511).
+    p->plut.assign(kPlutEntries, 0);
+    {
+        const uint32_t npos = p->BS * p->BS;
+        const uint32_t span = p->BS == 4 ? 8 : npos;  // positions per table
+        const uint32_t ntab = p->BS == 4 ? 2 : 1;
+        for (uint32_t tab = 0; tab < ntab; ++tab)
+            for (uint32_t v = 0; v < (1u << span); ++v) {
+                uint16_t bits = 0;
+                for (uint32_t j = 0; j < span; ++j) {
+                    const uint32_t pos = tab * span + j;
+                    if ((v >> j & 1) && pos < npos && p->bid[pos] != 0xFF) bits |= uint16_t(1u << p->bid[pos]);
+                }
+                p->plut[tab * 256 + v] = bits;
+            }
+    }
     const int64_t Si = p->S;
     uint32_t dir8 = 0;
     for (int dy = -1; dy <= 1; ++dy)

@@ -46,6 +46,7 @@ struct TilePlan {
     uint32_t box_bytes = 0, slot_off = 0, nslot = 0, lds_total = 0;
     uint32_t rm = 0, Sc = 0, lut0_stride = 0, dummy = 0;
     uint8_t bid[16];
+    std::vector<uint16_t> plut;   // kPlutEntries, see TileParams::plut
     uint64_t ntiles = 0;
     std::vector<uint16_t> lut0;   // phase 0, K entries
     std::vector<uint16_t> lut0p;  // 16 phase copies
