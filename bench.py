@@ -238,7 +238,17 @@ def main():
         if Kb == K:
             parity = bool(torch.equal(g.gather(resb), res))
             log(f"compact == gathered box after {K} steps: {parity}")
-        del box, box2, resb
+        # the paper's lambda approach on the same box (threads over fractal cells)
+        Kl = min(Kb, 50)
+        box = g.init_bbox(wl.seeds[0], wl.p)
+        ref = g.step_bbox(box.clone(), box2, Kl, rule).clone()
+        msl, resl = time_events(torch, lambda: g.step_lambda(box, box2, Kl, rule))
+        bbox["lambda_approach"] = {"ms_per_step": msl / Kl, "steps": Kl,
+                                   "cell_updates_per_s": g.cells * Kl / (msl * 1e-3),
+                                   "equals_box_step": bool(torch.equal(resl, ref))}
+        log(f"lambda approach: {msl / Kl * 1e3:.1f} us/step, same as box step: "
+            f"{bbox['lambda_approach']['equals_box_step']}")
+        del box, box2, resb, ref, resl
 
     # ---- maps ---------------------------------------------------------------
     x = torch.empty(g.cells, dtype=torch.int32, device="cuda")

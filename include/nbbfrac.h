@@ -187,6 +187,18 @@ nbb_status nbb_step_bbox(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t 
                          uint64_t len, uint32_t steps, uint32_t rule, int *result_in_b,
                          void *stream);
 
+/*
+ * The paper's lambda approach (section 4, second method): the same
+ * generations on the box layout, but with one thread per fractal cell, which
+ * finds its box position with lambda and reads its neighbours from the box
+ * directly.  Arguments, result buffer and errors as nbb_step_bbox; the input
+ * must hold 0 at non-members and padding, and b is cleared once per call
+ * (steps >= 1) so that its non-members hold 0 too.
+ */
+nbb_status nbb_step_lambda(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t pitch,
+                           uint64_t len, uint32_t steps, uint32_t rule, int *result_in_b,
+                           void *stream);
+
 /* bbox[lambda(i)] = compact[i]; every other box byte becomes 0. */
 nbb_status nbb_expand(const nbb_fractal *f, const uint8_t *compact, uint8_t *bbox, uint64_t pitch,
                       uint64_t len, void *stream);

@@ -272,6 +272,31 @@ void orc_cells_after(const orc_fractal *f, const uint8_t *in, const int64_t *idx
     for (int64_t t = 0; t < count; ++t) out[t] = orc_cell_after(f, in, idx[t], rule, steps);
 }
 
+/* The same light cone with the initial state of each cell taken from its
+ * definition (member, SplitMix64 key y*n + x below the threshold) instead of
+ * an array: for levels whose whole state is too large to build on the host. */
+static uint8_t orc_cell_after_seeded(const orc_fractal *f, uint64_t seed, uint32_t thr, int64_t i, uint32_t rule,
+                                     int steps) {
+    int64_t x, y;
+    orc_lambda(f, i, &x, &y);
+    if (steps == 0) return (uint8_t)orc_alive_at(f, x, y, seed, thr);
+    int64_t live = 0;
+    for (int64_t dy = -1; dy <= 1; ++dy)
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            int64_t j = orc_nu(f, x + dx, y + dy);
+            if (j != ORC_OUTSIDE && orc_cell_after_seeded(f, seed, thr, j, rule, steps - 1)) ++live;
+        }
+    return orc_apply_rule(rule, live, orc_cell_after_seeded(f, seed, thr, i, rule, steps - 1) != 0);
+}
+
+void orc_cells_after_seeded(const orc_fractal *f, uint64_t seed, double p, const int64_t *idx, int64_t count,
+                            uint32_t rule, int steps, uint8_t *out) {
+    uint32_t thr = orc_threshold(p);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < count; ++t) out[t] = orc_cell_after_seeded(f, seed, thr, idx[t], rule, steps);
+}
+
 /* compact[i] = bbox[lambda(i)] */
 void orc_gather(const orc_fractal *f, const uint8_t *bbox, uint8_t *compact) {
 #pragma omp parallel for schedule(static)

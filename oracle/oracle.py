@@ -52,6 +52,7 @@ def lib():
         L.orc_lambda_many.argtypes = [vp, vp, i64, vp, vp]
         L.orc_nu_many.argtypes = [vp, vp, vp, i64, vp]
         L.orc_cells_after.argtypes = [vp, vp, vp, i64, u32, ctypes.c_int, vp]
+        L.orc_cells_after_seeded.argtypes = [vp, u64, dbl, vp, i64, u32, ctypes.c_int, vp]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -178,6 +179,18 @@ class Fractal:
             raise IndexError("index out of range")
         out = np.empty(idx.size, dtype=np.uint8)
         lib().orc_cells_after(self._h, _ptr(st), _ptr(idx), idx.size, int(rule), int(steps), _ptr(out))
+        return out
+
+    def cells_after_seeded(self, seed: int, p: float, idx, rule: int, steps: int) -> np.ndarray:
+        """As cells_after, from the Bernoulli(p) initial state of `seed`,
+        evaluated per cell (no whole-state array; steps <= 3)."""
+        assert 0 <= steps <= 3
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        if idx.size and (idx.min() < 0 or idx.max() >= self.cells):
+            raise IndexError("index out of range")
+        out = np.empty(idx.size, dtype=np.uint8)
+        lib().orc_cells_after_seeded(self._h, seed & (2 ** 64 - 1), float(p), _ptr(idx), idx.size, int(rule),
+                                     int(steps), _ptr(out))
         return out
 
     def compact_steps(self, state: np.ndarray, rule: int, steps: int) -> np.ndarray:

@@ -903,6 +903,32 @@ nbb_status nbb_step_bbox(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t 
     return NBB_OK;
 }
 
+nbb_status nbb_step_lambda(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t pitch, uint64_t len,
+                           uint32_t steps, uint32_t rule, int *result_in_b, void *stream) {
+    if (!F || !b) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_box_args(F, a, pitch, len);
+    if (st != NBB_OK) return st;
+    if (!aligned16(b)) return fail(NBB_E_INVALID, "box state must be 16-byte aligned");
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (result_in_b) *result_in_b = int(steps & 1);
+    if (steps == 0) return NBB_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // only fractal cells are written: b's other cells must start at 0
+    hipError_t e = launch_fill_zero(b, len, s);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    const int grid = map_grid(F, F->f.cells);
+    uint8_t *in = a, *out = b;
+    for (uint32_t i = 0; i < steps; ++i) {
+        e = launch_step_lambda(F->mp, F->lam_words, in, out, pitch, rule, grid, s);
+        if (e != hipSuccess) return hip_fail(e, "lambda step launch");
+        std::swap(in, out);
+    }
+    return NBB_OK;
+}
+
 nbb_status nbb_expand(const nbb_fractal *F, const uint8_t *compact, uint8_t *bbox, uint64_t pitch, uint64_t len,
                       void *stream) {
     if (!F || !compact) return fail(NBB_E_INVALID, "null argument");

@@ -432,6 +432,38 @@ __global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_w
     }
 }
 
+// The lambda approach (section 4, second method): threads run over the
+// compact cells but the state lives in the box.  Cell i finds (x, y) =
+// lambda(i) and reads its 3 x 3 neighbourhood straight from the box; cells
+// outside the fractal hold 0 there, so no nu is needed.  Box cells that are
+// not fractal cells are never written.
+__global__ __launch_bounds__(512) void k_step_lambda(MapParams P, uint32_t lam_words,
+                                                     const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                                     uint64_t pitch, uint32_t rule) {
+    extern __shared__ __align__(16) uint32_t smem_l[];
+    load_map_tables(P, lam_words, 0, smem_l, nullptr);
+    const uint64_t cells = uint64_t(P.cells_m1) + 1;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        uint32_t x, y;
+        lam_lut(P, smem_l, uint32_t(i), x, y);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const uint32_t yy = y + dy;
+            if (yy >= P.n) continue;  // above row 0 wraps to a huge value
+            const uint8_t *row = in + uint64_t(yy) * pitch;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const uint32_t xx = x + dx;
+                if (xx < P.n) sum += row[xx];
+            }
+        }
+        const uint32_t self = in[uint64_t(y) * pitch + x];
+        out[uint64_t(y) * pitch + x] = uint8_t((rule >> (sum - self + 16 * self)) & 1u);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Compact step, tiled: the kernel and its helpers (the kernel's comment
 // describes the scheme).
@@ -912,6 +944,12 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
                               uint8_t *out, uint32_t rule, int grid, hipStream_t st) {
     const size_t lds = size_t(lam_words) * 4 + size_t(nu_halves) * 2;
     hipLaunchKernelGGL(k_step_direct, dim3(grid), dim3(512), lds, st, P, lam_words, nu_halves, in, out, rule);
+    return hipGetLastError();
+}
+hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint8_t *in, uint8_t *out,
+                              uint64_t pitch, uint32_t rule, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_lambda, dim3(grid), dim3(512), size_t(lam_words) * 4, st, P, lam_words, in, out,
+                       pitch, rule);
     return hipGetLastError();
 }
 // Persistent launch: as many work-groups as can be resident at once (the

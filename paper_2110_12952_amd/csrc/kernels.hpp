@@ -27,6 +27,8 @@ hipError_t launch_gather(const MapParams &P, uint32_t lam_words, const uint8_t *
                          uint8_t *compact, int grid, hipStream_t st);
 hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t nu_halves, const uint8_t *in,
                               uint8_t *out, uint32_t rule, int grid, hipStream_t st);
+hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint8_t *in, uint8_t *out,
+                              uint64_t pitch, uint32_t rule, int grid, hipStream_t st);
 // Persistent launch sized to the resident capacity of cu_count CUs.
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                              uint32_t rule, int cu_count, hipStream_t st);

@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.nbb_step_compact.restype = st
     L.nbb_step_bbox.argtypes = [vp, vp, vp, u64, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
     L.nbb_step_bbox.restype = st
+    L.nbb_step_lambda.argtypes = [vp, vp, vp, u64, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_step_lambda.restype = st
     L.nbb_expand.argtypes = [vp, vp, vp, u64, u64, vp]
     L.nbb_expand.restype = st
     L.nbb_gather.argtypes = [vp, vp, u64, vp, u64, vp]
@@ -286,6 +288,14 @@ class Fractal:
         pitch = a.shape[-1]
         _check(lib().nbb_step_bbox(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), pitch, a.numel(),
                                    int(steps), int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a
+
+    def step_lambda(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        """The lambda approach on box buffers (threads over fractal cells)."""
+        res = ctypes.c_int(0)
+        pitch = a.shape[-1]
+        _check(lib().nbb_step_lambda(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), pitch, a.numel(),
+                                     int(steps), int(rule), ctypes.byref(res), _stream(stream)))
         return b if res.value else a
 
     def expand(self, compact, out=None, stream=None):

@@ -288,6 +288,33 @@ def test_step_bbox_small(N, name, r):
                                           err_msg=f"{name} r={r} {rule} steps={steps}")
 
 
+@pytest.mark.parametrize("name,r", SMALL)
+def test_step_lambda_small(N, name, r):
+    # the lambda approach (threads over fractal cells, state in the box)
+    fd, o, g = pair(name, r, N)
+    st0 = o.init_bbox(91 + r, 0.45)
+    for rule in RULES:
+        rm = W.rule_mask(rule)
+        for steps in (1, 2, 7):
+            a = g.init_bbox(91 + r, 0.45)
+            res = g.step_lambda(a, torch.full_like(a, 0x5A), steps, rm)
+            np.testing.assert_array_equal(box_view(g, res), o.bbox_steps(st0, rm, steps),
+                                          err_msg=f"{name} r={r} {rule} steps={steps}")
+
+
+def test_step_lambda_matches_box_step(N):
+    fd, o, g = pair("hfractal", 5, N)
+    pitch = g.pitch + 32
+    a = torch.empty((o.n, pitch), dtype=torch.uint8, device="cuda")
+    g.init_bbox(6, 0.5, out=a)
+    want = g.step_bbox(a.clone(), torch.empty_like(a), 9)
+    got = g.step_lambda(a.clone(), torch.full_like(a, 1), 9)
+    assert torch.equal(got, want)
+    assert g.step_lambda(a, torch.empty_like(a), 0) is a
+    with pytest.raises(N.NbbError):
+        g.step_lambda(a, a, 1)
+
+
 def test_step_bbox_wider_pitch(N):
     fd, o, g = pair("hfractal", 4, N)
     pitch = g.pitch + 48
@@ -374,3 +401,27 @@ def test_long_runs_against_oracle(N, name, r, steps):
         a = dev(st0)
         res = g.step_compact(a, torch.empty_like(a), steps)
         np.testing.assert_array_equal(host(res), want, err_msg=f"{name} r={r} repeat {rep}")
+
+
+def test_triangle_r20_compact(N):
+    # the paper's largest level: triangle r = 20 (3,486,784,401 cells, n =
+    # 2^20; its box, 2^40 bytes, cannot exist).  Sampled cells against the
+    # oracle's light cone from the seeded initial state, and the tiled step
+    # against the per-cell step over the whole state.
+    fd = W.TRIANGLE
+    o = O.Fractal(fd.s, fd.offsets, 20)
+    g = N.Fractal(fd.s, fd.offsets, 20)
+    assert g.cells == 3 ** 20 and g.info().strategy == N.STRATEGY_TILED
+    a = g.init_compact(20, 0.3)
+    samp = np.unique(np.concatenate([W.random_indices(5, 4000, g.cells).astype(np.int64),
+                                     np.array([0, 1, g.cells - 2, g.cells - 1], np.int64)]))
+    sidx = torch.from_numpy(samp).cuda()
+    np.testing.assert_array_equal(host(a[sidx]), o.cells_after_seeded(20, 0.3, samp, B3S23, 0))
+    b = torch.empty_like(a)
+    res = g.step_compact(a.clone(), b, 2)
+    np.testing.assert_array_equal(host(res[sidx]), o.cells_after_seeded(20, 0.3, samp, B3S23, 2))
+    tiled = res.clone()
+    del res
+    g.configure(N.STRATEGY_DIRECT)
+    res = g.step_compact(a, b, 2)
+    assert torch.equal(res, tiled)

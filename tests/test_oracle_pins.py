@@ -411,3 +411,17 @@ def test_cells_after_matches_full_steps(name):
     for steps in (0, 1, 2, 3):
         np.testing.assert_array_equal(f.cells_after(st, idx, B3S23, steps),
                                       f.compact_steps(st, B3S23, steps)[idx])
+
+
+@pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier"])
+def test_cells_after_seeded_matches_full_steps(name):
+    # the per-cell initial state is the whole-state init read at that cell,
+    # and the light cone from it matches whole-state generations
+    f = frac(name, min(max_level(name), 5))
+    st = f.init_compact(77, 0.4)
+    idx = np.arange(0, f.cells, max(1, f.cells // 300))
+    for steps in (0, 1, 2, 3):
+        np.testing.assert_array_equal(f.cells_after_seeded(77, 0.4, idx, B3S23, steps),
+                                      f.compact_steps(st, B3S23, steps)[idx])
+    with pytest.raises(IndexError):
+        f.cells_after_seeded(77, 0.4, [f.cells], B3S23, 1)
