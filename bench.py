@@ -85,6 +85,48 @@ def cpu_baseline(W, wl, seconds):
                       f"the full {o.cells}-cell state, {t:.1f} s"}
 
 
+def small_case(torch, N, W, rule):
+    """Triangle r = 10 (59,049 cells), 100 generations: one launch per
+    generation is launch-bound, so the same 100 launches are also captured
+    in a HIP graph and replayed.  Also times the initial-state kernel."""
+    wl = W.SMALL_TRIANGLE
+    fd = wl.fractal
+    g = N.Fractal(fd.s, fd.offsets, wl.r)
+    a0 = g.init_compact(wl.seeds[0], wl.p)
+    a, b = a0.clone(), torch.empty_like(a0)
+    T = wl.steps
+    g.step_compact(a, b, 2, rule)
+    ms_eager, res = time_events(torch, lambda: g.step_compact(a, b, T, rule))
+    eager = res.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.step_compact(a, b, 2, rule)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    a.copy_(a0)
+    with torch.cuda.graph(graph):
+        gres = g.step_compact(a, b, T, rule)
+    a.copy_(a0)
+    graph.replay()
+    a.copy_(a0)
+    ms_graph, _ = time_events(torch, graph.replay)
+    same = bool(torch.equal(gres, eager))
+    # the initial-state kernel on the large triangle (1 byte written per cell)
+    big = W.LARGE_TRIANGLE
+    gb = N.Fractal(big.fractal.s, big.fractal.offsets, big.r)
+    st = gb.new_compact()
+    gb.init_compact(big.seeds[0], big.p, out=st)
+    ms_init, _ = time_events(torch, lambda: gb.init_compact(big.seeds[0], big.p, out=st), 10)
+    out = {"cells": g.cells, "steps": T, "eager_us_per_step": ms_eager / T * 1e3,
+           "graph_us_per_step": ms_graph / T * 1e3, "graph_equals_eager": same,
+           "init_triangle_r16_us": ms_init / 10 * 1e3,
+           "init_triangle_r16_gbps": gb.cells / (ms_init / 10 * 1e-3) / 1e9}
+    log(f"small triangle r10: eager {out['eager_us_per_step']:.2f} us/step, graph "
+        f"{out['graph_us_per_step']:.2f} us/step, same={same}; init r16 {out['init_triangle_r16_us']:.1f} us")
+    return out
+
+
 def batch_run(torch, N, W, args):
     """The 512-instance batched workload: all instances stepped together, one
     launch per fractal group per generation, against one launch per instance
@@ -250,6 +292,9 @@ def main():
             f"{bbox['lambda_approach']['equals_box_step']}")
         del box, box2, resb, ref, resl
 
+    # ---- the small case: launch-bound, eager launches against a HIP graph ------
+    small = small_case(torch, N, W, rule)
+
     # ---- maps ---------------------------------------------------------------
     x = torch.empty(g.cells, dtype=torch.int32, device="cuda")
     y = torch.empty_like(x)
@@ -318,6 +363,7 @@ def main():
         "compact_equals_bbox": parity,
         "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
         "maps": maps,
+        "small_triangle_r10": small,
         "batch": batch,
         "serve": serve,
     }

@@ -181,12 +181,11 @@ nbb_status upload_maps(nbb_fractal *F) {
 }
 
 nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TileParams *T) {
-    const void *src[6] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data(),
-                          p.plut.data()};
-    size_t bytes[6] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
-                       p.nbr.size() * 4, p.plut.size() * 2};
-    void *dst[6];
-    nbb_status s = upload(blob, src, bytes, 6, dst);
+    const void *src[5] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data()};
+    size_t bytes[5] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
+                       p.nbr.size() * 4};
+    void *dst[5];
+    nbb_status s = upload(blob, src, bytes, 5, dst);
     if (s != NBB_OK) return s;
     *T = TileParams{};
     T->team = p.team;
@@ -200,9 +199,6 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->cbmask = p.CB >= 32 ? 0xFFFFFFFFu : ((1u << p.CB) - 1u);
     T->nblk = p.nblk;
     T->box_bytes = p.box_bytes;
-    T->slot_off = p.slot_off;
-    T->nslot = p.nslot;
-    T->divCB = make_udiv(p.CB);
     T->lds_total = p.lds_total;
     T->rm = p.rm;
     T->ntiles = uint32_t(p.ntiles);
@@ -216,8 +212,9 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->halo_src = static_cast<const uint32_t *>(dst[2]);
     T->halo_dst = static_cast<const uint32_t *>(dst[3]);
     T->nbr = static_cast<const uint32_t *>(dst[4]);
-    T->plut = static_cast<const uint16_t *>(dst[5]);
     std::memcpy(T->bid, p.bid, sizeof(T->bid));
+    std::memcpy(T->pack01, p.pack01, sizeof(T->pack01));
+    std::memcpy(T->pack23, p.pack23, sizeof(T->pack23));
     return NBB_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.hpp"
 
@@ -534,23 +535,19 @@ __device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
     return t;
 }
 
-// Next states of one block (BS x BS square, CB cells consecutive in compact
-// order) as a CB-bit mask in compact order.  The window is BS+2 rows of the
-// LDS box starting one row up and one column left of the block, read as two
-// dwords per row; byte c of H is the 3-sum of window columns c..c+2, byte c of
-// V the 3x3 sum around block column c (self included).
-//   4 x 4 blocks, perm rules: per block row, N = V - self gives four
-//   neighbour counts, two v_perm look up the birth and survival bytes of all
-//   four at once, self picks between them, and v_dot4 packs the row's bytes
-//   into four bits of a position mask; plut (LDS) turns the position mask
-//   into compact order.
-//   otherwise: V + 15 * self = live neighbours + 16 * self indexes the rule
-//   word bit by bit for every position (member positions only survive the
-//   final mask); for 3 x 3 blocks this is as fast and needs no table.
-template <int BS>
-__device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32_t *box32, uint32_t W4,
-                                               uint32_t base, uint32_t rule, const RuleTables &RT,
-                                               const uint16_t *plut) {
+// Next states of one block (a BS x BS square whose CB fractal cells are
+// consecutive in compact order), one byte per position: row r of the block
+// in next[r], byte c = column c (bytes past BS and rows past BS are
+// unspecified or 0).  The window is BS+2 rows of the LDS box starting one row
+// up and one column left of the block, read as two dwords per row; byte c of
+// H is the 3-sum of window columns c..c+2, so H[r] + H[r+1] + H[r+2] - self
+// is the live-neighbour count of every position of block row r at once.
+//   rules without birth or survival at 8: two v_perm look up the birth and
+//   the survival byte of four positions at once and self picks between them;
+//   otherwise each byte indexes the rule word (neighbours + 16 * self).
+template <int BS, bool PERM>
+__device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, uint32_t base, uint32_t rule,
+                                           const RuleTables &RT, uint32_t (&next)[4]) {
     const uint32_t a0 = base >> 2, sh = base & 3;
     uint32_t lo[BS + 2], hi[BS + 2], C[BS + 2], H[BS + 2];
 #pragma unroll
@@ -571,38 +568,79 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
             H[rr] = lo[rr] + C[rr] + alignbyte(hi[rr], lo[rr], 2);
         }
     }
-    if (BS == 4 && RT.perm) {
-        // weights of the block's columns in the packed row (bytes past BS dropped)
-        constexpr uint32_t kWeights = BS == 4 ? 0x08040201u : BS == 3 ? 0x00040201u : 0x00000201u;
-        uint32_t pos = 0;
 #pragma unroll
-        for (int rr = 0; rr < BS; ++rr) {
-            const uint32_t self = C[rr + 1];
-            const uint32_t n = H[rr] + H[rr + 1] + H[rr + 2] - self;   // live neighbours, 0..8 per byte
+    for (int rr = 0; rr < 4; ++rr) {
+        if (rr >= BS) {
+            next[rr] = 0;
+            continue;
+        }
+        const uint32_t self = C[rr + 1];
+        const uint32_t n = H[rr] + H[rr + 1] + H[rr + 2] - self;   // live neighbours, 0..8 per byte
+        if (PERM) {
             const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
             const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
             const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, self);  // 0xFF where alive
-            const uint32_t next = (born & ~smask) | (surv & smask);
-            pos |= __builtin_amdgcn_udot4(next, kWeights, 0u, false) << (BS * rr);
-        }
-        if (BS == 4) return uint32_t(plut[pos & 0xFFu]) | uint32_t(plut[256 + (pos >> 8)]);
-        return plut[pos];
-    }
-    uint32_t bits = 0;
-#pragma unroll
-    for (int rr = 0; rr < BS; ++rr) {
-        const uint32_t V = H[rr] + H[rr + 1] + H[rr + 2];
-        const uint32_t I = BS == 4 ? V + (C[rr + 1] << 4) - C[rr + 1] : V + __umul24(C[rr + 1], 15u);
-#pragma unroll
-        for (int cc = 0; cc < BS; ++cc) {
+            next[rr] = (born & ~smask) | (surv & smask);
+        } else {
             // v_bfe takes its offset from the low 5 bits of the operand, and
-            // byte cc of I (<= 24) is exactly those bits of I >> 8cc.
-            // Positions outside the fractal carry id 31, a bit dropped below.
-            const uint32_t id = T.bid[cc + BS * rr];
-            bits |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << (id & 31u);
+            // byte c of I (<= 24) is exactly those bits of I >> 8c
+            const uint32_t I = n + (self << 4);
+            uint32_t v = __builtin_amdgcn_ubfe(rule, I, 1);
+#pragma unroll
+            for (int cc = 1; cc < BS; ++cc) v |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << (8 * cc);
+            next[rr] = v;
         }
     }
-    return bits & T.cbmask;
+}
+
+__device__ __forceinline__ void store_u8(uint8_t *p, uint32_t v) { *p = uint8_t(v); }
+__device__ __forceinline__ void store_u16(uint8_t *p, uint32_t v) {
+    const uint16_t h = uint16_t(v);
+    __builtin_memcpy(p, &h, 2);
+}
+__device__ __forceinline__ void store_u32(uint8_t *p, uint32_t v) { __builtin_memcpy(p, &v, 4); }
+__device__ __forceinline__ void store_u64(uint8_t *p, uint32_t v0, uint32_t v1) {
+    const uint64_t v = uint64_t(v1) << 32 | v0;
+    __builtin_memcpy(p, &v, 8);
+}
+
+// Gathers the block's member bytes into compact order with v_perm and stores
+// its CB next states at p (any alignment: gfx950 global stores need none).
+// CB is uniform, so the size split below is scalar branches only.
+template <int BS>
+__device__ __forceinline__ void block_store(const TileParams &T, const uint32_t (&next)[4], uint8_t *p) {
+    uint32_t w[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        w[d] = __builtin_amdgcn_perm(next[1], next[0], T.pack01[d]);
+        if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], T.pack23[d]);
+    }
+    uint32_t r = T.CB;  // 1..16 bytes
+    uint32_t x = w[0], y = w[1];
+    if (r >= 8) {
+        store_u64(p, w[0], w[1]);
+        p += 8;
+        r -= 8;
+        x = w[2];
+        y = w[3];
+    }
+    if (r >= 8) {
+        store_u64(p, x, y);
+        return;
+    }
+    if (r >= 4) {
+        store_u32(p, x);
+        p += 4;
+        r -= 4;
+        x = y;
+    }
+    if (r >= 2) {
+        store_u16(p, x);
+        p += 2;
+        r -= 2;
+        x >>= 16;
+    }
+    if (r) store_u8(p, x);
 }
 
 #ifndef NBB_TILED_WAVES_PER_SIMD
@@ -616,14 +654,15 @@ __device__ __forceinline__ uint32_t block_next(const TileParams &T, const uint32
 // cells that touch the block (halo) are the same for every tile; only the
 // eight neighbour tiles differ.  Per tile a work-group
 //   1. scatters the tile's K bytes and its halo into an LDS box of
-//      (S+2) x W bytes (cells outside the fractal stay 0),
-//   2. evaluates the rule for each block of CB cells (block_next) and ORs the
-//      result bits into an LDS bit row in compact order,
-//   3. expands the bit row to bytes and stores it with aligned 16-byte stores.
+//      rows x W bytes (cells outside the fractal stay 0),
+//   2. evaluates the rule for each block of CB cells (block_rows: four
+//      positions per dword), gathers the block's member bytes into compact
+//      order (block_store: v_perm) and stores its CB next states, which are
+//      consecutive compact cells, straight to global memory.
 // Work-groups are persistent and walk an XCD-contiguous range of tiles as a
 // software pipeline: the next tile's bytes and halo are loaded into registers
 // while the current tile computes, and the neighbour tiles are found two
-// tiles ahead by threads that are idle during the stores.
+// tiles ahead by a few threads and passed on through LDS.
 //
 // BATCH: the tiles of many independent fractals that share the tile plan
 // (same k, s, offsets and m, any r), each state at its own place in one
@@ -675,11 +714,6 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
     for (uint32_t o = threadIdx.x * 16; o < kTeams * T.lds_total; o += 256 * 16)
         *reinterpret_cast<uint4 *>(lds_all + o) = make_uint4(0, 0, 0, 0);
-    // the position-mask table (4 x 4 blocks only), shared by the teams,
-    // after their regions
-    uint16_t *plut = reinterpret_cast<uint16_t *>(lds_all + kTeams * T.lds_total);
-    if (BS == 4)
-        for (uint32_t e = threadIdx.x; e < kPlutEntries; e += 256) plut[e] = T.plut[e];
     const RuleTables RT = rule_tables(rule);
     uint32_t hsrc[HPT], hdst[HPT];
 #pragma unroll
@@ -730,11 +764,10 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
     const uint32_t W4 = T.W >> 2;
-    uint16_t *slots = reinterpret_cast<uint16_t *>(lds + T.slot_off);
     uint32_t it = 0;
     for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
         const uint32_t B = local * K;  // first cell of the tile in its state array (< 2^32)
-        uint8_t *gout = dst + (B & ~15u);
+        uint8_t *gout = dst + B;
         const uint32_t ph = B & 15;
         const uint32_t nchunks = (ph + K + 15) >> 4;
         // 1. scatter the prefetched tile and halo into the box.  Offsets of
@@ -763,49 +796,31 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         uint32_t nb2 = kOutside;
         if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
 
-        // 3. rule per block -> slot (the stores of the previous tile, the
-        //    only readers, all finished before this tile's first barrier)
+        // 3. rule per block, next states straight to global memory (block b
+        //    holds the tile's cells [b CB, (b+1) CB))
+        if (RT.perm) {
 #pragma unroll
-        for (int j = 0; j < BPT; ++j)
-            if (tid + TEAM * j < T.nblk)  // waves with no block left skip the work
-                slots[tid + TEAM * j] = uint16_t(block_next<BS>(T, box32, W4, blk[j], rule, RT, plut));
-        team_sync<TEAM>();
-
-        // 4. slots -> 16 next states per chunk -> bytes -> global; the two
-        //    edge chunks are shared with the neighbouring tiles and written
-        //    bytewise.  Byte t of chunk c holds local cell 16 c - ph + t.
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const uint32_t c = tid + TEAM * j;
-            if (c < nchunks) {
-                const uint32_t lo = 16 * c > ph ? 16 * c - ph : 0u;  // first local cell in the chunk
-                const uint32_t a0 = udiv(T.divCB, lo);
-                const uint32_t r0 = lo - a0 * T.CB;
-                uint32_t acc;
-                if (T.nslot <= 4) {
-                    // four independent reads (the slot row is padded past the
-                    // last block), no loop: the usual case, CB >= 5
-                    const uint32_t s0 = slots[a0], s1 = slots[a0 + 1], s2 = slots[a0 + 2], s3 = slots[a0 + 3];
-                    const uint32_t h1 = T.CB - r0, h2 = h1 + T.CB, h3 = h2 + T.CB;
-                    acc = (s0 >> r0) | (h1 < 16 ? s1 << h1 : 0u) | (h2 < 16 ? s2 << h2 : 0u) |
-                          (h3 < 16 ? s3 << h3 : 0u);
-                } else {
-                    acc = uint32_t(slots[a0]) >> r0;
-                    uint32_t sh = T.CB - r0;
-                    for (uint32_t e = 1; e < T.nslot; ++e, sh += T.CB)
-                        if (sh < 16) acc |= uint32_t(slots[a0 + e]) << sh;
+            for (int j = 0; j < BPT; ++j) {
+                const uint32_t bi = tid + TEAM * j;
+                if (bi < T.nblk) {  // waves with no block left skip the work
+                    uint32_t next[4];
+                    block_rows<BS, true>(box32, W4, blk[j], rule, RT, next);
+                    block_store<BS>(T, next, gout + bi * T.CB);
                 }
-                const uint32_t m16 = (acc << (lo + ph - 16 * c)) & 0xFFFFu;
-                const uint4 v = make_uint4(nibble_to_bytes(m16 & 0xFu), nibble_to_bytes((m16 >> 4) & 0xFu),
-                                           nibble_to_bytes((m16 >> 8) & 0xFu), nibble_to_bytes(m16 >> 12));
-                if (16 * c >= ph && 16 * c + 16 <= ph + K) {
-                    *reinterpret_cast<uint4 *>(gout + 16 * c) = v;
-                } else {
-                    const uint32_t lo_b = max(16 * c, ph), hi_b = min(16 * c + 16, ph + K);
-                    for (uint32_t b = lo_b; b < hi_b; ++b) gout[b] = uint8_t((m16 >> (b - 16 * c)) & 1u);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const uint32_t bi = tid + TEAM * j;
+                if (bi < T.nblk) {
+                    uint32_t next[4];
+                    block_rows<BS, false>(box32, W4, blk[j], rule, RT, next);
+                    block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
         }
+        // the box is read until here; the next tile's scatter comes after
+        team_sync<TEAM>();
         if (tid >= kLane0) nbr[it & 1][tid - kLane0] = nb2;
     }
 }
@@ -958,12 +973,21 @@ template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     constexpr uint32_t kTeams = 256 / TEAM;
-    const size_t lds = size_t(kTeams) * T.lds_total + (BS == 4 ? kPlutEntries * sizeof(uint16_t) : 0);
+    const size_t lds = size_t(kTeams) * T.lds_total;
+    // resident work-groups per CU for this instantiation and LDS size; the
+    // last answer is kept (one query per plan, not per launch)
+    static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>, 256, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
+    const uint64_t c = cached.load(std::memory_order_relaxed);
+    if (c >> 32 == lds && (c & 0xFFFFFFFFu)) {
+        per_cu = int(c & 0xFFFFFFFFu);
+    } else {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>, 256, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
+    }
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, (T.ntiles + kTeams - 1) / kTeams);
     hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>), dim3(uint32_t(grid)), dim3(256), lds, st,
                        P, T, in, out, rule, rec);

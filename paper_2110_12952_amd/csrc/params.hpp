@@ -65,9 +65,6 @@ struct TileParams {
     uint32_t cbmask;      // (1 << CB) - 1
     uint32_t nblk;        // k^(m-q) blocks per tile
     uint32_t box_bytes;   // LDS box allocation
-    uint32_t slot_off;    // LDS offset of the result slots: u16 slot b = next states of block b
-    uint32_t nslot;       // slots that cover any 16 consecutive cells: 1 + ceil(15 / CB)
-    UDiv divCB;           // division by CB
     uint32_t lds_total;   // LDS per team
     uint32_t rm;          // coarse levels r - m
     uint32_t ntiles;      // k^(r-m)
@@ -82,10 +79,12 @@ struct TileParams {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;     // 8 neighbour tiles per tile (0xFFFFFFFF = none)
-    const uint16_t *plut;    // kPlutEntries: block position mask -> the block's next-state bits in
-                             // compact order (BS = 4: two tables of 256, rows 0-1 and rows 2-3)
+    // v_perm selectors that gather a block's next states, one byte per
+    // block position (row r in a dword, byte c = column c), into compact
+    // order: output dword d = perm(row1, row0, pack01[d]) | perm(row3, row2,
+    // pack23[d]); selector 12 gives a zero byte.
+    uint32_t pack01[4], pack23[4];
     uint8_t bid[16];      // position c + BS*row inside a block -> cell id in the block, 0xFF if none
-                          // (the kernel reads 0xFF & 31 = 31: a bit outside cbmask)
 };
 
 // One instance of a batch (device table, sorted by tile0): its state starts
@@ -98,8 +97,6 @@ struct BatchInstance {
     uint32_t ntiles;
     uint32_t tail_partial;  // 1 if k^r is not a multiple of 16
 };
-
-constexpr uint32_t kPlutEntries = 512;
 
 // The bounding-box step.  Membership splits into the low L levels (an
 // SL x SL bitmap, SL = s^L, one row of LW words per y) and the high r - L

@@ -331,15 +331,7 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->CB = uint32_t(ipow64(f.k, q));
     p->nblk = uint32_t(ipow64(f.k, m - q));
     p->box_bytes = p->rows * p->W + 8;
-    p->slot_off = (p->box_bytes + 15) & ~15u;
-    // one u16 slot per block (blocks past the last one, evaluated to keep
-    // every thread on the same path, included), plus the slots a 16-cell
-    // chunk at the end of the tile may read past them.
-    p->nslot = 1 + (15 + p->CB - 1) / p->CB;
-    const uint64_t nblk_pad = (uint64_t(p->nblk) + 255) / 256 * 256;
-    // (at least four past the last block: the store phase reads four slots
-    // unconditionally when nslot <= 4)
-    p->lds_total = p->slot_off + uint32_t(((nblk_pad + std::max(p->nslot, 4u) + 1) * 2 + 15) & ~uint64_t(15));
+    p->lds_total = (p->box_bytes + 15) & ~15u;
     if (team == 64 && 4 * uint64_t(p->lds_total) > 65536) {
         *msg = "four wavefront boxes do not fit 64 KiB of LDS";
         return false;
@@ -370,24 +362,26 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
             int64_t v = nu_levels(f, q, c, rr);
             if (v >= 0) p->bid[c + p->BS * rr] = uint8_t(v);
         }
-    // Position mask -> compact bits.  Bit c + BS*row of a position mask is the
-    // next state at column c, row `row` of a block; the table ORs in bit
-    // bid[...] of each set member position.  For BS = 4 the 16-bit mask is
-    // looked up as two bytes (rows 0-1 at entries 0-255, rows 2-3 at 256-511).
-    p->plut.assign(kPlutEntries, 0);
-    {
-        const uint32_t npos = p->BS * p->BS;
-        const uint32_t span = p->BS == 4 ? 8 : npos;  // positions per table
-        const uint32_t ntab = p->BS == 4 ? 2 : 1;
-        for (uint32_t tab = 0; tab < ntab; ++tab)
-            for (uint32_t v = 0; v < (1u << span); ++v) {
-                uint16_t bits = 0;
-                for (uint32_t j = 0; j < span; ++j) {
-                    const uint32_t pos = tab * span + j;
-                    if ((v >> j & 1) && pos < npos && p->bid[pos] != 0xFF) bits |= uint16_t(1u << p->bid[pos]);
+    // Byte gathers from block rows to compact order: byte j of the block's
+    // output is the cell with id j, at column c of row r; rows 0 and 1 feed
+    // pack01 (row 0 as the low source, selectors 0-3, row 1 as the high one,
+    // 4-7), rows 2 and 3 feed pack23 the same way; 12 selects a zero byte.
+    for (uint32_t d = 0; d < 4; ++d) {
+        uint32_t s01 = 0, s23 = 0;
+        for (uint32_t b = 0; b < 4; ++b) {
+            uint32_t a = 12, h = 12;
+            const uint32_t j = 4 * d + b;
+            for (uint32_t pos = 0; pos < p->BS * p->BS; ++pos)
+                if (p->bid[pos] == j) {
+                    const uint32_t c = pos % p->BS, r = pos / p->BS;
+                    if (r < 2) a = r * 4 + c;
+                    else h = (r - 2) * 4 + c;
                 }
-                p->plut[tab * 256 + v] = bits;
-            }
+            s01 |= a << (8 * b);
+            s23 |= h << (8 * b);
+        }
+        p->pack01[d] = s01;
+        p->pack23[d] = s23;
     }
     const int64_t Si = p->S;
     uint32_t dir8 = 0;

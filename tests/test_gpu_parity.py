@@ -425,3 +425,35 @@ def test_triangle_r20_compact(N):
     g.configure(N.STRATEGY_DIRECT)
     res = g.step_compact(a, b, 2)
     assert torch.equal(res, tiled)
+
+
+@pytest.mark.parametrize("name,r,strategy", [("triangle", 8, "tiled"), ("carpet", 4, "wave"), ("hfractal", 3, "direct")])
+def test_step_compact_in_a_captured_graph(N, name, r, strategy):
+    # The step entry points only enqueue kernels (no allocation, memset or
+    # synchronisation), so a caller can capture them in a HIP graph.  The
+    # graph is replayed several times with eager work in between; every
+    # replay must give the oracle's result.
+    fd, o, g = pair(name, r, N)
+    if strategy == "wave":
+        g.configure(N.STRATEGY_TILED_WAVE, 2)
+    elif strategy == "direct":
+        g.configure(N.STRATEGY_DIRECT)
+    st0 = o.init_compact(12, 0.5)
+    want = o.compact_steps(st0, B3S23, 6)
+    a0 = dev(st0)
+    a, b = a0.clone(), torch.empty_like(a0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.step_compact(a, b, 2)          # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        res = g.step_compact(a, b, 6)
+    assert res is a
+    other = dev(o.init_compact(99, 0.5))
+    for rep in range(4):
+        a.copy_(a0)
+        graph.replay()
+        g.step_compact(other, torch.empty_like(other), 3)   # eager work between replays
+        np.testing.assert_array_equal(host(a), want, err_msg=f"replay {rep}")
