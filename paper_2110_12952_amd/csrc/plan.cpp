@@ -172,6 +172,10 @@ static uint32_t box_alloc_bytes(uint32_t S) { return (S + 2) * box_pitch_bytes(S
 
 // LDS budget of the tile box: keeps several work-groups resident per CU.
 static const uint32_t kBoxBudget = 32 * 1024;
+// LDS per CU on gfx950 and the work-groups of 256 threads one CU holds at
+// most (eight waves per SIMD).
+static const uint32_t kLdsPerCU = 160 * 1024;
+static const uint32_t kMaxGroupsPerCU = 8;
 
 static uint32_t block_level(const Fractal &f, uint32_t m);
 
@@ -310,15 +314,26 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->K = uint32_t(K);
     uint32_t cols;
     box_extent(f, m, &p->rows, &cols);
-    // Box pitch: the multiple of 4 in [cols, cols+64) with the fewest
-    // modelled LDS bank conflicts whose box still fits the budget (the
-    // smallest pitch when none fits, as for large requested tile levels).
+    // Box pitch: among the multiples of 4 in [cols, cols+64) whose box fits
+    // the budget (or the smallest pitch when none fits, as for large
+    // requested tile levels), those that keep the most work-groups resident
+    // per CU by LDS, and among them the one with the fewest modelled bank
+    // conflicts.
     p->W = (cols + 3) & ~3u;
     {
         const uint32_t least = p->rows * p->W + 8;
-        uint64_t best = box_pitch_cost(f, m, q, p->W);
-        for (uint32_t W = p->W + 4; W < p->W + 64; W += 4) {
-            if (p->rows * W + 8 > std::max(kBoxBudget, least)) break;
+        auto resident = [&](uint32_t W) {
+            const uint32_t per_team = ((p->rows * W + 8) + 15) & ~15u;
+            return std::min(kMaxGroupsPerCU, kLdsPerCU / (per_team * (256 / team) + 256));
+        };
+        uint32_t most = resident(p->W);
+        for (uint32_t W = p->W + 4; W < p->W + 64 && p->rows * W + 8 <= std::max(kBoxBudget, least); W += 4)
+            most = std::max(most, resident(W));
+        uint64_t best = ~uint64_t(0);
+        const uint32_t W0 = p->W;
+        for (uint32_t W = W0; W < W0 + 64; W += 4) {
+            if (W > W0 && p->rows * W + 8 > std::max(kBoxBudget, least)) break;
+            if (resident(W) < most) continue;
             const uint64_t c = box_pitch_cost(f, m, q, W);
             if (c < best) {
                 best = c;
