@@ -606,7 +606,10 @@ __device__ __forceinline__ void store_u64(uint8_t *p, uint32_t v0, uint32_t v1) 
 
 // Gathers the block's member bytes into compact order with v_perm and stores
 // its CB next states at p (any alignment: gfx950 global stores need none).
-// CB is uniform, so the size split below is scalar branches only.
+// Blocks of 5 to 7 cells are written as two overlapping 4-byte stores of the
+// same lane (the overlap gets the same bytes twice; blocks of different
+// lanes never overlap).  CB is uniform, so the choice below is scalar
+// branches only.
 template <int BS>
 __device__ __forceinline__ void block_store(const TileParams &T, const uint32_t (&next)[4], uint8_t *p) {
     uint32_t w[4];
@@ -615,32 +618,42 @@ __device__ __forceinline__ void block_store(const TileParams &T, const uint32_t 
         w[d] = __builtin_amdgcn_perm(next[1], next[0], T.pack01[d]);
         if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], T.pack23[d]);
     }
-    uint32_t r = T.CB;  // 1..16 bytes
-    uint32_t x = w[0], y = w[1];
-    if (r >= 8) {
+    const uint32_t CB = T.CB;  // 1..16 bytes
+    if (CB == 16) {
         store_u64(p, w[0], w[1]);
+        store_u64(p + 8, w[2], w[3]);
+    } else if (CB > 8) {
+        // (an overlapping second 8-byte store measured slower than the
+        // pieces for the 9-cell blocks of the triangle)
+        store_u64(p, w[0], w[1]);
+        uint32_t r = CB - 8, x = w[2];  // 1..7
         p += 8;
-        r -= 8;
-        x = w[2];
-        y = w[3];
+        if (r >= 4) {
+            store_u32(p, x);
+            p += 4;
+            r -= 4;
+            x = w[3];
+        }
+        if (r >= 2) {
+            store_u16(p, x);
+            p += 2;
+            r -= 2;
+            x >>= 16;
+        }
+        if (r) store_u8(p, x);
+    } else if (CB == 8) {
+        store_u64(p, w[0], w[1]);
+    } else if (CB > 4) {
+        store_u32(p, w[0]);
+        store_u32(p + (CB - 4), alignbyte(w[1], w[0], CB - 4));
+    } else if (CB == 4) {
+        store_u32(p, w[0]);
+    } else if (CB >= 2) {
+        store_u16(p, w[0]);
+        if (CB == 3) store_u16(p + 1, w[0] >> 8);
+    } else {
+        store_u8(p, w[0]);
     }
-    if (r >= 8) {
-        store_u64(p, x, y);
-        return;
-    }
-    if (r >= 4) {
-        store_u32(p, x);
-        p += 4;
-        r -= 4;
-        x = y;
-    }
-    if (r >= 2) {
-        store_u16(p, x);
-        p += 2;
-        r -= 2;
-        x >>= 16;
-    }
-    if (r) store_u8(p, x);
 }
 
 #ifndef NBB_TILED_WAVES_PER_SIMD
