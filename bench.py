@@ -96,6 +96,7 @@ def small_case(torch, N, W, rule):
     a, b = a0.clone(), torch.empty_like(a0)
     T = wl.steps
     g.step_compact(a, b, 2, rule)
+    a.copy_(a0)
     ms_eager, res = time_events(torch, lambda: g.step_compact(a, b, T, rule))
     eager = res.clone()
     side = torch.cuda.Stream()
