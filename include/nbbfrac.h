@@ -30,8 +30,9 @@
  *     fractal, and the padding columns x >= n, hold 0.
  *   - Rule word: bit c (c = 0..8) set = a dead cell with c live Moore
  *     neighbours is born; bit 16+c set = a live cell with c live neighbours
- *     survives.  Conway's Life B3/S23 is NBB_RULE_B3S23.  Cells outside the
- *     fractal or the box count as dead and stay dead.
+ *     survives; bit 31 (NBB_RULE_VON_NEUMANN) = count the four edge
+ *     neighbours only.  Conway's Life B3/S23 is NBB_RULE_B3S23.  Cells
+ *     outside the fractal or the box count as dead and stay dead.
  *   - Device pointers are owned by the caller and must be device memory of the
  *     device that was current at nbb_create (e.g. torch CUDA tensors).  A
  *     `stream` is a hipStream_t (NULL = the null stream).  Calls check their
@@ -65,6 +66,11 @@ typedef enum {
 
 /* B3/S23: born with 3, survives with 2 or 3. */
 #define NBB_RULE_B3S23 ((1u << 3) | ((1u << 2 | 1u << 3) << 16))
+
+/* Rule-word flag: count only the four neighbours that share an edge with the
+ * cell (the four-cell stencil of section 3's example) instead of the eight of
+ * the Moore neighbourhood; counts then run 0..4. */
+#define NBB_RULE_VON_NEUMANN (1u << 31)
 
 /* How nbb_step_compact evaluates a step (nbb_configure). */
 #define NBB_STRATEGY_AUTO 0u   /* TILED when the fractal allows it, else DIRECT */
@@ -171,7 +177,7 @@ nbb_status nbb_init_bbox(const nbb_fractal *f, uint8_t *state, uint64_t pitch, u
  * stencil procedure; section 4, Game of Life on the fractal).  The state
  * starts in a; buffers a and b alternate, and *result_in_b (if not NULL) is
  * set to steps & 1, i.e. whether the result ended in b.  len must be k^r;
- * a and b must not overlap; the rule may only use bits 0-8 and 16-24; state
+ * a and b must not overlap; the rule may only use bits 0-8, 16-24 and 31; state
  * bytes must be 0 or 1.  steps == 0 leaves both buffers untouched.
  */
 nbb_status nbb_step_compact(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len,

@@ -36,16 +36,20 @@ def member_set(s: int, offsets: Sequence[Cell], r: int) -> Set[Cell]:
     return set(build_levels(s, offsets, r))
 
 
+NEIGHBOURS = {8: [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dx or dy],
+              4: [(0, -1), (-1, 0), (1, 0), (0, 1)]}
+
+
 def gol_step(members: Set[Cell], live: Set[Cell], birth: Sequence[int],
-             survive: Sequence[int]) -> Set[Cell]:
-    """One synchronous generation on the member cells; everything else is dead."""
+             survive: Sequence[int], neighbourhood: int = 8) -> Set[Cell]:
+    """One synchronous generation on the member cells; everything else is
+    dead.  neighbourhood 8 = Moore, 4 = the cells sharing an edge."""
     out: Set[Cell] = set()
     for (x, y) in members:
         c = 0
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
-                if (dx or dy) and (x + dx, y + dy) in live:
-                    c += 1
+        for dx, dy in NEIGHBOURS[neighbourhood]:
+            if (x + dx, y + dy) in live:
+                c += 1
         if (x, y) in live:
             if c in survive:
                 out.add((x, y))
@@ -55,11 +59,12 @@ def gol_step(members: Set[Cell], live: Set[Cell], birth: Sequence[int],
 
 
 def run_compact(s: int, offsets: Sequence[Cell], r: int, state: Sequence[int],
-                birth: Sequence[int], survive: Sequence[int], steps: int) -> List[int]:
+                birth: Sequence[int], survive: Sequence[int], steps: int,
+                neighbourhood: int = 8) -> List[int]:
     """Evolve a compact-order state (list of 0/1) for `steps` generations."""
     order = build_levels(s, offsets, r)
     members = set(order)
     live = {c for c, v in zip(order, state) if v}
     for _ in range(steps):
-        live = gol_step(members, live, birth, survive)
+        live = gol_step(members, live, birth, survive, neighbourhood)
     return [1 if c in live else 0 for c in order]

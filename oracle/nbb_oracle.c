@@ -205,6 +205,15 @@ static uint8_t orc_apply_rule(uint32_t rule, int64_t live_neighbours, int self_a
     return (uint8_t)((rule >> bit) & 1u);
 }
 
+/* Whether the cell at offset (dx, dy) is a neighbour: the eight cells of the
+ * Moore neighbourhood, or with bit 31 of the rule word only the four that
+ * share an edge (section 3's example stencil). */
+static int orc_neighbour(uint32_t rule, int64_t dx, int64_t dy) {
+    if (dx == 0 && dy == 0) return 0;
+    if ((rule >> 31) && dx != 0 && dy != 0) return 0;
+    return 1;
+}
+
 /* One generation on the box.  mask is orc_member_mask's output; only member
  * neighbours inside the box count; non-members come out dead. */
 void orc_bbox_step(const orc_fractal *f, const uint8_t *mask, const uint8_t *in, uint8_t *out,
@@ -220,7 +229,7 @@ void orc_bbox_step(const orc_fractal *f, const uint8_t *mask, const uint8_t *in,
             int64_t live = 0;
             for (int64_t dy = -1; dy <= 1; ++dy)
                 for (int64_t dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0) continue;
+                    if (!orc_neighbour(rule, dx, dy)) continue;
                     int64_t xx = x + dx, yy = y + dy;
                     if (xx < 0 || yy < 0 || xx >= n || yy >= n) continue;
                     if (mask[yy * n + xx] && in[yy * n + xx]) ++live;
@@ -241,7 +250,7 @@ void orc_compact_step(const orc_fractal *f, const uint8_t *in, uint8_t *out, uin
         int64_t live = 0;
         for (int64_t dy = -1; dy <= 1; ++dy)
             for (int64_t dx = -1; dx <= 1; ++dx) {
-                if (dx == 0 && dy == 0) continue;
+                if (!orc_neighbour(rule, dx, dy)) continue;
                 int64_t j = orc_nu(f, x + dx, y + dy);
                 if (j != ORC_OUTSIDE && in[j]) ++live;
             }
@@ -259,7 +268,7 @@ static uint8_t orc_cell_after(const orc_fractal *f, const uint8_t *in, int64_t i
     int64_t live = 0;
     for (int64_t dy = -1; dy <= 1; ++dy)
         for (int64_t dx = -1; dx <= 1; ++dx) {
-            if (dx == 0 && dy == 0) continue;
+            if (!orc_neighbour(rule, dx, dy)) continue;
             int64_t j = orc_nu(f, x + dx, y + dy);
             if (j != ORC_OUTSIDE && orc_cell_after(f, in, j, rule, steps - 1)) ++live;
         }
@@ -283,7 +292,7 @@ static uint8_t orc_cell_after_seeded(const orc_fractal *f, uint64_t seed, uint32
     int64_t live = 0;
     for (int64_t dy = -1; dy <= 1; ++dy)
         for (int64_t dx = -1; dx <= 1; ++dx) {
-            if (dx == 0 && dy == 0) continue;
+            if (!orc_neighbour(rule, dx, dy)) continue;
             int64_t j = orc_nu(f, x + dx, y + dy);
             if (j != ORC_OUTSIDE && orc_cell_after_seeded(f, seed, thr, j, rule, steps - 1)) ++live;
         }

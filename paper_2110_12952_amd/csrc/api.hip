@@ -271,7 +271,7 @@ bool overlap(const void *a, const void *b, uint64_t len) {
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-const uint32_t kRuleMask = 0x1FFu | (0x1FFu << 16);
+const uint32_t kRuleMask = 0x1FFu | (0x1FFu << 16) | (1u << 31);
 
 int map_grid(const nbb_fractal *F, uint64_t work_items) {
     uint64_t g = (work_items + 511) / 512;
@@ -469,7 +469,7 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
     if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
     if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
     if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "state buffers must be 16-byte aligned");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
     // Candidates: (strategy, level).  Tile levels whose plan fits a
@@ -692,7 +692,7 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     if (arena_len < B->arena_bytes) return fail(NBB_E_INVALID, "arena shorter than the batch needs");
     if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
     if (B->count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -723,7 +723,7 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     if (arena_len < B->arena_bytes) return fail(NBB_E_INVALID, "arena shorter than the batch needs");
     if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
     if (B->count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -855,7 +855,7 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     if (len != F->f.cells) return fail(NBB_E_INVALID, "len must equal k^r");
     if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
     if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "state buffers must be 16-byte aligned");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
     if (result_in_b) *result_in_b = int(steps & 1);
@@ -885,7 +885,7 @@ nbb_status nbb_step_bbox(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t 
     if (st != NBB_OK) return st;
     if (!aligned16(b)) return fail(NBB_E_INVALID, "box state must be 16-byte aligned");
     if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     st = check_device(F);
     if (st != NBB_OK) return st;
     if (result_in_b) *result_in_b = int(steps & 1);
@@ -907,7 +907,7 @@ nbb_status nbb_step_lambda(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_
     if (st != NBB_OK) return st;
     if (!aligned16(b)) return fail(NBB_E_INVALID, "box state must be 16-byte aligned");
     if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
-    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8 and 16-24");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     st = check_device(F);
     if (st != NBB_OK) return st;
     if (result_in_b) *result_in_b = int(steps & 1);

@@ -425,6 +425,7 @@ __global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_w
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
             if (d == 4) continue;
+            if ((rule >> 31) && d % 3 != 1 && d / 3 != 1) continue;  // corners: not edge neighbours
             uint32_t j = nu_lut(P, nu, int32_t(x) + d % 3 - 1, int32_t(y) + d / 3 - 1);
             if (j != kOutside) live += in[j];
         }
@@ -433,6 +434,10 @@ __global__ __launch_bounds__(512) void k_step_direct(MapParams P, uint32_t lam_w
     }
 }
 
+// Rule words with bit 31 set count only the four neighbours that share an
+// edge (section 3's example stencil) instead of the eight of the Moore
+// neighbourhood; every step kernel honours it.
+//
 // The lambda approach (section 4, second method): threads run over the
 // compact cells but the state lives in the box.  Cell i finds (x, y) =
 // lambda(i) and reads its 3 x 3 neighbourhood straight from the box; cells
@@ -449,6 +454,7 @@ __global__ __launch_bounds__(512) void k_step_lambda(MapParams P, uint32_t lam_w
         uint32_t x, y;
         lam_lut(P, smem_l, uint32_t(i), x, y);
         uint32_t sum = 0;
+        const bool edge_only = (rule >> 31) != 0;
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
             const uint32_t yy = y + dy;
@@ -456,6 +462,7 @@ __global__ __launch_bounds__(512) void k_step_lambda(MapParams P, uint32_t lam_w
             const uint8_t *row = in + uint64_t(yy) * pitch;
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
+                if (edge_only && dx != 0 && dy != 0) continue;
                 const uint32_t xx = x + dx;
                 if (xx < P.n) sum += row[xx];
             }
@@ -545,7 +552,7 @@ __device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
 //   rules without birth or survival at 8: two v_perm look up the birth and
 //   the survival byte of four positions at once and self picks between them;
 //   otherwise each byte indexes the rule word (neighbours + 16 * self).
-template <int BS, bool PERM>
+template <int BS, bool PERM, bool EDGE>
 __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, uint32_t base, uint32_t rule,
                                            const RuleTables &RT, uint32_t (&next)[4]) {
     const uint32_t a0 = base >> 2, sh = base & 3;
@@ -575,7 +582,14 @@ __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, u
             continue;
         }
         const uint32_t self = C[rr + 1];
-        const uint32_t n = H[rr] + H[rr + 1] + H[rr + 2] - self;   // live neighbours, 0..8 per byte
+        // live neighbours per byte: the 3x3 sum minus self, or the cells
+        // above and below plus the left and right ones
+        uint32_t n;
+        if (EDGE)
+            n = C[rr] + C[rr + 2] + lo[rr + 1] +
+                (BS == 2 ? lo[rr + 1] >> 16 : alignbyte(hi[rr + 1], lo[rr + 1], 2));
+        else
+            n = H[rr] + H[rr + 1] + H[rr + 2] - self;
         if (PERM) {
             const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
             const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
@@ -702,7 +716,7 @@ __device__ __forceinline__ void team_sync() {
     }
 }
 
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE>
 __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule,
     const uint32_t *__restrict__ rec) {
@@ -817,7 +831,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {  // waves with no block left skip the work
                     uint32_t next[4];
-                    block_rows<BS, true>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -827,7 +841,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {
                     uint32_t next[4];
-                    block_rows<BS, false>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -900,7 +914,9 @@ __global__ __launch_bounds__(256) void k_step_box(BoxParams B, uint32_t gx,
                 const uint32_t X = ((V - self) | self) ^ 0x03030303u;
                 res = (~(X + 0x7F7F7F7Fu) & 0x80808080u) >> 7;
             } else {
-                const uint32_t I = V + (self << 4) - self;  // neighbours + 16 * self
+                // neighbours + 16 * self; the four edge neighbours are the
+                // cells above and below plus the row's 3-sum minus self
+                const uint32_t I = ((rule >> 31) ? up.w[i] + dn.w[i] + mid.h[i] : V) + (self << 4) - self;
                 res = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) res |= ((rule >> ((I >> (8 * b)) & 0xFFu)) & 1u) << (8 * b);
@@ -982,7 +998,7 @@ hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint
 }
 // Persistent launch: as many work-groups as can be resident at once (the
 // occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     constexpr uint32_t kTeams = 256 / TEAM;
@@ -996,32 +1012,32 @@ static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const 
         per_cu = int(c & 0xFFFFFFFFu);
     } else {
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>, 256, lds);
+            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE>, 256, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
     }
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, (T.ntiles + kTeams - 1) / kTeams);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM>), dim3(uint32_t(grid)), dim3(256), lds, st,
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE>), dim3(uint32_t(grid)), dim3(256), lds, st,
                        P, T, in, out, rule, rec);
     return hipGetLastError();
 }
-template <int BS, int CPT, int HPT, bool BATCH, int TEAM>
+template <int BS, int CPT, int HPT, bool BATCH, int TEAM, bool EDGE>
 static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t bpt = (T.nblk + TEAM - 1) / TEAM;
-    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
-template <int BS, bool BATCH, int TEAM>
+template <int BS, bool BATCH, int TEAM, bool EDGE>
 static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t cpt = (T.K + 30 + 16 * TEAM - 1) / (16 * TEAM);
     const uint32_t hpt = (T.halo_count + TEAM - 1) / TEAM;
 #define NBB_TILED_CASE(C, H) \
-    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st)
+    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st)
     NBB_TILED_CASE(1, 1);
     NBB_TILED_CASE(1, 2);
     NBB_TILED_CASE(1, 4);
@@ -1031,21 +1047,26 @@ static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const 
 #undef NBB_TILED_CASE
     return hipErrorInvalidValue;
 }
-template <bool BATCH, int TEAM>
+template <bool BATCH, int TEAM, bool EDGE>
 static hipError_t launch_tiled_bs(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                   uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     switch (T.BS) {
-        case 2: return launch_tiled_s<2, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
-        case 3: return launch_tiled_s<3, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
-        case 4: return launch_tiled_s<4, BATCH, TEAM>(P, T, in, out, rule, rec, cu_count, st);
+        case 2: return launch_tiled_s<2, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+        case 3: return launch_tiled_s<3, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+        case 4: return launch_tiled_s<4, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
         default: return hipErrorInvalidValue;
     }
 }
 template <bool BATCH>
 static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                    uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    if (T.team == 64) return launch_tiled_bs<BATCH, 64>(P, T, in, out, rule, rec, cu_count, st);
-    if (T.team == 256) return launch_tiled_bs<BATCH, 256>(P, T, in, out, rule, rec, cu_count, st);
+    const bool edge = (rule >> 31) != 0;  // four edge neighbours only
+    if (T.team == 64)
+        return edge ? launch_tiled_bs<BATCH, 64, true>(P, T, in, out, rule, rec, cu_count, st)
+                    : launch_tiled_bs<BATCH, 64, false>(P, T, in, out, rule, rec, cu_count, st);
+    if (T.team == 256)
+        return edge ? launch_tiled_bs<BATCH, 256, true>(P, T, in, out, rule, rec, cu_count, st)
+                    : launch_tiled_bs<BATCH, 256, false>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,

@@ -23,6 +23,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nbbfrac.h")
 NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
 NBB_OUTSIDE = 0xFFFFFFFF
 NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
+NBB_RULE_VON_NEUMANN = 1 << 31
 STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE = 0, 1, 2, 3
 MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 

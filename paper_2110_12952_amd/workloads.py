@@ -69,25 +69,39 @@ FRACTALS: Dict[str, FractalDef] = {
                         VICSEK, XFRACTAL, CANTOR_DUST, CANTOR, SINGLE, GRID4)
 }
 
-# Game-of-Life rules as (birth counts, survival counts).
+# Game-of-Life rules as (birth counts, survival counts[, neighbourhood]):
+# neighbourhood 8 (default) = the Moore neighbourhood, 4 = the four cells
+# that share an edge.
 RULES = {
     "B3/S23": ((3,), (2, 3)),             # Conway's Game of Life
     "B1357/S1357": ((1, 3, 5, 7), (1, 3, 5, 7)),    # replicator (XOR of neighbours)
     "B1357/S02468": ((1, 3, 5, 7), (0, 2, 4, 6, 8)),  # Fredkin (self XOR neighbours)
     "B36/S23": ((3, 6), (2, 3)),          # HighLife
     "B2/S": ((2,), ()),                   # Seeds
+    "vN:B13/S13": ((1, 3), (1, 3), 4),    # 4-neighbour parity (XOR of the four)
+    "vN:B13/S024": ((1, 3), (0, 2, 4), 4),  # 4-neighbour Fredkin (self XOR the four)
+    "vN:B2/S12": ((2,), (1, 2), 4),       # a 4-neighbour life-like rule
 }
+
+VON_NEUMANN = 1 << 31  # rule-word flag: count the four edge neighbours only
 
 
 def rule_mask(name_or_pair) -> int:
-    """Rule word: bit c (0..8) = birth with c live neighbours, bit 16+c = survival."""
-    birth, survive = RULES[name_or_pair] if isinstance(name_or_pair, str) else name_or_pair
-    m = 0
+    """Rule word: bit c (0..8) = birth with c live neighbours, bit 16+c =
+    survival, bit 31 = four-cell neighbourhood."""
+    spec = RULES[name_or_pair] if isinstance(name_or_pair, str) else name_or_pair
+    birth, survive = spec[0], spec[1]
+    m = VON_NEUMANN if len(spec) > 2 and spec[2] == 4 else 0
     for c in birth:
         m |= 1 << c
     for c in survive:
         m |= 1 << (16 + c)
     return m
+
+
+def rule_neighbourhood(name_or_pair) -> int:
+    spec = RULES[name_or_pair] if isinstance(name_or_pair, str) else name_or_pair
+    return spec[2] if len(spec) > 2 else 8
 
 
 @dataclass(frozen=True)

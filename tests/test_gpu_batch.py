@@ -61,7 +61,7 @@ def _spread_offsets(cells, seed):
     return offs, o + 32
 
 
-@pytest.mark.parametrize("rule", ["B3/S23", "B36/S23", "B1357/S02468", "B2/S"])
+@pytest.mark.parametrize("rule", ["B3/S23", "B36/S23", "B1357/S02468", "B2/S", "vN:B2/S12"])
 @pytest.mark.parametrize("steps", [1, 6])
 def test_batch_mixed_vs_oracle(N, rule, steps):
     fds, rs, frs = _mixed(N)

@@ -285,7 +285,7 @@ def test_fullsquare_textbook_patterns(pat):
 
 
 @pytest.mark.parametrize("name", SMALL_FRACTALS)
-@pytest.mark.parametrize("rule", ["B3/S23", "B1357/S1357", "B36/S23"])
+@pytest.mark.parametrize("rule", ["B3/S23", "B1357/S1357", "B36/S23", "vN:B2/S12", "vN:B13/S13"])
 def test_compact_procedure_matches_box_definition(name, rule):
     # The paper's compact stencil procedure (lambda, neighbour coordinates,
     # nu, read) against the automaton on the box, gathered through lambda.
@@ -299,14 +299,16 @@ def test_compact_procedure_matches_box_definition(name, rule):
 
 
 @pytest.mark.parametrize("name", SMALL_FRACTALS)
-def test_compact_matches_set_brute_force(name):
+@pytest.mark.parametrize("rule", ["B3/S23", "vN:B2/S12"])
+def test_compact_matches_set_brute_force(name, rule):
     fd = W.FRACTALS[name]
-    birth, survive = W.RULES["B3/S23"]
+    spec = W.RULES[rule]
     for r in range(0, min(max_level(name), 3) + 1):
         f = frac(name, r)
         st = W.random_bits(seed=r + 3, count=f.cells, p=0.5)
-        want = brute.run_compact(fd.s, fd.offsets, r, st.tolist(), birth, survive, 3)
-        assert f.compact_steps(st, B3S23, 3).tolist() == want
+        want = brute.run_compact(fd.s, fd.offsets, r, st.tolist(), spec[0], spec[1], 3,
+                                 W.rule_neighbourhood(rule))
+        assert f.compact_steps(st, W.rule_mask(rule), 3).tolist() == want
 
 
 @pytest.mark.parametrize("name,r", [("triangle", 2), ("carpet", 1), ("hfractal", 1),
@@ -315,16 +317,18 @@ def test_compact_matches_set_brute_force(name):
 def test_every_initial_state_one_step(name, r):
     fd = W.FRACTALS[name]
     f = frac(name, r)
-    birth, survive = W.RULES["B3/S23"]
-    for bits in itertools.product((0, 1), repeat=f.cells):
-        st = np.array(bits, dtype=np.uint8)
-        want = brute.run_compact(fd.s, fd.offsets, r, list(bits), birth, survive, 1)
-        assert f.compact_steps(st, B3S23, 1).tolist() == want
+    for rule in ("B3/S23", "vN:B2/S12"):
+        spec = W.RULES[rule]
+        for bits in itertools.product((0, 1), repeat=f.cells):
+            st = np.array(bits, dtype=np.uint8)
+            want = brute.run_compact(fd.s, fd.offsets, r, list(bits), spec[0], spec[1], 1,
+                                     W.rule_neighbourhood(rule))
+            assert f.compact_steps(st, W.rule_mask(rule), 1).tolist() == want, rule
 
 
 @pytest.mark.parametrize("name,r", [("triangle", 6), ("carpet", 3), ("hfractal", 3),
                                     ("chandelier", 4)])
-@pytest.mark.parametrize("rule", ["B1357/S1357", "B1357/S02468"])
+@pytest.mark.parametrize("rule", ["B1357/S1357", "B1357/S02468", "vN:B13/S13", "vN:B13/S024"])
 def test_linear_rules_superpose(name, r, rule):
     # Both rules are linear over GF(2), so evolve(A xor B) = evolve(A) xor evolve(B).
     f = frac(name, r)
@@ -338,9 +342,11 @@ def test_linear_rules_superpose(name, r, rule):
 
 @pytest.mark.parametrize("name,r", [("triangle", 5), ("carpet", 3), ("hfractal", 3),
                                     ("chandelier", 3), ("cantor", 4)])
-def test_single_cell_impulse_under_replicator(name, r):
+@pytest.mark.parametrize("rule", ["B1357/S1357", "vN:B13/S13"])
+def test_single_cell_impulse_under_replicator(name, r, rule):
     f = frac(name, r)
-    rm = W.rule_mask("B1357/S1357")
+    rm = W.rule_mask(rule)
+    four = W.rule_neighbourhood(rule) == 4
     for i in range(0, f.cells, max(1, f.cells // 37)):
         st = np.zeros(f.cells, dtype=np.uint8)
         st[i] = 1
@@ -348,9 +354,32 @@ def test_single_cell_impulse_under_replicator(name, r):
         want = np.zeros(f.cells, dtype=np.uint8)
         for dy in (-1, 0, 1):
             for dx in (-1, 0, 1):
-                if (dx or dy) and f.member(x + dx, y + dy):
+                if (dx or dy) and not (four and dx and dy) and f.member(x + dx, y + dy):
                     want[f.nu(x + dx, y + dy)] = 1
         np.testing.assert_array_equal(f.compact_steps(st, rm, 1), want)
+
+
+@pytest.mark.parametrize("rule,offsets", [
+    ("vN:B13/S13", [(1, 0), (-1, 0), (0, 1), (0, -1)]),
+    ("B1357/S1357", [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if dx or dy])])
+def test_parity_rule_doubles_the_neighbourhood(rule, offsets):
+    # A parity rule is linear over GF(2) and its neighbourhood operator N
+    # satisfies N^2 = N(2x) mod 2 (cross terms pair up), so a single live cell
+    # in open space becomes, after 2^j generations, exactly the neighbourhood
+    # scaled by 2^j.  Textbook closed form, on the full square far from its
+    # edges.
+    f = frac("fullsquare", 5)
+    c = 16
+    box = np.zeros((f.n, f.n), dtype=np.uint8)
+    box[c, c] = 1
+    st = f.gather(box)
+    rm = W.rule_mask(rule)
+    for j in range(4):
+        out = f.expand(f.compact_steps(st, rm, 2 ** j))
+        want = np.zeros_like(box)
+        for dx, dy in offsets:
+            want[c + dy * 2 ** j, c + dx * 2 ** j] = 1
+        np.testing.assert_array_equal(out, want, err_msg=f"{rule} after {2 ** j} generations")
 
 
 def test_all_dead_stays_dead():
@@ -404,13 +433,15 @@ def test_init_threshold_boundary():
 
 
 @pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier", "cantor"])
-def test_cells_after_matches_full_steps(name):
+@pytest.mark.parametrize("rule", ["B3/S23", "vN:B2/S12"])
+def test_cells_after_matches_full_steps(name, rule):
     f = frac(name, min(max_level(name), 5))
     st = f.init_compact(31, 0.5)
+    rm = W.rule_mask(rule)
     idx = np.arange(0, f.cells, max(1, f.cells // 200))
     for steps in (0, 1, 2, 3):
-        np.testing.assert_array_equal(f.cells_after(st, idx, B3S23, steps),
-                                      f.compact_steps(st, B3S23, steps)[idx])
+        np.testing.assert_array_equal(f.cells_after(st, idx, rm, steps),
+                                      f.compact_steps(st, rm, steps)[idx])
 
 
 @pytest.mark.parametrize("name", ["triangle", "carpet", "hfractal", "chandelier"])
