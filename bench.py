@@ -292,6 +292,18 @@ def main():
         log(f"lambda approach: {msl / Kl * 1e3:.1f} us/step, same as box step: "
             f"{bbox['lambda_approach']['equals_box_step']}")
         del box, box2, resb, ref, resl
+        # the blocked layout (each tile stored as its S x S square)
+        if info.strategy != N.STRATEGY_DIRECT:
+            blk = g.to_blocked(init)
+            blk2 = torch.empty_like(blk)
+            refc = g.step_compact(init.clone(), torch.empty_like(init), Kl, rule)
+            msk, resk = time_events(torch, lambda: g.step_blocked(blk, blk2, Kl, rule))
+            bbox["blocked_layout"] = {"ms_per_step": msk / Kl, "steps": Kl, "bytes": blk.numel(),
+                                      "cell_updates_per_s": g.cells * Kl / (msk * 1e-3),
+                                      "equals_compact_step": bool(torch.equal(g.from_blocked(resk), refc))}
+            log(f"blocked layout: {msk / Kl * 1e3:.1f} us/step over {blk.numel()} B, same as compact: "
+                f"{bbox['blocked_layout']['equals_compact_step']}")
+            del blk, blk2, refc, resk
 
     # ---- the small case: launch-bound, eager launches against a HIP graph ------
     small = small_case(torch, N, W, rule)

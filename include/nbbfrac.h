@@ -205,6 +205,30 @@ nbb_status nbb_step_lambda(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_
                            uint64_t len, uint32_t steps, uint32_t rule, int *result_in_b,
                            void *stream);
 
+/*
+ * Blocked layout (section 3, blocked approach: the compact space as a packed
+ * collection of small bounding boxes, one per coarse cell).  With the
+ * descriptor's tiled plan at tile level m (S = s^m, k^(r-m) tiles), tile t is
+ * stored as its whole S x S square at bytes [t S^2, (t+1) S^2): cell (x, y)
+ * of the square at t S^2 + y S + x, positions outside the fractal 0.  Memory
+ * is (s^2/k)^m times the compact size; steps touch every position of every
+ * square.  Needs a TILED or TILED_WAVE plan (NBB_E_INVALID otherwise); the
+ * layout follows the plan, so nbb_configure changes it.
+ *   nbb_blocked_bytes: k^(r-m) S^2 (0 without a tiled plan).
+ *   nbb_blocked_from_compact / _to_compact: conversions; len is the blocked
+ *   length, the compact side is k^r bytes; blocked buffers 16-byte aligned.
+ *   nbb_step_blocked: generations on the blocked layout, arguments and
+ *   result buffer as nbb_step_compact (the input must hold 0 at
+ *   non-members; the output does too).
+ */
+uint64_t nbb_blocked_bytes(const nbb_fractal *f);
+nbb_status nbb_blocked_from_compact(const nbb_fractal *f, const uint8_t *compact, uint8_t *blocked,
+                                    uint64_t len, void *stream);
+nbb_status nbb_blocked_to_compact(const nbb_fractal *f, const uint8_t *blocked, uint64_t len,
+                                  uint8_t *compact, void *stream);
+nbb_status nbb_step_blocked(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                            uint32_t rule, int *result_in_b, void *stream);
+
 /* bbox[lambda(i)] = compact[i]; every other box byte becomes 0. */
 nbb_status nbb_expand(const nbb_fractal *f, const uint8_t *compact, uint8_t *bbox, uint64_t pitch,
                       uint64_t len, void *stream);

@@ -181,11 +181,12 @@ nbb_status upload_maps(nbb_fractal *F) {
 }
 
 nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TileParams *T) {
-    const void *src[5] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data()};
-    size_t bytes[5] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
-                       p.nbr.size() * 4};
-    void *dst[5];
-    nbb_status s = upload(blob, src, bytes, 5, dst);
+    const void *src[7] = {p.lut0p.data(), p.lut1.data(), p.halo_src.data(), p.halo_dst.data(), p.nbr.data(),
+                          p.blk_pos.data(), p.blk_mask.data()};
+    size_t bytes[7] = {p.lut0p.size() * 2, p.lut1.size() * 2, p.halo_src.size() * 4, p.halo_dst.size() * 4,
+                       p.nbr.size() * 4, p.blk_pos.size() * 4, p.blk_mask.size() * 4};
+    void *dst[7];
+    nbb_status s = upload(blob, src, bytes, 7, dst);
     if (s != NBB_OK) return s;
     *T = TileParams{};
     T->team = p.team;
@@ -212,6 +213,10 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->halo_src = static_cast<const uint32_t *>(dst[2]);
     T->halo_dst = static_cast<const uint32_t *>(dst[3]);
     T->nbr = static_cast<const uint32_t *>(dst[4]);
+    T->blk_pos = static_cast<const uint32_t *>(dst[5]);
+    T->blk_mask = static_cast<const uint32_t *>(dst[6]);
+    T->divK = make_udiv(p.K);
+    T->divS = make_udiv(p.S);
     std::memcpy(T->bid, p.bid, sizeof(T->bid));
     std::memcpy(T->pack01, p.pack01, sizeof(T->pack01));
     std::memcpy(T->pack23, p.pack23, sizeof(T->pack23));
@@ -921,6 +926,67 @@ nbb_status nbb_step_lambda(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_
     for (uint32_t i = 0; i < steps; ++i) {
         e = launch_step_lambda(F->mp, F->lam_words, in, out, pitch, rule, grid, s);
         if (e != hipSuccess) return hip_fail(e, "lambda step launch");
+        std::swap(in, out);
+    }
+    return NBB_OK;
+}
+
+uint64_t nbb_blocked_bytes(const nbb_fractal *F) {
+    if (!F || F->strategy == NBB_STRATEGY_DIRECT) return 0;
+    return F->tile.ntiles * uint64_t(F->tile.S) * F->tile.S;
+}
+
+static nbb_status check_blocked(const nbb_fractal *F, const void *blocked, uint64_t len) {
+    if (F->strategy == NBB_STRATEGY_DIRECT) return fail(NBB_E_INVALID, "the blocked layout needs a tiled plan");
+    if (!blocked) return fail(NBB_E_INVALID, "null argument");
+    if (len != nbb_blocked_bytes(F)) return fail(NBB_E_INVALID, "len must equal nbb_blocked_bytes");
+    if (!aligned16(blocked)) return fail(NBB_E_INVALID, "blocked state must be 16-byte aligned");
+    return NBB_OK;
+}
+
+nbb_status nbb_blocked_from_compact(const nbb_fractal *F, const uint8_t *compact, uint8_t *blocked, uint64_t len,
+                                    void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_blocked(F, blocked, len);
+    if (st != NBB_OK) return st;
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_fill_zero(blocked, len & ~uint64_t(15), s);
+    if (e == hipSuccess) e = launch_fill_tail(blocked + (len & ~uint64_t(15)), uint32_t(len & 15), s);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    return launched(launch_blocked_scatter(F->tp, compact, blocked, F->f.cells, map_grid(F, F->f.cells), s),
+                    "blocked scatter launch");
+}
+
+nbb_status nbb_blocked_to_compact(const nbb_fractal *F, const uint8_t *blocked, uint64_t len, uint8_t *compact,
+                                  void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_blocked(F, blocked, len);
+    if (st != NBB_OK) return st;
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_blocked_gather(F->tp, blocked, compact, F->f.cells, map_grid(F, F->f.cells),
+                                          static_cast<hipStream_t>(stream)),
+                    "blocked gather launch");
+}
+
+nbb_status nbb_step_blocked(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                            uint32_t rule, int *result_in_b, void *stream) {
+    if (!F || !a || !b) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_blocked(F, a, len);
+    if (st == NBB_OK) st = check_blocked(F, b, len);
+    if (st != NBB_OK) return st;
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (result_in_b) *result_in_b = int(steps & 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *in = a, *out = b;
+    for (uint32_t i = 0; i < steps; ++i) {
+        hipError_t e = launch_step_blocked(F->tp, in, out, rule, F->cu_count, s);
+        if (e != hipSuccess) return hip_fail(e, "blocked step launch");
         std::swap(in, out);
     }
     return NBB_OK;

@@ -375,6 +375,9 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4 *__restrict__ p, uint64
     for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n16; t += stride)
         p[t] = make_uint4(0, 0, 0, 0);
 }
+__global__ __launch_bounds__(64) void k_fill_tail(uint8_t *__restrict__ p, uint32_t n) {
+    if (threadIdx.x < n) p[threadIdx.x] = 0;
+}
 
 __global__ __launch_bounds__(512) void k_expand(MapParams P, uint32_t lam_words,
                                                 const uint8_t *__restrict__ compact,
@@ -667,6 +670,111 @@ __device__ __forceinline__ void block_store(const TileParams &T, const uint32_t 
         if (CB == 3) store_u16(p + 1, w[0] >> 8);
     } else {
         store_u8(p, w[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked layout (section 3, blocked approach: the compact space as a packed
+// collection of small bounding boxes): tile t of the tile plan is stored as
+// its whole S x S square at bytes [t S^2, (t+1) S^2), cell (x, y) of the
+// square at y S + x, positions outside the fractal 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_blocked_scatter(TileParams T, const uint8_t *__restrict__ compact,
+                                                         uint8_t *__restrict__ blocked, uint64_t cells) {
+    const uint64_t S2 = uint64_t(T.S) * T.S;
+    for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < cells; i += uint64_t(gridDim.x) * 256) {
+        const uint32_t t = udiv(T.divK, uint32_t(i));
+        const uint32_t j = uint32_t(i) - t * T.K;
+        blocked[t * S2 + T.blk_pos[j]] = compact[i];
+    }
+}
+__global__ __launch_bounds__(256) void k_blocked_gather(TileParams T, const uint8_t *__restrict__ blocked,
+                                                        uint8_t *__restrict__ compact, uint64_t cells) {
+    const uint64_t S2 = uint64_t(T.S) * T.S;
+    for (uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x; i < cells; i += uint64_t(gridDim.x) * 256) {
+        const uint32_t t = udiv(T.divK, uint32_t(i));
+        const uint32_t j = uint32_t(i) - t * T.K;
+        compact[i] = blocked[t * S2 + T.blk_pos[j]];
+    }
+}
+
+// One generation on the blocked layout: a work-group per tile copies the
+// tile's square and the facing rows, columns and corners of its eight
+// neighbour squares into an LDS box of (S+2) x W bytes, then every thread
+// evaluates the rule for four positions at a time (every position of the
+// square, the "micro brute force" inside the block) and writes them back,
+// member positions only.
+template <bool EDGE>
+__global__ __launch_bounds__(256) void k_step_blocked(TileParams T, const uint8_t *__restrict__ in,
+                                                      uint8_t *__restrict__ out, uint32_t rule, uint32_t W) {
+    extern __shared__ __align__(16) uint8_t bbox[];
+    const uint32_t S = T.S, nq = (S + 3) >> 2;
+    const uint64_t S2 = uint64_t(S) * S;
+    const RuleTables RT = rule_tables(rule);
+    const uint32_t W4 = W >> 2;
+    const uint32_t *box32 = reinterpret_cast<const uint32_t *>(bbox);
+    for (uint32_t o = threadIdx.x * 4; o < (S + 2) * W; o += 256 * 4) *reinterpret_cast<uint32_t *>(bbox + o) = 0;
+    __syncthreads();
+    for (uint64_t t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+        const uint8_t *src = in + t * S2;
+        for (uint32_t i = threadIdx.x; i < S * S; i += 256) {
+            const uint32_t y = udiv(T.divS, i), x = i - y * S;
+            bbox[(y + 1) * W + x + 1] = src[i];
+        }
+        // the ring: from the neighbour square in direction d (row-major over
+        // dy, dx in -1..1 without the centre), 0 where there is none
+        for (uint32_t h = threadIdx.x; h < 4 * S + 4; h += 256) {
+            int32_t rx, ry;                      // ring position in tile coordinates
+            if (h < S) { rx = int32_t(h); ry = -1; }
+            else if (h < 2 * S) { rx = int32_t(h - S); ry = int32_t(S); }
+            else if (h < 3 * S) { rx = -1; ry = int32_t(h - 2 * S); }
+            else if (h < 4 * S) { rx = int32_t(S); ry = int32_t(h - 3 * S); }
+            else { const uint32_t c = h - 4 * S; rx = (c & 1) ? int32_t(S) : -1; ry = (c & 2) ? int32_t(S) : -1; }
+            const int32_t dx = rx < 0 ? -1 : (rx >= int32_t(S) ? 1 : 0);
+            const int32_t dy = ry < 0 ? -1 : (ry >= int32_t(S) ? 1 : 0);
+            const uint32_t d = uint32_t((dy + 1) * 3 + (dx + 1));
+            const uint32_t nt = T.nbr[t * 8 + (d > 4 ? d - 1 : d)];
+            uint8_t v = 0;
+            if (nt != kOutside) {
+                const uint32_t lx = uint32_t(rx - dx * int32_t(S)), ly = uint32_t(ry - dy * int32_t(S));
+                v = in[uint64_t(nt) * S2 + uint64_t(ly) * S + lx];
+            }
+            bbox[uint32_t(ry + 1) * W + uint32_t(rx + 1)] = v;
+        }
+        __syncthreads();
+        uint8_t *dst = out + t * S2;
+        for (uint32_t o = threadIdx.x; o < S * nq; o += 256) {
+            const uint32_t y = o / nq, c = o - y * nq;   // row y, columns 4c .. 4c+3
+            uint32_t lo[3], hi[3], H[3], C[3];
+#pragma unroll
+            for (int rr = 0; rr < 3; ++rr) {
+                lo[rr] = box32[(y + rr) * W4 + c];
+                hi[rr] = box32[(y + rr) * W4 + c + 1];
+                C[rr] = alignbyte(hi[rr], lo[rr], 1);
+                H[rr] = lo[rr] + C[rr] + alignbyte(hi[rr], lo[rr], 2);
+            }
+            const uint32_t self = C[1];
+            const uint32_t n = EDGE ? C[0] + C[2] + lo[1] + alignbyte(hi[1], lo[1], 2) : H[0] + H[1] + H[2] - self;
+            uint32_t next;
+            if (RT.perm) {
+                const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
+                const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
+                const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, self);
+                next = (born & ~smask) | (surv & smask);
+            } else {
+                const uint32_t I = n + (self << 4);
+                next = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) next |= __builtin_amdgcn_ubfe(rule, I >> (8 * b), 1) << (8 * b);
+            }
+            next &= T.blk_mask[o];
+            uint8_t *p = dst + y * S + 4 * c;
+            const uint32_t nb = min(4u, S - 4 * c);
+            if (nb == 4) store_u32(p, next);
+            else
+                for (uint32_t b = 0; b < nb; ++b) p[b] = uint8_t(next >> (8 * b));
+        }
+        __syncthreads();
     }
 }
 
@@ -974,6 +1082,10 @@ hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t st) {
     if (n16) hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint4 *>(p), n16);
     return hipGetLastError();
 }
+hipError_t launch_fill_tail(void *p, uint32_t bytes, hipStream_t st) {
+    if (bytes) hipLaunchKernelGGL(k_fill_tail, dim3(1), dim3(64), 0, st, static_cast<uint8_t *>(p), bytes);
+    return hipGetLastError();
+}
 hipError_t launch_expand(const MapParams &P, uint32_t lam_words, const uint8_t *compact, uint8_t *box,
                          uint64_t pitch, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_expand, dim3(grid), dim3(512), lam_words * 4, st, P, lam_words, compact, box, pitch);
@@ -988,6 +1100,27 @@ hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t n
                               uint8_t *out, uint32_t rule, int grid, hipStream_t st) {
     const size_t lds = size_t(lam_words) * 4 + size_t(nu_halves) * 2;
     hipLaunchKernelGGL(k_step_direct, dim3(grid), dim3(512), lds, st, P, lam_words, nu_halves, in, out, rule);
+    return hipGetLastError();
+}
+hipError_t launch_blocked_scatter(const TileParams &T, const uint8_t *compact, uint8_t *blocked, uint64_t cells,
+                                  int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_blocked_scatter, dim3(grid), dim3(256), 0, st, T, compact, blocked, cells);
+    return hipGetLastError();
+}
+hipError_t launch_blocked_gather(const TileParams &T, const uint8_t *blocked, uint8_t *compact, uint64_t cells,
+                                 int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_blocked_gather, dim3(grid), dim3(256), 0, st, T, blocked, compact, cells);
+    return hipGetLastError();
+}
+hipError_t launch_step_blocked(const TileParams &T, const uint8_t *in, uint8_t *out, uint32_t rule, int cu_count,
+                               hipStream_t st) {
+    const uint32_t W = ((T.S + 2 + 3) & ~3u) + 4;  // dword rows; reads reach column 4 nq + 3
+    const size_t lds = size_t(T.S + 2) * W;
+    const uint64_t grid = std::min<uint64_t>(T.ntiles, uint64_t(cu_count) * 8);
+    if (rule >> 31)
+        hipLaunchKernelGGL(k_step_blocked<true>, dim3(uint32_t(grid)), dim3(256), lds, st, T, in, out, rule, W);
+    else
+        hipLaunchKernelGGL(k_step_blocked<false>, dim3(uint32_t(grid)), dim3(256), lds, st, T, in, out, rule, W);
     return hipGetLastError();
 }
 hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint8_t *in, uint8_t *out,

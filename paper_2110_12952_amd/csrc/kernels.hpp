@@ -20,13 +20,20 @@ hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, c
 hipError_t launch_init_compact(const MapParams &P, uint32_t lam_words, uint8_t *state, uint64_t seed,
                                uint32_t thr, int grid, hipStream_t st);
 hipError_t launch_init_box(const BoxParams &B, uint8_t *state, uint64_t seed, uint32_t thr, hipStream_t st);
-hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t st);
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t st);   // bytes / 16 chunks; p 16-aligned
+hipError_t launch_fill_tail(void *p, uint32_t bytes, hipStream_t st);   // bytes < 64, any alignment
 hipError_t launch_expand(const MapParams &P, uint32_t lam_words, const uint8_t *compact, uint8_t *box,
                          uint64_t pitch, int grid, hipStream_t st);
 hipError_t launch_gather(const MapParams &P, uint32_t lam_words, const uint8_t *box, uint64_t pitch,
                          uint8_t *compact, int grid, hipStream_t st);
 hipError_t launch_step_direct(const MapParams &P, uint32_t lam_words, uint32_t nu_halves, const uint8_t *in,
                               uint8_t *out, uint32_t rule, int grid, hipStream_t st);
+hipError_t launch_blocked_scatter(const TileParams &T, const uint8_t *compact, uint8_t *blocked, uint64_t cells,
+                                  int grid, hipStream_t st);
+hipError_t launch_blocked_gather(const TileParams &T, const uint8_t *blocked, uint8_t *compact, uint64_t cells,
+                                 int grid, hipStream_t st);
+hipError_t launch_step_blocked(const TileParams &T, const uint8_t *in, uint8_t *out, uint32_t rule, int cu_count,
+                               hipStream_t st);
 hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint8_t *in, uint8_t *out,
                               uint64_t pitch, uint32_t rule, int grid, hipStream_t st);
 // Persistent launch sized to the resident capacity of cu_count CUs.

@@ -79,6 +79,9 @@ struct TileParams {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;     // 8 neighbour tiles per tile (0xFFFFFFFF = none)
+    const uint32_t *blk_pos;   // blocked layout: y*S + x of local cell j
+    const uint32_t *blk_mask;  // blocked layout: member bytes per row and 4-column group
+    UDiv divK, divS;           // division by K and by S
     // v_perm selectors that gather a block's next states, one byte per
     // block position (row r in a dword, byte c = column c), into compact
     // order: output dword d = perm(row1, row0, pack01[d]) | perm(row3, row2,

@@ -365,6 +365,17 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     p->lut0p.assign(size_t(16) * p->lut0_stride, uint16_t(p->dummy));
     for (uint32_t ph = 0; ph < 16; ++ph)
         for (uint32_t i = 0; i < p->K; ++i) p->lut0p[size_t(ph) * p->lut0_stride + i + ph] = p->lut0[i];
+    p->blk_pos.resize(p->K);
+    {
+        const uint32_t nq = (p->S + 3) / 4;
+        p->blk_mask.assign(size_t(p->S) * nq, 0);
+        for (uint32_t i = 0; i < p->K; ++i) {
+            int64_t x, y;
+            lambda_levels(f, m, i, &x, &y);
+            p->blk_pos[i] = uint32_t(y * p->S + x);
+            p->blk_mask[size_t(y) * nq + x / 4] |= 1u << (8 * (x % 4));
+        }
+    }
     p->lut1.resize(p->nblk);
     for (uint32_t b = 0; b < p->nblk; ++b) {
         int64_t X, Y;

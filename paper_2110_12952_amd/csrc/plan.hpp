@@ -53,6 +53,10 @@ struct TilePlan {
     std::vector<uint16_t> lut1;
     std::vector<uint32_t> halo_src, halo_dst;
     std::vector<uint32_t> nbr;    // 8 per tile: nu_{r-m} of the neighbouring coarse coordinates
+    // Blocked layout (each tile stored as its S x S square): position y*S + x
+    // of local cell j, and per row y and 4-column group c a dword with byte b
+    // = 1 where (4c + b, y) is a fractal cell (S rows of ceil(S/4) dwords).
+    std::vector<uint32_t> blk_pos, blk_mask;
 };
 // True if the tiled step supports this fractal (2 <= s <= 4, r >= 1).
 bool tiled_supported(const Fractal &f);

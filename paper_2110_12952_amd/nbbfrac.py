@@ -104,6 +104,14 @@ def lib() -> ctypes.CDLL:
     L.nbb_step_bbox.restype = st
     L.nbb_step_lambda.argtypes = [vp, vp, vp, u64, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
     L.nbb_step_lambda.restype = st
+    L.nbb_blocked_bytes.argtypes = [vp]
+    L.nbb_blocked_bytes.restype = u64
+    L.nbb_blocked_from_compact.argtypes = [vp, vp, vp, u64, vp]
+    L.nbb_blocked_from_compact.restype = st
+    L.nbb_blocked_to_compact.argtypes = [vp, vp, u64, vp, vp]
+    L.nbb_blocked_to_compact.restype = st
+    L.nbb_step_blocked.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_step_blocked.restype = st
     L.nbb_expand.argtypes = [vp, vp, vp, u64, u64, vp]
     L.nbb_expand.restype = st
     L.nbb_gather.argtypes = [vp, vp, u64, vp, u64, vp]
@@ -297,6 +305,30 @@ class Fractal:
         pitch = a.shape[-1]
         _check(lib().nbb_step_lambda(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), pitch, a.numel(),
                                      int(steps), int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a
+
+    # ---- blocked layout (one S x S square per tile) ------------------------
+    def blocked_bytes(self) -> int:
+        return int(lib().nbb_blocked_bytes(self._h))
+
+    def to_blocked(self, compact, out=None, stream=None):
+        import torch
+        n = self.blocked_bytes()
+        blk = torch.empty(max(n, 1), dtype=torch.uint8, device=compact.device)[:n] if out is None else out
+        _check(lib().nbb_blocked_from_compact(self._h, _dev_ptr(compact, "uint8", self.cells), _dev_ptr(blk, "uint8"),
+                                              blk.numel(), _stream(stream)))
+        return blk
+
+    def from_blocked(self, blocked, out=None, stream=None):
+        c = self.new_compact() if out is None else out
+        _check(lib().nbb_blocked_to_compact(self._h, _dev_ptr(blocked, "uint8"), blocked.numel(),
+                                            _dev_ptr(c, "uint8", self.cells), _stream(stream)))
+        return c
+
+    def step_blocked(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        res = ctypes.c_int(0)
+        _check(lib().nbb_step_blocked(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
+                                      int(rule), ctypes.byref(res), _stream(stream)))
         return b if res.value else a
 
     def expand(self, compact, out=None, stream=None):

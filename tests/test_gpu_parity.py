@@ -315,6 +315,46 @@ def test_step_lambda_matches_box_step(N):
         g.step_lambda(a, a, 1)
 
 
+@pytest.mark.parametrize("name,r,m", [("triangle", 6, 3), ("triangle", 8, 7), ("carpet", 3, 2), ("hfractal", 3, 2),
+                                      ("chandelier", 4, 3), ("grid4_12", 3, 2), ("cantor", 6, 3), ("vicsek", 3, 2),
+                                      ("fullsquare", 5, 3), ("triangle", 3, 1)])
+def test_blocked_layout(N, name, r, m):
+    # the blocked layout: each tile stored as its whole S x S square
+    fd, o, g = pair(name, r, N)
+    g.configure(N.STRATEGY_TILED, m)
+    S, K, T = fd.s ** m, fd.k ** m, fd.k ** (r - m)
+    assert g.blocked_bytes() == T * S * S
+    st0 = o.init_compact(5 + r, 0.5)
+    fm = O.Fractal(fd.s, fd.offsets, m)
+    xs, ys = fm.lam_many(np.arange(K))
+    i = np.arange(o.cells)
+    pos = (i // K) * S * S + ys[i % K] * S + xs[i % K]
+    want = np.zeros(T * S * S, np.uint8)
+    want[pos] = st0
+    member = np.zeros(T * S * S, bool)
+    member[pos] = True
+    blk = g.to_blocked(dev(st0))
+    np.testing.assert_array_equal(host(blk), want)
+    np.testing.assert_array_equal(host(g.from_blocked(blk)), st0)
+    for rule in RULES:
+        rm = W.rule_mask(rule)
+        for steps in (1, 4):
+            a = g.to_blocked(dev(st0))
+            res = g.step_blocked(a, torch.full_like(a, 0xCD), steps, rm)
+            got = host(res)
+            assert not got[~member].any(), f"{rule}: a position outside the fractal came out alive"
+            np.testing.assert_array_equal(got[pos], o.compact_steps(st0, rm, steps),
+                                          err_msg=f"{name} r={r} m={m} {rule} steps={steps}")
+
+
+def test_blocked_layout_needs_a_tiled_plan(N):
+    fd, o, g = pair("carpet", 3, N)
+    g.configure(N.STRATEGY_DIRECT)
+    assert g.blocked_bytes() == 0
+    with pytest.raises(N.NbbError, match="tiled plan"):
+        g.to_blocked(g.new_compact(), out=torch.empty(64, dtype=torch.uint8, device="cuda"))
+
+
 def test_step_bbox_wider_pitch(N):
     fd, o, g = pair("hfractal", 4, N)
     pitch = g.pitch + 48
