@@ -197,7 +197,6 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->q = p.q;
     T->BS = p.BS;
     T->CB = p.CB;
-    T->cbmask = p.CB >= 32 ? 0xFFFFFFFFu : ((1u << p.CB) - 1u);
     T->nblk = p.nblk;
     T->box_bytes = p.box_bytes;
     T->lds_total = p.lds_total;
@@ -217,7 +216,6 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->blk_mask = static_cast<const uint32_t *>(dst[6]);
     T->divK = make_udiv(p.K);
     T->divS = make_udiv(p.S);
-    std::memcpy(T->bid, p.bid, sizeof(T->bid));
     std::memcpy(T->pack01, p.pack01, sizeof(T->pack01));
     std::memcpy(T->pack23, p.pack23, sizeof(T->pack23));
     return NBB_OK;

@@ -62,7 +62,6 @@ struct TileParams {
     uint32_t team;        // threads per tile: 256 (work-group) or 64 (wavefront)
     uint32_t m, S, K, W;
     uint32_t q, BS, CB;   // block level, block side s^q, cells per block k^q
-    uint32_t cbmask;      // (1 << CB) - 1
     uint32_t nblk;        // k^(m-q) blocks per tile
     uint32_t box_bytes;   // LDS box allocation
     uint32_t lds_total;   // LDS per team
@@ -87,7 +86,6 @@ struct TileParams {
     // order: output dword d = perm(row1, row0, pack01[d]) | perm(row3, row2,
     // pack23[d]); selector 12 gives a zero byte.
     uint32_t pack01[4], pack23[4];
-    uint8_t bid[16];      // position c + BS*row inside a block -> cell id in the block, 0xFF if none
 };
 
 // One instance of a batch (device table, sorted by tile0): its state starts
