@@ -253,3 +253,41 @@ def test_autotune_rejects_zero_steps(N):
     a, b = f.new_compact(), f.new_compact()
     with pytest.raises(N.NbbError, match="steps"):
         f.autotune(a, b, steps=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batch_random_fractals_vs_oracle(N, seed):
+    # seeded random NBB fractals (s in 2..4, any k), random levels and plans
+    # (automatic, a common level, one wavefront per tile where it fits)
+    rng = np.random.default_rng(500 + seed)
+    fds, rs, frs = [], [], []
+    for i in range(14):
+        fd = W.random_fractal(1000 * seed + i)
+        r = 1
+        while fd.k ** (r + 1) <= 20000 and r < 10:
+            r += 1
+        r = int(rng.integers(max(1, r - 2), r + 1))
+        f = N.Fractal(fd.s, fd.offsets, r)
+        choice = int(rng.integers(3))
+        if choice == 1 and f.info().strategy != N.STRATEGY_DIRECT:
+            f.configure(N.STRATEGY_TILED, max(1, min(r, 2)))
+        elif choice == 2 and f.info().strategy != N.STRATEGY_DIRECT:
+            try:
+                f.configure(N.STRATEGY_TILED_WAVE, max(1, min(r, 2)))
+            except N.NbbError:
+                pass
+        fds.append(fd)
+        rs.append(r)
+        frs.append(f)
+    batch = N.Batch(frs)
+    a, b = batch.new_arena(), batch.new_arena()
+    rule = W.rule_mask("B36/S23" if seed else "vN:B2/S12")
+    want = []
+    for i, (fd, r, f) in enumerate(zip(fds, rs, frs)):
+        f.init_compact(i, 0.5, out=batch.state(a, i))
+        o = O.Fractal(fd.s, fd.offsets, r)
+        want.append(o.compact_steps(o.init_compact(i, 0.5), rule, 5))
+    got = host(batch.step(a, b, 5, rule))
+    for i, f in enumerate(frs):
+        np.testing.assert_array_equal(got[batch.offsets[i]:batch.offsets[i] + f.cells], want[i],
+                                      err_msg=f"instance {i}: {fds[i]} r={rs[i]}")
