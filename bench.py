@@ -8,7 +8,8 @@ over the whole fractal (one kernel launch).  The same run also times the
 bounding-box step over the full 65,536^2 box (the paper's baseline) and the
 lambda / nu maps over all 43M indices, checks that the compact and box
 results agree, times the 512-instance batched workload against one launch
-per instance, serves Poisson-arriving requests for p50/p99 latency, and
+per instance (and its small instances run in LDS against the per-generation
+launches), serves Poisson-arriving requests for p50/p99 latency, and
 times the CPU oracle on a bounded sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -171,6 +172,36 @@ def batch_run(torch, N, W, args):
     out["roofline_frac"] = out["alg_gbps"] / HBM_PEAK_GBPS
     log(f"batch: {ms_step * 1e3:.1f} us/step, {out['cell_updates_per_s']:.3e} cell-updates/s, "
         f"{out['alg_gbps']:.0f} GB/s; one launch per instance {ms_seq / Ts * 1e3:.1f} us/step; same={same}")
+    out["small_instances"] = small_batch_run(torch, N, items, frs, init, batch, rule, Kb)
+    return out
+
+
+def small_batch_run(torch, N, items, frs, init, big_batch, rule, steps):
+    """The batch's small instances (those a work-group's LDS holds) on their
+    own: every generation in LDS, one launch for all of them, against the
+    per-generation group launches."""
+    idx = [i for i, f in enumerate(frs) if 2 * f.cells < 65536]
+    sub = [frs[i] for i in idx]
+    out = {"instances": len(idx), "cells": int(sum(f.cells for f in sub)), "steps": steps}
+    res = {}
+    for resident in (True, False):
+        bt = N.Batch(sub, resident=resident)
+        a, b = bt.new_arena(), bt.new_arena()
+        for j, i in enumerate(idx):
+            bt.state(a, j).copy_(big_batch.state(init, i))
+        a0 = a.clone()
+        bt.step(a, b, 2, rule)
+        a.copy_(a0)
+        ms, _ = time_events(torch, lambda: bt.step(a, b, steps, rule))
+        res[resident] = (b if steps & 1 else a).clone()
+        key = "lds_resident" if resident else "group_launches"
+        out[key] = {"us_per_step": ms / steps * 1e3, "cell_updates_per_s": out["cells"] * steps / (ms * 1e-3),
+                    "resident_instances": int(bt.info().resident), "groups": int(bt.info().groups)}
+        del bt
+    out["same"] = bool(torch.equal(res[True], res[False]))
+    out["speedup"] = out["group_launches"]["us_per_step"] / out["lds_resident"]["us_per_step"]
+    log(f"batch, {len(idx)} small instances alone: in LDS {out['lds_resident']['us_per_step']:.1f} us/step, "
+        f"group launches {out['group_launches']['us_per_step']:.1f} us/step, same={out['same']}")
     return out
 
 

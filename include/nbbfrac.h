@@ -262,7 +262,22 @@ nbb_status nbb_autotune(nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, ui
  * group and are stepped by one launch per generation over all their tiles
  * (configure a common tile level with nbb_configure to group instances of
  * different r); instances with the DIRECT strategy are stepped one launch
- * each.
+ * each.  Small tiled instances, those whose state fits one work-group's LDS
+ * twice over, with the tile boxes and the neighbour table (160 KiB on gfx950;
+ * e.g. up to 3^9 triangle or 7^5 H cells), and whose generation takes at most
+ * 8 passes of up to 4 tiles, may instead be stepped in LDS (by default when
+ * they hold at least 1/8 of the batch's tiled cells; see
+ * nbb_batch_create_ex): one work-group per instance runs all of the call's
+ * generations of it in one launch, with no global traffic between
+ * generations, at a tile level of its own (the one with the fewest passes;
+ * built with the descriptor on the first batch that needs it, and independent
+ * of nbb_configure).  These launches, one per plan, run on streams of a
+ * per-device pool of the library (4 streams, kept until the process ends)
+ * that are forked from `stream` at the start of each step call and joined
+ * back to it before the call's last enqueued work (so, seen from `stream`,
+ * the call's work is ordered as before).  Step calls on one batch
+ * share its small device tables: enqueue them from one host thread, and order
+ * calls made on different streams (an event) before the later one starts.
  *
  * nbb_batch_create: fractals[i] (may repeat) must outlive the batch and keep
  * their configuration while it exists; offsets[i] must be multiples of 16,
@@ -278,14 +293,23 @@ typedef struct {
     uint32_t instances;
     uint32_t groups;          /* one launch per generation each */
     uint32_t direct;          /* instances stepped by their own launch */
-    uint32_t reserved;
+    uint32_t resident;        /* instances stepped in LDS, all generations in one launch */
     uint64_t cells;           /* sum of k_i^r_i */
-    uint64_t tiles;           /* tiles over all groups */
+    uint64_t tiles;           /* tiles of all tiled instances (groups and resident) */
     uint64_t arena_bytes;     /* smallest arena: max(offset + cells) rounded up to 16 */
     uint64_t device_table_bytes;
 } nbb_batch_info;
 nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
                             void *stream, nbb_batch **out);
+/* As nbb_batch_create (flags 0: the default choice above), with flags:
+ * NBB_BATCH_NO_RESIDENT steps every tiled instance by the per-generation group
+ * launches, small ones included; NBB_BATCH_RESIDENT steps every small one in
+ * LDS, whatever its share of the cells.  NBB_E_INVALID for unknown flag bits
+ * or both flags. */
+#define NBB_BATCH_NO_RESIDENT 1u
+#define NBB_BATCH_RESIDENT 2u
+nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                               uint32_t flags, void *stream, nbb_batch **out);
 void nbb_batch_destroy(nbb_batch *batch);
 nbb_status nbb_batch_query(const nbb_batch *batch, nbb_batch_info *info);
 
@@ -294,7 +318,9 @@ nbb_status nbb_batch_query(const nbb_batch *batch, nbb_batch_info *info);
  * starting in arena a, alternating with arena b as nbb_step_compact does
  * (*result_in_b = steps & 1).  Both arenas must be 16-byte aligned, at least
  * arena_bytes long (arena_len), and must not overlap; bytes outside the
- * instances' ranges are neither read nor written.
+ * instances' ranges are neither read nor written.  Only the result is
+ * specified: an instance's range in the other arena holds some earlier
+ * generation (instances stepped in LDS leave it untouched).
  */
 nbb_status nbb_batch_step(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
                           uint32_t rule, int *result_in_b, void *stream);
@@ -305,8 +331,9 @@ nbb_status nbb_batch_step(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64
  * steps[i] > g, so instance i's result ends in b iff steps[i] is odd and an
  * instance with 0 steps is left untouched.  Within each group the step
  * counts must not increase in the order the instances were given to
- * nbb_batch_create (NBB_E_INVALID otherwise): list instances by decreasing
- * step count.  steps is a host array of nbb_batch_info.instances entries.
+ * nbb_batch_create (NBB_E_INVALID otherwise; instances stepped in LDS are
+ * exempt): list instances by decreasing step count.  steps is a host array of
+ * nbb_batch_info.instances entries.
  */
 nbb_status nbb_batch_step_each(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len,
                                const uint32_t *steps, uint32_t rule, void *stream);

@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <array>
+#include <functional>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -53,6 +56,14 @@ struct nbb_fractal {
     TileParams tp{};
     BoxParams bp{};
     uint32_t lam_words = 0, nu_halves = 0;
+    // Plan of the LDS-resident batch step, made on a batch's first use:
+    // 0 not tried yet, 1 built (res_tp, stepped res_teams tiles at a time),
+    // 2 none (the state does not fit, or would take too many passes).
+    mutable std::mutex res_mu;
+    mutable int res_state = 0;
+    mutable TileParams res_tp{};
+    mutable uint32_t res_teams = 1;
+    mutable DevBlob dres;
 };
 
 struct nbb_plan {
@@ -73,14 +84,38 @@ struct BatchDirect {
     uint64_t offset;
     uint32_t index;
 };
+// Small instances of one plan that run all their generations in LDS, one
+// work-group each, one launch per group.
+struct ResidentGroup {
+    TileParams tp;
+    const BatchInstance *inst = nullptr;  // device table, in `index` order
+    uint32_t *steps = nullptr;            // device: per-instance generation counts (nbb_batch_step_each)
+    std::vector<uint32_t> index;          // the instances (caller's numbering)
+    uint32_t teams = 1;                   // tiles per pass
+    uint32_t lds = 0;                     // LDS of the largest
+};
+// An instance is stepped in LDS only if a generation takes at most this many
+// passes (each about a microsecond: a tile scatter, the rule, two barriers):
+// beyond that the per-generation group launches are faster.
+constexpr uint32_t kResidentMaxPasses = 8;
+// Resident groups of different plans run on up to this many streams of a
+// per-device pool, so that they overlap each other (and the group launches).
+constexpr int kResidentStreams = 4;
 struct nbb_batch {
     int device = 0;
     int cu_count = 256;
     uint32_t count = 0;
     uint64_t cells = 0, tiles = 0, arena_bytes = 0;
     std::vector<BatchGroup> groups;
+    std::vector<ResidentGroup> resident;
     std::vector<BatchDirect> direct;
     DevBlob dtab;
+    // the resident launches run on streams of the device's pool, forked from
+    // and joined back to the caller's stream, so that they overlap the
+    // per-generation launches and each other
+    hipStream_t side[kResidentStreams] = {};
+    hipEvent_t fork = nullptr, join[kResidentStreams] = {};
+    int nside = 0;
 };
 
 namespace {
@@ -403,6 +438,7 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
 
 void nbb_destroy(nbb_fractal *F) {
     if (!F) return;
+    blob_free(&F->dres);
     blob_free(&F->dmap);
     blob_free(&F->dbox);
     blob_free(&F->dtile);
@@ -535,9 +571,103 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
 
 nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
                             void *stream, nbb_batch **out) {
+    return nbb_batch_create_ex(fractals, offsets, count, 0, stream, out);
+}
+
+// Most LDS one work-group may take on the current device.
+static uint32_t device_lds_per_group() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+        (void)hipGetLastError();
+        return 65536;
+    }
+    return uint32_t(std::min(v, 163840));
+}
+
+// The LDS-resident plan of F, built on first use and kept with F: the tile
+// level and tiles per pass with the fewest passes per generation (ties: the
+// larger level) among those whose boxes, two state copies and neighbour table
+// fit one work-group's LDS.  NULL if none does in kResidentMaxPasses passes.
+static const TileParams *resident_plan(const nbb_fractal *F, uint32_t *teams) {
+    std::lock_guard<std::mutex> lock(F->res_mu);
+    if (F->res_state == 0) {
+        F->res_state = 2;
+        const uint32_t budget = device_lds_per_group();
+        if (tiled_supported(F->f) && 2 * F->f.cells < budget) {
+            TilePlan best;
+            uint32_t best_passes = kResidentMaxPasses + 1, best_teams = 1;
+            for (uint32_t m = F->f.r; m >= 1; --m) {
+                TilePlan plan;
+                std::string msg;
+                if (!build_tile_plan(F->f, m, &plan, &msg, 256)) continue;
+                if (uint64_t(plan.ntiles) * plan.K != F->f.cells) continue;
+                TileParams probe{};
+                probe.K = plan.K;
+                probe.lds_total = plan.lds_total;
+                probe.halo_count = uint32_t(plan.halo_src.size());
+                probe.nblk = plan.nblk;
+                const uint32_t nt = uint32_t(plan.ntiles);
+                for (uint32_t t : {4u, 2u, 1u}) {
+                    if (t > nt && t > 1) continue;
+                    if (!resident_fits(probe, t) || resident_lds_bytes(probe, nt, t) > budget) continue;
+                    const uint32_t passes = (nt + t - 1) / t;
+                    if (passes < best_passes) {
+                        best = plan;
+                        best_passes = passes;
+                        best_teams = t;
+                    }
+                    break;  // more tiles per pass is never worse
+                }
+            }
+            if (best_passes <= kResidentMaxPasses &&
+                upload_tile(const_cast<nbb_fractal *>(F), best, &F->dres, &F->res_tp) == NBB_OK) {
+                F->res_teams = best_teams;
+                F->res_state = 1;
+            }
+        }
+    }
+    if (F->res_state != 1) return nullptr;
+    *teams = F->res_teams;
+    return &F->res_tp;
+}
+
+// The device's pool of streams for resident launches (created on first use,
+// kept until the process ends; default priority, non-blocking).
+static hipError_t resident_streams(int dev, hipStream_t (&out)[kResidentStreams]) {
+    static std::mutex mu;
+    static std::vector<std::array<hipStream_t, kResidentStreams>> pool;
+    std::lock_guard<std::mutex> lock(mu);
+    if (pool.size() <= size_t(dev)) pool.resize(dev + 1, std::array<hipStream_t, kResidentStreams>{});
+    for (int i = 0; i < kResidentStreams; ++i) {
+        if (!pool[dev][i]) {
+            hipError_t e = hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                pool[dev][i] = nullptr;
+                return e;
+            }
+        }
+        out[i] = pool[dev][i];
+    }
+    return hipSuccess;
+}
+
+static void batch_free(nbb_batch *B) {
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    for (hipEvent_t &j : B->join)
+        if (j) (void)hipEventDestroy(j);
+    blob_free(&B->dtab);
+    delete B;
+}
+
+nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                               uint32_t flags, void *stream, nbb_batch **out) {
     if (!out) return fail(NBB_E_INVALID, "out is NULL");
     *out = nullptr;
     if (count && (!fractals || !offsets)) return fail(NBB_E_INVALID, "null argument");
+    if ((flags & ~uint32_t(NBB_BATCH_NO_RESIDENT | NBB_BATCH_RESIDENT)) ||
+        flags == (NBB_BATCH_NO_RESIDENT | NBB_BATCH_RESIDENT))
+        return fail(NBB_E_INVALID, "unknown or conflicting batch flags");
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -577,39 +707,77 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         return x->strategy == y->strategy && a.team == b.team && a.m == b.m && a.W == b.W &&
                a.lds_total == b.lds_total && a.halo_count == b.halo_count;
     };
+    // Resident instances group by their resident plans.
+    auto same_resident = [](const nbb_fractal *x, const nbb_fractal *y) {
+        if (x->f.k != y->f.k || x->f.s != y->f.s) return false;
+        for (uint32_t j = 0; j < x->f.k; ++j)
+            if (x->f.ox[j] != y->f.ox[j] || x->f.oy[j] != y->f.oy[j]) return false;
+        const TileParams &a = x->res_tp, &b = y->res_tp;
+        return a.m == b.m && a.W == b.W && a.lds_total == b.lds_total && a.halo_count == b.halo_count;
+    };
     // Instances keep the caller's order inside each group (nbb_batch_step_each
     // relies on it).
-    std::vector<const nbb_fractal *> reps;
-    std::vector<std::vector<BatchInstance>> members;
-    std::vector<std::vector<uint32_t>> member_index;
+    struct Part {
+        std::vector<const nbb_fractal *> reps;
+        std::vector<std::vector<BatchInstance>> members;
+        std::vector<std::vector<uint32_t>> index;
+        void add(const nbb_fractal *F, uint32_t i, const BatchInstance &I,
+                 const std::function<bool(const nbb_fractal *, const nbb_fractal *)> &same) {
+            size_t g = 0;
+            while (g < reps.size() && !same(reps[g], F)) ++g;
+            if (g == reps.size()) {
+                reps.push_back(F);
+                members.emplace_back();
+                index.emplace_back();
+            }
+            index[g].push_back(i);
+            members[g].push_back(I);
+        }
+    } launch, res;
+    // Small instances go to LDS when asked to, or by default when they hold
+    // at least 1/8 of the tiled cells: beside a few large instances they are
+    // cheap in the group launches, while a long resident launch takes issue
+    // slots from every generation of those.
+    bool use_resident = false;
+    if (!(flags & NBB_BATCH_NO_RESIDENT)) {
+        uint64_t tiled = 0, small = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            const nbb_fractal *F = fractals[i];
+            if (F->strategy == NBB_STRATEGY_DIRECT) continue;
+            uint32_t teams = 0;
+            tiled += F->f.cells;
+            if (resident_plan(F, &teams)) small += F->f.cells;
+        }
+        use_resident = (flags & NBB_BATCH_RESIDENT) ? small > 0 : (small && 8 * small >= tiled);
+    }
     for (uint32_t i = 0; i < count; ++i) {
         const nbb_fractal *F = fractals[i];
         if (F->strategy == NBB_STRATEGY_DIRECT) {
             B->direct.push_back({F, offsets[i], i});
             continue;
         }
-        size_t g = 0;
-        while (g < reps.size() && !same_plan(reps[g], F)) ++g;
-        if (g == reps.size()) {
-            reps.push_back(F);
-            members.emplace_back();
-            member_index.emplace_back();
-        }
-        member_index[g].push_back(i);
+        uint32_t teams = 0;
+        const TileParams *rp = use_resident ? resident_plan(F, &teams) : nullptr;
+        const TileParams &tp = rp ? *rp : F->tp;
         BatchInstance I{};
-        I.nbr = F->tp.nbr;
+        I.nbr = tp.nbr;
         I.base16 = uint32_t(offsets[i] >> 4);
-        I.ntiles = F->tp.ntiles;
+        I.ntiles = tp.ntiles;
         I.tail_partial = (F->f.cells & 15) ? 1u : 0u;
-        members[g].push_back(I);
+        if (rp)
+            res.add(F, i, I, same_resident);
+        else
+            launch.add(F, i, I, same_plan);
     }
     // One device allocation: per group the instance table, the records
-    // (2 words per tile) and the neighbour table (8 words per tile).
-    std::vector<size_t> off_inst(reps.size()), off_rec(reps.size()), off_nbr(reps.size()), ntiles(reps.size());
+    // (2 words per tile) and the neighbour table (8 words per tile); per
+    // resident group its instance table.
+    const size_t ng = launch.reps.size(), nr = res.reps.size();
+    std::vector<size_t> off_inst(ng), off_rec(ng), off_nbr(ng), ntiles(ng), off_res(nr);
     size_t total = 0;
-    for (size_t g = 0; g < reps.size(); ++g) {
+    for (size_t g = 0; g < ng; ++g) {
         uint64_t t = 0;
-        for (BatchInstance &I : members[g]) {
+        for (BatchInstance &I : launch.members[g]) {
             I.tile0 = uint32_t(t);
             t += I.ntiles;
         }
@@ -620,11 +788,19 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
         ntiles[g] = t;
         B->tiles += t;
         off_inst[g] = total;
-        total += align256(members[g].size() * sizeof(BatchInstance));
+        total += align256(launch.members[g].size() * sizeof(BatchInstance));
         off_rec[g] = total;
         total += align256(std::max<size_t>(t * 8, 1));
         off_nbr[g] = total;
         total += align256(std::max<size_t>(t * 32, 1));
+    }
+    std::vector<size_t> off_rsteps(nr);
+    for (size_t g = 0; g < nr; ++g) {
+        for (const BatchInstance &I : res.members[g]) B->tiles += I.ntiles;
+        off_res[g] = total;
+        total += align256(res.members[g].size() * sizeof(BatchInstance));
+        off_rsteps[g] = total;
+        total += align256(res.members[g].size() * sizeof(uint32_t));
     }
     if (total) {
         e = hipMalloc(&B->dtab.ptr, total);
@@ -638,41 +814,78 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(B->dtab.ptr);
-    for (size_t g = 0; g < reps.size(); ++g) {
+    for (size_t g = 0; g < ng; ++g) {
         auto *inst = reinterpret_cast<BatchInstance *>(base + off_inst[g]);
         auto *rec = reinterpret_cast<uint32_t *>(base + off_rec[g]);
         auto *nbr = reinterpret_cast<uint32_t *>(base + off_nbr[g]);
-        e = hipMemcpyAsync(inst, members[g].data(), members[g].size() * sizeof(BatchInstance),
+        e = hipMemcpyAsync(inst, launch.members[g].data(), launch.members[g].size() * sizeof(BatchInstance),
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table goes out of scope
         if (e == hipSuccess)
-            e = launch_batch_tiles(inst, uint32_t(members[g].size()), uint32_t(ntiles[g]), rec, nbr, s);
+            e = launch_batch_tiles(inst, uint32_t(launch.members[g].size()), uint32_t(ntiles[g]), rec, nbr, s);
         if (e != hipSuccess) {
-            blob_free(&B->dtab);
-            delete B;
+            batch_free(B);
             return hip_fail(e, "batch table build");
         }
         BatchGroup G;
-        G.tp = reps[g]->tp;
+        G.tp = launch.reps[g]->tp;
         G.tp.nbr = nbr;
         G.tp.ntiles = uint32_t(ntiles[g]);
         G.tp.cells = 0;  // per instance, from the records
         G.rec = rec;
-        G.index = member_index[g];
+        G.index = launch.index[g];
         uint64_t acc = 0;
-        for (const BatchInstance &I : members[g]) G.tiles_end.push_back(acc += I.ntiles);
+        for (const BatchInstance &I : launch.members[g]) G.tiles_end.push_back(acc += I.ntiles);
         B->groups.push_back(std::move(G));
-        B->cu_count = reps[g]->cu_count;
+        B->cu_count = launch.reps[g]->cu_count;
+    }
+    const uint32_t lds_budget = nr ? device_lds_per_group() : 0;
+    for (size_t g = 0; g < nr; ++g) {
+        auto *inst = reinterpret_cast<BatchInstance *>(base + off_res[g]);
+        e = hipMemcpyAsync(inst, res.members[g].data(), res.members[g].size() * sizeof(BatchInstance),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            batch_free(B);
+            return hip_fail(e, "batch table build");
+        }
+        ResidentGroup R;
+        R.tp = res.reps[g]->res_tp;
+        R.inst = inst;
+        R.steps = reinterpret_cast<uint32_t *>(base + off_rsteps[g]);
+        R.index = res.index[g];
+        // tiles per pass: as many (up to 4) as the registers and LDS allow
+        // for the group's largest instance
+        uint32_t most = 1;
+        for (const BatchInstance &I : res.members[g]) most = std::max(most, I.ntiles);
+        R.teams = 1;
+        for (uint32_t t : {4u, 2u})
+            if (t <= most && resident_fits(R.tp, t) && resident_lds_bytes(R.tp, most, t) <= lds_budget) {
+                R.teams = t;
+                break;
+            }
+        R.lds = resident_lds_bytes(R.tp, most, R.teams);
+        B->resident.push_back(std::move(R));
     }
     for (const BatchDirect &d : B->direct) B->cu_count = d.f->cu_count;
+    // side streams unless one resident group is all there is
+    if (!B->resident.empty() && (B->resident.size() > 1 || !B->groups.empty() || !B->direct.empty())) {
+        B->nside = int(std::min<size_t>(B->resident.size(), kResidentStreams));
+        e = resident_streams(dev, B->side);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
+        for (int i = 0; i < B->nside && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&B->join[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            batch_free(B);
+            return hip_fail(e, "batch streams");
+        }
+    }
     *out = B;
     return NBB_OK;
 }
 
 void nbb_batch_destroy(nbb_batch *B) {
-    if (!B) return;
-    blob_free(&B->dtab);
-    delete B;
+    if (B) batch_free(B);
 }
 
 nbb_status nbb_batch_query(const nbb_batch *B, nbb_batch_info *info) {
@@ -681,11 +894,55 @@ nbb_status nbb_batch_query(const nbb_batch *B, nbb_batch_info *info) {
     info->instances = B->count;
     info->groups = uint32_t(B->groups.size());
     info->direct = uint32_t(B->direct.size());
+    for (const ResidentGroup &R : B->resident) info->resident += uint32_t(R.index.size());
     info->cells = B->cells;
     info->tiles = B->tiles;
     info->arena_bytes = B->arena_bytes;
     info->device_table_bytes = B->dtab.bytes;
     return NBB_OK;
+}
+
+// Enqueues the resident groups (instance i of the batch takes steps[i]
+// generations, or steps_all if steps is NULL): on the caller's stream if
+// nothing else runs, else on the batch's side stream, forked from it here;
+// batch_join_resident joins it back.  One launch per group: the per-instance
+// counts go to the group's device array first.
+static hipError_t batch_fork_resident(const nbb_batch *B, uint8_t *a, uint8_t *b, uint32_t rule,
+                                      const uint32_t *steps, uint32_t steps_all, hipStream_t s) {
+    if (B->resident.empty()) return hipSuccess;
+    if (B->nside) {
+        hipError_t e = hipEventRecord(B->fork, s);
+        for (int i = 0; i < B->nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(B->side[i], B->fork, 0);
+        if (e != hipSuccess) return e;
+    }
+    std::vector<uint32_t> n;
+    for (size_t g = 0; g < B->resident.size(); ++g) {
+        const ResidentGroup &R = B->resident[g];
+        hipStream_t rs = B->nside ? B->side[g % B->nside] : s;
+        const uint32_t count = uint32_t(R.index.size());
+        const uint32_t *steps_of = nullptr;
+        if (steps) {
+            n.resize(count);
+            for (uint32_t j = 0; j < count; ++j) n[j] = steps[R.index[j]];
+            hipError_t e = launch_set_words(R.steps, n.data(), count, rs);
+            if (e != hipSuccess) return e;
+            steps_of = R.steps;
+        }
+        hipError_t e = launch_step_resident(R.tp, R.inst, count, steps_of, steps_all, R.teams, R.lds, a, b, rule, rs);
+        if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < B->nside; ++i) {
+        hipError_t e = hipEventRecord(B->join[i], B->side[i]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+static hipError_t batch_join_resident(const nbb_batch *B, hipStream_t s) {
+    for (int i = 0; i < B->nside; ++i) {
+        hipError_t e = hipStreamWaitEvent(s, B->join[i], 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
@@ -701,7 +958,10 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != B->device) return fail(NBB_E_INVALID, "batch belongs to another device");
     if (result_in_b) *result_in_b = int(steps & 1);
+    if (!steps) return NBB_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    e = batch_fork_resident(B, a, b, rule, nullptr, steps, s);
+    if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
     uint8_t *in = a, *out = b;
     for (uint32_t i = 0; i < steps; ++i) {
         for (const BatchGroup &G : B->groups) {
@@ -716,7 +976,8 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
         }
         std::swap(in, out);
     }
-    return NBB_OK;
+    e = batch_join_resident(B, s);
+    return e == hipSuccess ? NBB_OK : hip_fail(e, "batch resident join");
 }
 
 nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len,
@@ -743,6 +1004,13 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     // than g steps; instance i's state alternates a -> b -> a ... like the
     // whole batch's, so its result ends in b iff steps[i] is odd.
     hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t most_res = 0;
+    for (const ResidentGroup &R : B->resident)
+        for (uint32_t i : R.index) most_res = std::max(most_res, steps[i]);
+    if (most_res) {
+        e = batch_fork_resident(B, a, b, rule, steps, 0, s);
+        if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
+    }
     std::vector<size_t> live(B->groups.size());
     for (size_t k = 0; k < B->groups.size(); ++k) live[k] = B->groups[k].index.size();
     uint8_t *in = a, *out = b;
@@ -764,6 +1032,10 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
             if (e != hipSuccess) return hip_fail(e, "batch direct step launch");
         }
         std::swap(in, out);
+    }
+    if (most_res) {
+        e = batch_join_resident(B, s);
+        if (e != hipSuccess) return hip_fail(e, "batch resident join");
     }
     return NBB_OK;
 }

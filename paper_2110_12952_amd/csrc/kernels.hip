@@ -961,6 +961,146 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 }
 
 // ---------------------------------------------------------------------------
+// Batched step, LDS-resident form for small instances: work-group w owns
+// instance w of the launch (steps_of[w] generations, or steps_all for every
+// instance if steps_of is NULL) and runs all of them without touching
+// global memory in between.  LDS holds `teams` tile boxes, two copies of the
+// instance's state (this generation and the next; tile t at bytes
+// [t Kp, t Kp + K), Kp = K rounded up to 16, so every tile starts a 16-byte
+// chunk and the phase-0 scatter table serves all of them) and the
+// instance's neighbour table.  The work-group splits into `teams` teams of
+// 256 / teams threads; per generation the tiles go through in passes of
+// `teams` tiles (team j takes tile pass * teams + j), each pass the two
+// phases of the tiled step: scatter the tile and its halo from LDS into the
+// team's box, then the rule per block with the block's next states written
+// in compact order into the other copy.  A thread's scatter offsets, halo
+// entries and block corners are the same for every tile and generation, so
+// they are loaded once into registers (at most 2 chunks, 4 halo cells and
+// 4 blocks per thread; the launcher picks `teams` so they fit).  The final
+// state goes to `a` if the instance's generation count is even, else to `b`
+// (like the launch-per-generation form, whose ping-pong ends there).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kResCPT = 2, kResHPT = 4, kResBPT = 4;
+template <int BS, bool EDGE>
+__global__ __launch_bounds__(256) void k_step_resident(TileParams T, const BatchInstance *__restrict__ inst,
+                                                       const uint32_t *__restrict__ steps_of, uint32_t steps_all,
+                                                       uint32_t teams, uint8_t *__restrict__ a,
+                                                       uint8_t *__restrict__ b, uint32_t rule) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint32_t steps = steps_of ? steps_of[blockIdx.x] : steps_all;
+    if (!steps) return;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tsize = 256 / teams;
+    const uint32_t team = tid / tsize, lt = tid % tsize;
+    const BatchInstance I = inst[blockIdx.x];
+    const uint32_t K = T.K, Kp = (K + 15) & ~15u, nt = I.ntiles;
+    const uint32_t cells = nt * K;
+    uint8_t *box = lds + team * T.lds_total;
+    uint8_t *cur = lds + teams * T.lds_total;
+    uint8_t *nxt = cur + nt * Kp;
+    uint32_t *nbrL = reinterpret_cast<uint32_t *>(nxt + nt * Kp);
+    const uint64_t base = uint64_t(I.base16) << 4;
+
+    for (uint32_t o = tid * 16; o < teams * T.lds_total; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(lds + o) = make_uint4(0, 0, 0, 0);
+    for (uint32_t i = tid; i < nt * 8; i += 256) nbrL[i] = I.nbr[i];
+    const uint8_t *gin = a + base;
+    for (uint32_t i = tid; i < cells; i += 256) {
+        const uint32_t t = udiv(T.divK, i);
+        cur[t * Kp + (i - t * K)] = gin[i];
+    }
+    const uint32_t nchunks = Kp >> 4;
+    uint4 e[kResCPT][2];
+#pragma unroll
+    for (uint32_t j = 0; j < kResCPT; ++j) {
+        const uint32_t c = min(lt + tsize * j, nchunks - 1);
+        e[j][0] = *reinterpret_cast<const uint4 *>(T.lut0p + 16 * c);
+        e[j][1] = *reinterpret_cast<const uint4 *>(T.lut0p + 16 * c + 8);
+    }
+    uint32_t hsrc[kResHPT], hdst[kResHPT], blk[kResBPT];
+#pragma unroll
+    for (uint32_t j = 0; j < kResHPT; ++j) {
+        const uint32_t h = lt + tsize * j;
+        const bool ok = h < T.halo_count;
+        hsrc[j] = ok ? T.halo_src[h] : kOutside;
+        hdst[j] = ok ? T.halo_dst[h] : T.dummy;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kResBPT; ++j) blk[j] = T.lut1[min(lt + tsize * j, T.nblk - 1)];
+    const RuleTables RT = rule_tables(rule);
+    const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
+    const uint32_t W4 = T.W >> 2;
+    __syncthreads();
+
+    for (uint32_t g = 0; g < steps; ++g) {
+        for (uint32_t t0 = 0; t0 < nt; t0 += teams) {
+            const uint32_t t = t0 + team;
+            const bool active = t < nt;
+            // 1. the tile and its halo into the team's box (offsets past the
+            //    tile's K cells point at the never-read byte)
+            if (active) {
+                const uint8_t *ct = cur + t * Kp;
+#pragma unroll
+                for (uint32_t j = 0; j < kResCPT; ++j) {
+                    const uint32_t c = lt + tsize * j;
+                    if (c < nchunks) {
+                        const uint4 v4 = *reinterpret_cast<const uint4 *>(ct + 16 * c);
+                        const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+                        const uint32_t ee[8] = {e[j][0].x, e[j][0].y, e[j][0].z, e[j][0].w,
+                                                e[j][1].x, e[j][1].y, e[j][1].z, e[j][1].w};
+#pragma unroll
+                        for (int k = 0; k < 16; ++k)
+                            box[(ee[k >> 1] >> (16 * (k & 1))) & 0xFFFFu] = uint8_t(v[k >> 2] >> (8 * (k & 3)));
+                    }
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < kResHPT; ++j) {
+                    const uint32_t src = hsrc[j];
+                    const uint32_t ntile = src != kOutside ? nbrL[t * 8 + (src >> 29)] : kOutside;
+                    box[hdst[j]] = ntile != kOutside ? cur[ntile * Kp + (src & 0x1FFFFFFFu)] : uint8_t(0);
+                }
+            }
+            __syncthreads();
+            // 2. the rule per block; block bi's CB next states go to cells
+            //    [bi CB, (bi + 1) CB) of the tile in the other copy
+            if (active) {
+                uint8_t *tout = nxt + t * Kp;
+#pragma unroll
+                for (uint32_t j = 0; j < kResBPT; ++j) {
+                    const uint32_t bi = lt + tsize * j;
+                    if (bi < T.nblk) {
+                        uint32_t next[4];
+                        if (RT.perm)
+                            block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
+                        else
+                            block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
+                        uint32_t w[4];
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            w[d] = __builtin_amdgcn_perm(next[1], next[0], T.pack01[d]);
+                            if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], T.pack23[d]);
+                        }
+                        uint8_t *p = tout + bi * T.CB;
+#pragma unroll
+                        for (uint32_t k = 0; k < 16; ++k)
+                            if (k < T.CB) p[k] = uint8_t(w[k >> 2] >> (8 * (k & 3)));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        uint8_t *sw = cur;
+        cur = nxt;
+        nxt = sw;
+    }
+    uint8_t *gout = (steps & 1 ? b : a) + base;
+    for (uint32_t i = tid; i < cells; i += 256) {
+        const uint32_t t = udiv(T.divK, i);
+        gout[i] = cur[t * Kp + (i - t * K)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Bounding-box step (section 4, method 1): every cell of the n x n box is
 // visited.  A thread owns 16 consecutive columns and walks down a band of
 // rows, keeping the horizontal 3-sums of three rows in registers, so each
@@ -1209,6 +1349,54 @@ hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint
 hipError_t launch_step_tiled_batch(const TileParams &T, const uint32_t *rec, const uint8_t *arena_in,
                                    uint8_t *arena_out, uint32_t rule, int cu_count, hipStream_t st) {
     return launch_tiled_any<true>(MapParams{}, T, arena_in, arena_out, rule, rec, cu_count, st);
+}
+uint32_t resident_lds_bytes(const TileParams &T, uint32_t ntiles, uint32_t teams) {
+    const uint64_t Kp = (T.K + 15) & ~15u;
+    const uint64_t n = uint64_t(teams) * T.lds_total + 2 * ntiles * Kp + 32 * uint64_t(ntiles);
+    return n > 0xFFFFFFFFu ? 0xFFFFFFFFu : uint32_t(n);
+}
+bool resident_fits(const TileParams &T, uint32_t teams) {
+    const uint32_t tsize = 256 / teams;
+    const uint32_t nchunks = (T.K + 15) >> 4;
+    return teams && 256 % teams == 0 && nchunks <= kResCPT * tsize && T.halo_count <= kResHPT * tsize &&
+           T.nblk <= kResBPT * tsize;
+}
+template <int BS, bool EDGE>
+static hipError_t launch_resident_t(const TileParams &T, const BatchInstance *inst, uint32_t count,
+                                    const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
+                                    uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st) {
+    hipLaunchKernelGGL((k_step_resident<BS, EDGE>), dim3(count), dim3(256), lds, st, T, inst, steps_of, steps_all,
+                       teams, a, b, rule);
+    return hipGetLastError();
+}
+hipError_t launch_step_resident(const TileParams &T, const BatchInstance *inst, uint32_t count,
+                                const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
+                                uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st) {
+    if (!count) return hipSuccess;
+    if (!resident_fits(T, teams)) return hipErrorInvalidValue;
+    const bool edge = (rule >> 31) != 0;
+#define NBB_RES(BS_, E_) launch_resident_t<BS_, E_>(T, inst, count, steps_of, steps_all, teams, lds, a, b, rule, st)
+    switch (T.BS) {
+        case 2: return edge ? NBB_RES(2, true) : NBB_RES(2, false);
+        case 3: return edge ? NBB_RES(3, true) : NBB_RES(3, false);
+        case 4: return edge ? NBB_RES(4, true) : NBB_RES(4, false);
+        default: return hipErrorInvalidValue;
+    }
+#undef NBB_RES
+}
+__global__ __launch_bounds__(256) void k_set_words(uint32_t *__restrict__ dst, WordChunk w, uint32_t n) {
+    if (threadIdx.x < n) dst[threadIdx.x] = w.v[threadIdx.x];
+}
+hipError_t launch_set_words(uint32_t *dst, const uint32_t *src, uint32_t n, hipStream_t st) {
+    for (uint32_t i = 0; i < n; i += kWordChunk) {
+        WordChunk w{};
+        const uint32_t m = std::min(kWordChunk, n - i);
+        for (uint32_t j = 0; j < m; ++j) w.v[j] = src[i + j];
+        hipLaunchKernelGGL(k_set_words, dim3(1), dim3(kWordChunk), 0, st, dst + i, w, m);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 // One thread per batch tile: find the instance holding batch tile g (the
 // last one whose first tile is <= g) and write the tile's record and its

@@ -43,6 +43,24 @@ hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint
 // T.ntiles = batch tiles, T.nbr = the batch neighbour table).
 hipError_t launch_step_tiled_batch(const TileParams &T, const uint32_t *rec, const uint8_t *arena_in,
                                    uint8_t *arena_out, uint32_t rule, int cu_count, hipStream_t st);
+// LDS bytes the LDS-resident batch step needs for an instance of `ntiles`
+// tiles of plan T stepped by `teams` tiles at a time (boxes, two state
+// copies, neighbour table).
+uint32_t resident_lds_bytes(const TileParams &T, uint32_t ntiles, uint32_t teams);
+// Whether a tile of plan T fits the per-thread registers of the resident step
+// when a work-group works on `teams` (1, 2 or 4) tiles at a time.
+bool resident_fits(const TileParams &T, uint32_t teams);
+// All generations of `count` small instances of plan T, one work-group each
+// (inst: device table; instance w takes steps_of[w] generations, a device
+// array, or steps_all if steps_of is NULL; `teams` tiles at a time; lds =
+// resident_lds_bytes of the largest).  Instance w's result ends in a if its
+// generation count is even, else in b.
+hipError_t launch_step_resident(const TileParams &T, const BatchInstance *inst, uint32_t count,
+                                const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
+                                uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st);
+// Stores n host words at dst (device) in stream order, through kernels that
+// take them as arguments (no host memory is read after the call returns).
+hipError_t launch_set_words(uint32_t *dst, const uint32_t *src, uint32_t n, hipStream_t st);
 // Builds the per-tile record and neighbour tables of a batch on the device.
 hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_t total, uint32_t *rec,
                               uint32_t *nbr, hipStream_t st);

@@ -99,6 +99,12 @@ struct BatchInstance {
     uint32_t tail_partial;  // 1 if k^r is not a multiple of 16
 };
 
+// Up to 256 words passed by value to a kernel that stores them.
+constexpr uint32_t kWordChunk = 256;
+struct WordChunk {
+    uint32_t v[kWordChunk];
+};
+
 // The bounding-box step.  Membership splits into the low L levels (an
 // SL x SL bitmap, SL = s^L, one row of LW words per y) and the high r - L
 // levels (an NH x NH byte map, NH = s^(r-L)).

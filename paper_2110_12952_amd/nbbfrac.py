@@ -24,6 +24,8 @@ NBB_OK, NBB_E_INVALID, NBB_E_RANGE, NBB_E_NOMEM, NBB_E_DEVICE = range(5)
 NBB_OUTSIDE = 0xFFFFFFFF
 NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
 NBB_RULE_VON_NEUMANN = 1 << 31
+NBB_BATCH_NO_RESIDENT = 1  # nbb_batch_create_ex: small instances stepped by the group launches too
+NBB_BATCH_RESIDENT = 2     # nbb_batch_create_ex: every small instance stepped in LDS
 STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE = 0, 1, 2, 3
 MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 
@@ -60,7 +62,7 @@ class PlanView(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("instances", ctypes.c_uint32), ("groups", ctypes.c_uint32), ("direct", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("cells", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+                ("resident", ctypes.c_uint32), ("cells", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
                 ("arena_bytes", ctypes.c_uint64), ("device_table_bytes", ctypes.c_uint64)]
 
 
@@ -120,6 +122,8 @@ def lib() -> ctypes.CDLL:
     L.nbb_autotune.restype = st
     L.nbb_batch_create.argtypes = [vp, vp, u32, vp, ctypes.POINTER(vp)]
     L.nbb_batch_create.restype = st
+    L.nbb_batch_create_ex.argtypes = [vp, vp, u32, u32, vp, ctypes.POINTER(vp)]
+    L.nbb_batch_create_ex.restype = st
     L.nbb_batch_destroy.argtypes = [vp]
     L.nbb_batch_destroy.restype = None
     L.nbb_batch_query.argtypes = [vp, ctypes.POINTER(BatchInfo)]
@@ -382,9 +386,12 @@ class Batch:
     Instance i is the fractal fractals[i] with its state at byte offsets[i] of
     each arena (default: packed one after another).  The descriptors must stay
     alive and keep their configuration while the batch exists; the batch
-    holds references to them."""
+    holds references to them.  resident: None = the library's choice, True =
+    every small instance runs all generations in LDS, False = small instances
+    go through the per-generation group launches like the rest."""
 
-    def __init__(self, fractals: Sequence[Fractal], offsets: Optional[Sequence[int]] = None, stream=None):
+    def __init__(self, fractals: Sequence[Fractal], offsets: Optional[Sequence[int]] = None, stream=None,
+                 resident: Optional[bool] = None):
         self.fractals = list(fractals)
         cells = [f.cells for f in self.fractals]
         if offsets is None:
@@ -395,7 +402,8 @@ class Batch:
         hs = (ctypes.c_void_p * max(n, 1))(*[f._h.value for f in self.fractals])
         offs = (ctypes.c_uint64 * max(n, 1))(*self.offsets)
         h = ctypes.c_void_p()
-        _check(lib().nbb_batch_create(hs, offs, n, _stream(stream), ctypes.byref(h)))
+        flags = 0 if resident is None else (NBB_BATCH_RESIDENT if resident else NBB_BATCH_NO_RESIDENT)
+        _check(lib().nbb_batch_create_ex(hs, offs, n, flags, _stream(stream), ctypes.byref(h)))
         self._h = h
         self.arena_bytes = int(self.info().arena_bytes)
 

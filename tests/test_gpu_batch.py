@@ -61,14 +61,19 @@ def _spread_offsets(cells, seed):
     return offs, o + 32
 
 
+@pytest.mark.parametrize("resident", [True, False])
 @pytest.mark.parametrize("rule", ["B3/S23", "B36/S23", "B1357/S02468", "B2/S", "vN:B2/S12"])
 @pytest.mark.parametrize("steps", [1, 6])
-def test_batch_mixed_vs_oracle(N, rule, steps):
+def test_batch_mixed_vs_oracle(N, rule, steps, resident):
+    # every tiled instance here is small: stepped in LDS (resident) or by the
+    # per-generation group launches
     fds, rs, frs = _mixed(N)
     offs, total = _spread_offsets([f.cells for f in frs], 7 + steps)
-    batch = N.Batch(frs, offs)
+    batch = N.Batch(frs, offs, resident=resident)
     inf = batch.info()
     assert inf.instances == len(frs) and inf.direct >= 2  # triangle r = 0 and the s = 5 fractal
+    assert inf.resident == (inf.instances - inf.direct if resident else 0)
+    assert (inf.groups == 0) == resident
     a = torch.full((total,), 0xA5, dtype=torch.uint8, device="cuda")
     b = torch.full((total,), 0x5A, dtype=torch.uint8, device="cuda")
     want = []
@@ -89,8 +94,9 @@ def test_batch_mixed_vs_oracle(N, rule, steps):
     assert (host(a)[~inside] == 0xA5).all() and (host(b)[~inside] == 0x5A).all()
 
 
+@pytest.mark.parametrize("resident", [True, False])
 @pytest.mark.parametrize("rule", ["B3/S23", "B1357/S02468"])
-def test_batch_wave_and_workgroup_plans_vs_oracle(N, rule):
+def test_batch_wave_and_workgroup_plans_vs_oracle(N, rule, resident):
     # the same fractals once with one wavefront per tile and once with one
     # work-group per tile, in one batch: separate groups, same results
     specs = [("triangle", 5, 3), ("triangle", 8, 4), ("chandelier", 4, 3), ("carpet", 3, 2),
@@ -106,8 +112,9 @@ def test_batch_wave_and_workgroup_plans_vs_oracle(N, rule):
             frs.append(f)
             o = O.Fractal(fd.s, fd.offsets, r)
             want.append(o.compact_steps(o.init_compact(40 + i, 0.5), rm, 9))
-    batch = N.Batch(frs)
-    assert batch.info().groups == 2 * len(specs)
+    batch = N.Batch(frs, resident=resident)
+    inf = batch.info()
+    assert (inf.groups, inf.resident) == ((0, len(frs)) if resident else (2 * len(specs), 0))
     a, b = batch.new_arena(), batch.new_arena()
     for idx, f in enumerate(frs):
         f.init_compact(40 + idx % len(specs), 0.5, out=batch.state(a, idx))
@@ -119,7 +126,7 @@ def test_batch_wave_and_workgroup_plans_vs_oracle(N, rule):
 
 def test_batch_groups_by_plan(N):
     _, _, frs = _mixed(N, with_direct=False)
-    inf = N.Batch(frs).info()
+    inf = N.Batch(frs, resident=False).info()
     tiled = [f for f in frs if f.info().strategy != N.STRATEGY_DIRECT]
     kinds = {(f.s, f.offsets, f.info().tile_level, f.info().strategy) for f in tiled}
     assert inf.groups == len(kinds)
@@ -255,8 +262,9 @@ def test_autotune_rejects_zero_steps(N):
         f.autotune(a, b, steps=0)
 
 
+@pytest.mark.parametrize("resident", [True, False])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_batch_random_fractals_vs_oracle(N, seed):
+def test_batch_random_fractals_vs_oracle(N, seed, resident):
     # seeded random NBB fractals (s in 2..4, any k), random levels and plans
     # (automatic, a common level, one wavefront per tile where it fits)
     rng = np.random.default_rng(500 + seed)
@@ -279,7 +287,7 @@ def test_batch_random_fractals_vs_oracle(N, seed):
         fds.append(fd)
         rs.append(r)
         frs.append(f)
-    batch = N.Batch(frs)
+    batch = N.Batch(frs, resident=resident)
     a, b = batch.new_arena(), batch.new_arena()
     rule = W.rule_mask("B36/S23" if seed else "vN:B2/S12")
     want = []
@@ -291,3 +299,159 @@ def test_batch_random_fractals_vs_oracle(N, seed):
     for i, f in enumerate(frs):
         np.testing.assert_array_equal(got[batch.offsets[i]:batch.offsets[i] + f.cells], want[i],
                                       err_msg=f"instance {i}: {fds[i]} r={rs[i]}")
+
+
+# ------------------------------------------------- instances stepped in LDS --
+# Instances small enough for one work-group's LDS run all generations in one
+# launch on a stream of the batch, beside the per-generation launches of the
+# large ones.
+LARGE_AND_SMALL = [("triangle", 12, None), ("carpet", 5, None), ("hfractal", 6, None), ("triangle", 9, None),
+                   ("triangle", 7, None), ("carpet", 4, None), ("hfractal", 5, None), ("chandelier", 7, None),
+                   ("chandelier", 5, None), ("triangle", 3, None), ("vicsek", 4, 2), ("hfractal", 4, 2)]
+
+
+def _large_and_small(N):
+    fds = [W.FRACTALS[n] for n, _, _ in LARGE_AND_SMALL]
+    rs = [r for _, r, _ in LARGE_AND_SMALL]
+    frs = []
+    for fd, (_, r, m) in zip(fds, LARGE_AND_SMALL):
+        f = N.Fractal(fd.s, fd.offsets, r)
+        if m:
+            f.configure(N.STRATEGY_TILED, m)
+        frs.append(f)
+    return fds, rs, frs
+
+
+@pytest.mark.parametrize("rule", ["B3/S23", "vN:B13/S13"])
+def test_batch_resident_beside_group_launches(N, rule):
+    fds, rs, frs = _large_and_small(N)
+    offs, total = _spread_offsets([f.cells for f in frs], 3)
+    batch = N.Batch(frs, offs, resident=True)
+    inf = batch.info()
+    # the two largest take the group launches, the small ones LDS
+    assert inf.groups >= 1 and len(frs) - 3 <= inf.resident <= len(frs) - 2
+    a = torch.full((total,), 0x11, dtype=torch.uint8, device="cuda")
+    b = torch.full((total,), 0x22, dtype=torch.uint8, device="cuda")
+    rm = W.rule_mask(rule)
+    for i, f in enumerate(frs):
+        f.init_compact(60 + i, 0.4, out=batch.state(a, i))
+    T = 7
+    singles = []
+    for i, f in enumerate(frs):
+        s0 = f.init_compact(60 + i, 0.4)
+        singles.append(host(f.step_compact(s0, torch.empty_like(s0), T, rm)))
+    got = host(batch.step(a, b, T, rm))
+    for i, f in enumerate(frs):
+        np.testing.assert_array_equal(got[offs[i]:offs[i] + f.cells], singles[i], err_msg=f"instance {i}")
+        if f.cells <= 20000:
+            o = O.Fractal(fds[i].s, fds[i].offsets, rs[i])
+            np.testing.assert_array_equal(singles[i], o.compact_steps(o.init_compact(60 + i, 0.4), rm, T))
+    inside = np.zeros(total, bool)
+    for o_, c in zip(offs, [f.cells for f in frs]):
+        inside[o_:o_ + c] = True
+    assert (host(a)[~inside] == 0x11).all() and (host(b)[~inside] == 0x22).all()
+
+
+def test_batch_resident_step_each_any_order_vs_oracle(N):
+    # per-instance generation counts; resident instances need no order
+    fds, rs, frs = _large_and_small(N)
+    steps = [9, 6, 4, 0, 1, 2, 3, 5, 8, 13, 7, 10]   # the three largest first, in decreasing order
+    batch = N.Batch(frs, resident=True)
+    a, b = batch.new_arena(), batch.new_arena()
+    a0 = []
+    for i, f in enumerate(frs):
+        f.init_compact(80 + i, 0.5, out=batch.state(a, i))
+        a0.append(host(batch.state(a, i)).copy())
+    batch.step_each(a, b, steps)
+    ga, gb = host(a), host(b)
+    for i, (fd, r, f) in enumerate(zip(fds, rs, frs)):
+        got = (gb if steps[i] & 1 else ga)[batch.offsets[i]:batch.offsets[i] + f.cells]
+        if steps[i] == 0:
+            np.testing.assert_array_equal(got, a0[i])
+            continue
+        o = O.Fractal(fd.s, fd.offsets, r)
+        np.testing.assert_array_equal(got, o.compact_steps(o.init_compact(80 + i, 0.5), B3S23, steps[i]),
+                                      err_msg=f"instance {i} steps {steps[i]}")
+
+
+def test_batch_resident_many_chunks_vs_oracle(N):
+    # more small instances than one resident launch takes (several launches
+    # per plan), two plans, one shared descriptor per plan
+    tri = N.Fractal(2, W.TRIANGLE.offsets, 6)
+    car = N.Fractal(3, W.CARPET.offsets, 3)
+    frs = [tri if i % 3 else car for i in range(300)]
+    batch = N.Batch(frs)
+    inf = batch.info()
+    assert inf.resident == 300 and inf.groups == 0
+    a, b = batch.new_arena(), batch.new_arena()
+    for i, f in enumerate(frs):
+        f.init_compact(i, 0.5, out=batch.state(a, i))
+    got = host(batch.step(a, b, 12))
+    ot, oc = O.Fractal(2, W.TRIANGLE.offsets, 6), O.Fractal(3, W.CARPET.offsets, 3)
+    for i, f in enumerate(frs):
+        o = ot if i % 3 else oc
+        np.testing.assert_array_equal(got[batch.offsets[i]:batch.offsets[i] + f.cells],
+                                      o.compact_steps(o.init_compact(i, 0.5), B3S23, 12), err_msg=f"instance {i}")
+    # per-instance counts (more than one chunk of them), in no order
+    steps = [(7 * i) % 11 for i in range(len(frs))]
+    for i, f in enumerate(frs):
+        f.init_compact(i, 0.5, out=batch.state(a, i))
+    batch.step_each(a, b, steps)
+    ga, gb = host(a), host(b)
+    for i, f in enumerate(frs):
+        o = ot if i % 3 else oc
+        got = (gb if steps[i] & 1 else ga)[batch.offsets[i]:batch.offsets[i] + f.cells]
+        np.testing.assert_array_equal(got, o.compact_steps(o.init_compact(i, 0.5), B3S23, steps[i]),
+                                      err_msg=f"instance {i} steps {steps[i]}")
+
+
+def test_batch_resident_in_graph_replays(N):
+    # a captured batch step (fork to the batch's stream and join back inside
+    # the capture), replayed with eager work between replays
+    fds, rs, frs = _large_and_small(N)
+    batch = N.Batch(frs, resident=True)
+    assert batch.info().resident >= 9 and batch.info().groups >= 1
+    a, b = batch.new_arena(), batch.new_arena()
+    for i, f in enumerate(frs):
+        f.init_compact(5 + i, 0.5, out=batch.state(a, i))
+    a0 = a.clone()
+    ref_a, ref_b = batch.new_arena(), batch.new_arena()
+    ref_a.copy_(a0)
+    batch.step(ref_a, ref_b, 2)        # even: the result is back in ref_a
+    want = host(ref_a)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        batch.step(a, b, 1, stream=s)   # warm-up outside capture
+        a.copy_(a0)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            batch.step(a, b, 2, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        a.copy_(a0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = host(a)
+        for i, f in enumerate(frs):
+            sl = slice(batch.offsets[i], batch.offsets[i] + f.cells)
+            np.testing.assert_array_equal(got[sl], want[sl], err_msg=f"replay {rep} instance {i}")
+
+
+def test_batch_resident_default_policy(N):
+    # by default small instances go to LDS only when they hold at least 1/8
+    # of the tiled cells
+    big = N.Fractal(2, W.TRIANGLE.offsets, 12)
+    small = [N.Fractal(2, W.TRIANGLE.offsets, 7), N.Fractal(3, W.CARPET.offsets, 3)]
+    frs = [big] + small * 4
+    assert 8 * sum(f.cells for f in frs[1:]) < sum(f.cells for f in frs)
+    inf = N.Batch(frs).info()
+    assert inf.resident == 0 and inf.groups == 3
+    assert N.Batch(frs, resident=True).info().resident == 8
+    assert N.Batch(frs[1:]).info().resident == 8
+    assert N.Batch(frs[1:], resident=False).info().resident == 0
+    _, _, mixed = _mixed(N)
+    inf = N.Batch(mixed).info()
+    assert inf.resident == inf.instances - inf.direct and inf.groups == 0

@@ -58,15 +58,20 @@ def test_step_each_vs_oracle(N, seed):
 
 
 def test_step_each_rejects_increasing_counts(N):
+    # the order matters for the per-generation group launches only; the
+    # same small instances stepped in LDS take any order
     fd = W.CARPET
     frs = [N.Fractal(fd.s, fd.offsets, 2), N.Fractal(fd.s, fd.offsets, 3)]
-    batch = N.Batch(frs)
+    batch = N.Batch(frs, resident=False)
     a, b = batch.new_arena(), batch.new_arena()
     with pytest.raises(N.NbbError, match="increase"):
         batch.step_each(a, b, [3, 5])
     with pytest.raises(ValueError):
         batch.step_each(a, b, [3])
     batch.step_each(a, b, [5, 3])
+    res = N.Batch(frs)
+    assert res.info().resident == 2
+    res.step_each(a, b, [3, 5])
 
 
 SMALL_SERVE = W.ServeWorkload("serve_small", 400.0, 0.5, ("carpet", "hfractal", "triangle", "chandelier"), 11,

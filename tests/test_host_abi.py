@@ -204,6 +204,11 @@ def test_batch_create_without_device_reports_device_error():
     h = ctypes.c_void_p()
     assert L.nbb_batch_create(None, None, 0, None, ctypes.byref(h)) == N.NBB_E_DEVICE
     assert L.nbb_batch_create(None, None, 0, None, None) == N.NBB_E_INVALID
+    # flags are checked before the device is
+    assert L.nbb_batch_create_ex(None, None, 0, N.NBB_BATCH_RESIDENT, None, ctypes.byref(h)) == N.NBB_E_DEVICE
+    for bad in (N.NBB_BATCH_RESIDENT | N.NBB_BATCH_NO_RESIDENT, 4, 1 << 31):
+        assert L.nbb_batch_create_ex(None, None, 0, bad, None, ctypes.byref(h)) == N.NBB_E_INVALID
+    assert "flags" in L.nbb_last_error().decode()
     assert L.nbb_batch_step(None, None, None, 0, 1, N.NBB_RULE_B3S23, None, None) == N.NBB_E_INVALID
     assert L.nbb_batch_query(None, None) == N.NBB_E_INVALID
     L.nbb_batch_destroy(None)
