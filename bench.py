@@ -172,7 +172,8 @@ def batch_run(torch, N, W, args):
     out["roofline_frac"] = out["alg_gbps"] / HBM_PEAK_GBPS
     log(f"batch: {ms_step * 1e3:.1f} us/step, {out['cell_updates_per_s']:.3e} cell-updates/s, "
         f"{out['alg_gbps']:.0f} GB/s; one launch per instance {ms_seq / Ts * 1e3:.1f} us/step; same={same}")
-    out["small_instances"] = small_batch_run(torch, N, items, frs, init, batch, rule, Kb)
+    if not args.no_small_batch:
+        out["small_instances"] = small_batch_run(torch, N, items, frs, init, batch, rule, Kb)
     return out
 
 
@@ -245,6 +246,8 @@ def main():
     ap.add_argument("--batch-seq-steps", type=int, default=10,
                     help="generations of the one-launch-per-instance comparison")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-small-batch", action="store_true",
+                    help="skip timing the batch's small instances alone (in LDS and in group launches)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window of the served workload (its full length is 60 s); 0 skips it")
     ap.add_argument("--serve-deadline", type=float, default=0.5,

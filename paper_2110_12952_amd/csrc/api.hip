@@ -93,6 +93,7 @@ struct ResidentGroup {
     std::vector<uint32_t> index;          // the instances (caller's numbering)
     uint32_t teams = 1;                   // tiles per pass
     uint32_t lds = 0;                     // LDS of the largest
+    std::vector<uint32_t> passes;         // passes per generation of each instance
 };
 // An instance is stepped in LDS only if a generation takes at most this many
 // passes (each about a microsecond: a tile scatter, the rule, two barriers):
@@ -865,6 +866,7 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
                 break;
             }
         R.lds = resident_lds_bytes(R.tp, most, R.teams);
+        for (const BatchInstance &I : res.members[g]) R.passes.push_back((I.ntiles + R.teams - 1) / R.teams);
         B->resident.push_back(std::move(R));
     }
     for (const BatchDirect &d : B->direct) B->cu_count = d.f->cu_count;
@@ -915,10 +917,31 @@ static hipError_t batch_fork_resident(const nbb_batch *B, uint8_t *a, uint8_t *b
         for (int i = 0; i < B->nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(B->side[i], B->fork, 0);
         if (e != hipSuccess) return e;
     }
-    std::vector<uint32_t> n;
-    for (size_t g = 0; g < B->resident.size(); ++g) {
+    // Each launch lasts about (its instances' largest passes x generations)
+    // passes: longest first, each to the stream with the least work so far.
+    const size_t ng = B->resident.size();
+    std::vector<uint64_t> cost(ng, 0);
+    for (size_t g = 0; g < ng; ++g) {
         const ResidentGroup &R = B->resident[g];
-        hipStream_t rs = B->nside ? B->side[g % B->nside] : s;
+        for (size_t j = 0; j < R.index.size(); ++j)
+            cost[g] = std::max<uint64_t>(cost[g], uint64_t(R.passes[j]) * (steps ? steps[R.index[j]] : steps_all));
+    }
+    std::vector<size_t> order(ng);
+    std::iota(order.begin(), order.end(), size_t(0));
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    uint64_t load[kResidentStreams] = {};
+    std::vector<uint32_t> n;
+    for (size_t g : order) {
+        const ResidentGroup &R = B->resident[g];
+        if (!cost[g]) continue;  // no instance of the group takes a generation
+        hipStream_t rs = s;
+        if (B->nside) {
+            int best = 0;
+            for (int i = 1; i < B->nside; ++i)
+                if (load[i] < load[best]) best = i;
+            load[best] += cost[g];
+            rs = B->side[best];
+        }
         const uint32_t count = uint32_t(R.index.size());
         const uint32_t *steps_of = nullptr;
         if (steps) {
