@@ -229,6 +229,32 @@ nbb_status nbb_blocked_to_compact(const nbb_fractal *f, const uint8_t *blocked, 
 nbb_status nbb_step_blocked(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
                             uint32_t rule, int *result_in_b, void *stream);
 
+/*
+ * Bit-packed compact state (the byte layout at one bit per cell, 8x fewer
+ * bytes; stencils over bit rows are the usual way to cut the state's memory
+ * traffic further than the compact form does): cell i is bit i % 32 of the
+ * little-endian 32-bit word i / 32, i.e. bit i % 8 of byte i / 8.  Needs a
+ * TILED or TILED_WAVE plan (NBB_E_INVALID otherwise).
+ *   nbb_packed_bytes: 4 ceil(k^r / 32) (0 for NULL).  Bits past the last cell
+ *   are 0 after nbb_pack and are never written by nbb_step_packed.
+ *   nbb_pack: packed = bits of compact (k^r bytes; any non-zero byte packs as
+ *   1).  nbb_unpack: compact (k^r bytes, 0 or 1) from packed.  len is the
+ *   packed length, which must equal nbb_packed_bytes; packed buffers 4-byte
+ *   aligned.
+ *   nbb_step_packed: generations on packed states, arguments and result
+ *   buffer as nbb_step_compact (a and b packed, len = nbb_packed_bytes).
+ *   The descriptor's tile plan is used (after nbb_configure, the new one);
+ *   NBB_E_INVALID if a tile's output words do not fit the kernel's limits
+ *   (at most 1024 blocks, 1024 halo cells and 16 cells per block: every
+ *   automatic plan fits).  The first call for a plan builds a 32-phase copy
+ *   of its scatter table on the device (kept with the descriptor).
+ */
+uint64_t nbb_packed_bytes(const nbb_fractal *f);
+nbb_status nbb_pack(const nbb_fractal *f, const uint8_t *compact, uint8_t *packed, uint64_t len, void *stream);
+nbb_status nbb_unpack(const nbb_fractal *f, const uint8_t *packed, uint64_t len, uint8_t *compact, void *stream);
+nbb_status nbb_step_packed(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                           uint32_t rule, int *result_in_b, void *stream);
+
 /* bbox[lambda(i)] = compact[i]; every other box byte becomes 0. */
 nbb_status nbb_expand(const nbb_fractal *f, const uint8_t *compact, uint8_t *bbox, uint64_t pitch,
                       uint64_t len, void *stream);

@@ -64,6 +64,11 @@ struct nbb_fractal {
     mutable TileParams res_tp{};
     mutable uint32_t res_teams = 1;
     mutable DevBlob dres;
+    // 32-phase scatter table of the bit-packed step, for the plan whose
+    // (m, W, team) it records; rebuilt when the plan changes.
+    mutable std::mutex pk_mu;
+    mutable DevBlob dpk;
+    mutable uint32_t pk_stride = 0, pk_m = 0, pk_W = 0, pk_team = 0;
 };
 
 struct nbb_plan {
@@ -440,6 +445,7 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
 void nbb_destroy(nbb_fractal *F) {
     if (!F) return;
     blob_free(&F->dres);
+    blob_free(&F->dpk);
     blob_free(&F->dmap);
     blob_free(&F->dbox);
     blob_free(&F->dtile);
@@ -1280,6 +1286,89 @@ nbb_status nbb_step_blocked(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     for (uint32_t i = 0; i < steps; ++i) {
         hipError_t e = launch_step_blocked(F->tp, in, out, rule, F->cu_count, s);
         if (e != hipSuccess) return hip_fail(e, "blocked step launch");
+        std::swap(in, out);
+    }
+    return NBB_OK;
+}
+
+uint64_t nbb_packed_bytes(const nbb_fractal *F) { return F ? (F->f.cells + 31) / 32 * 4 : 0; }
+
+static nbb_status check_packed(const nbb_fractal *F, const void *packed, uint64_t len) {
+    if (F->strategy == NBB_STRATEGY_DIRECT) return fail(NBB_E_INVALID, "the packed state needs a tiled plan");
+    if (!packed) return fail(NBB_E_INVALID, "null argument");
+    if (len != nbb_packed_bytes(F)) return fail(NBB_E_INVALID, "len must equal nbb_packed_bytes");
+    if (reinterpret_cast<uintptr_t>(packed) & 3) return fail(NBB_E_INVALID, "packed state must be 4-byte aligned");
+    return NBB_OK;
+}
+
+nbb_status nbb_pack(const nbb_fractal *F, const uint8_t *compact, uint8_t *packed, uint64_t len, void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_packed(F, packed, len);
+    if (st == NBB_OK) st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_pack_bits(compact, reinterpret_cast<uint32_t *>(packed), F->f.cells,
+                                     map_grid(F, len / 4), static_cast<hipStream_t>(stream)),
+                    "pack launch");
+}
+
+nbb_status nbb_unpack(const nbb_fractal *F, const uint8_t *packed, uint64_t len, uint8_t *compact, void *stream) {
+    if (!F || !compact) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_packed(F, packed, len);
+    if (st == NBB_OK) st = check_device(F);
+    if (st != NBB_OK) return st;
+    return launched(launch_unpack_bits(reinterpret_cast<const uint32_t *>(packed), compact, F->f.cells,
+                                       map_grid(F, len / 4), static_cast<hipStream_t>(stream)),
+                    "unpack launch");
+}
+
+// The 32-phase copy of the plan's lut0 for the packed step (built on first
+// use, kept with the descriptor, rebuilt after a change of plan).
+static nbb_status packed_table(const nbb_fractal *F, const uint16_t **lut, uint32_t *stride) {
+    std::lock_guard<std::mutex> lock(F->pk_mu);
+    const TilePlan &P = F->tile;
+    if (!F->dpk.ptr || F->pk_m != P.m || F->pk_W != P.W || F->pk_team != P.team) {
+        blob_free(&F->dpk);
+        const uint32_t K = P.K, S = 32 * ((K + 62) / 32);
+        std::vector<uint16_t> t(size_t(32) * S, uint16_t(P.dummy));
+        for (uint32_t p = 0; p < 32; ++p)
+            for (uint32_t j = p; j < p + K; ++j) t[size_t(p) * S + j] = P.lut0p[j - p];  // phase-0 copy
+        const void *src[1] = {t.data()};
+        const size_t bytes[1] = {t.size() * 2};
+        void *dst[1];
+        nbb_status st = upload(&F->dpk, src, bytes, 1, dst);
+        if (st != NBB_OK) return st;
+        F->pk_stride = S;
+        F->pk_m = P.m;
+        F->pk_W = P.W;
+        F->pk_team = P.team;
+    }
+    *lut = static_cast<const uint16_t *>(F->dpk.ptr);
+    *stride = F->pk_stride;
+    return NBB_OK;
+}
+
+nbb_status nbb_step_packed(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps,
+                           uint32_t rule, int *result_in_b, void *stream) {
+    if (!F || !a || !b) return fail(NBB_E_INVALID, "null argument");
+    nbb_status st = check_packed(F, a, len);
+    if (st == NBB_OK) st = check_packed(F, b, len);
+    if (st != NBB_OK) return st;
+    if (overlap(a, b, len)) return fail(NBB_E_INVALID, "a and b overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
+    if (!packed_fits(F->tp)) return fail(NBB_E_INVALID, "the tile plan exceeds the packed step's limits");
+    st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (result_in_b) *result_in_b = int(steps & 1);
+    if (!steps) return NBB_OK;
+    const uint16_t *lut = nullptr;
+    uint32_t stride = 0;
+    st = packed_table(F, &lut, &stride);
+    if (st != NBB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *in = reinterpret_cast<uint32_t *>(a), *out = reinterpret_cast<uint32_t *>(b);
+    for (uint32_t i = 0; i < steps; ++i) {
+        hipError_t e = launch_step_packed(F->tp, lut, stride, in, out, rule, F->cu_count, s);
+        if (e != hipSuccess) return hip_fail(e, "packed step launch");
         std::swap(in, out);
     }
     return NBB_OK;

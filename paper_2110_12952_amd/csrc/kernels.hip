@@ -1101,6 +1101,143 @@ __global__ __launch_bounds__(256) void k_step_resident(TileParams T, const Batch
 }
 
 // ---------------------------------------------------------------------------
+// Bit-packed compact state: cell i is bit i % 32 of 32-bit word i / 32 (the
+// compact order of the byte layout, eight cells per byte, bytes little-endian).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_bits(const uint8_t *__restrict__ bytes, uint32_t *__restrict__ words,
+                                                   uint64_t cells, uint64_t nwords) {
+    for (uint64_t w = blockIdx.x * 256ull + threadIdx.x; w < nwords; w += uint64_t(gridDim.x) * 256) {
+        uint32_t v = 0;
+        for (uint32_t b = 0; b < 32; ++b) {
+            const uint64_t c = 32 * w + b;
+            if (c < cells) v |= uint32_t(bytes[c] != 0) << b;
+        }
+        words[w] = v;
+    }
+}
+__global__ __launch_bounds__(256) void k_unpack_bits(const uint32_t *__restrict__ words, uint8_t *__restrict__ bytes,
+                                                     uint64_t cells, uint64_t nwords) {
+    for (uint64_t w = blockIdx.x * 256ull + threadIdx.x; w < nwords; w += uint64_t(gridDim.x) * 256) {
+        const uint32_t v = words[w];
+        for (uint32_t b = 0; b < 32; ++b) {
+            const uint64_t c = 32 * w + b;
+            if (c < cells) bytes[c] = uint8_t((v >> b) & 1u);
+        }
+    }
+}
+
+// The tiled step on the packed state.  Per tile (K cells from bit t K, any
+// phase within a word): lanes load the words covering the tile and scatter
+// their bits as bytes into the LDS box through a 32-phase copy of lut0 (copy
+// p entry j = box offset of local cell j - p, or the never-read byte); the
+// halo bits come one by one; the rule runs per block exactly as in the byte
+// step; a block's CB next states, gathered into compact order, become CB
+// bits that are OR-ed into an LDS copy of the tile's output words.  Words
+// wholly inside the tile are then stored; the first and last words, shared
+// with the neighbouring tiles (which other work-groups may be writing), are
+// updated with an atomic AND that clears the tile's bits and an atomic OR
+// that sets them (the two tiles touch disjoint bits, so the order does not
+// matter).  Bits past the last cell are never written.
+constexpr uint32_t kPkBPT = 4, kPkHPT = 4;
+template <int BS, bool EDGE>
+__global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_t *__restrict__ lutw,
+                                                     uint32_t lutw_stride, const uint32_t *__restrict__ in,
+                                                     uint32_t *__restrict__ out, uint32_t rule) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint8_t *box = lds;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds + T.lds_total);
+    const uint32_t tid = threadIdx.x, K = T.K;
+    for (uint32_t o = tid * 16; o < T.lds_total; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(box + o) = make_uint4(0, 0, 0, 0);
+    const RuleTables RT = rule_tables(rule);
+    uint32_t hsrc[kPkHPT], hdst[kPkHPT], blk[kPkBPT];
+#pragma unroll
+    for (uint32_t j = 0; j < kPkHPT; ++j) {
+        const uint32_t h = tid + 256 * j;
+        const bool ok = h < T.halo_count;
+        hsrc[j] = ok ? T.halo_src[h] : kOutside;
+        hdst[j] = ok ? T.halo_dst[h] : T.dummy;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPkBPT; ++j) blk[j] = T.lut1[min(tid + 256 * j, T.nblk - 1)];
+    const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
+    const uint32_t W4 = T.W >> 2;
+    const uint32_t cbmask = T.CB >= 32 ? 0xFFFFFFFFu : (1u << T.CB) - 1;
+    __syncthreads();
+
+    for (uint32_t t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+        const uint32_t B = t * K;  // first cell of the tile (< 2^32)
+        const uint32_t ph = B & 31, w0 = B >> 5, nw = (ph + K + 31) >> 5;
+        const uint16_t *lut = lutw + ph * lutw_stride;
+        // 1. the tile's bits and its halo into the box; clear the output words
+        for (uint32_t c = tid; c < nw; c += 256) {
+            const uint32_t word = in[w0 + c];
+            const uint4 *e4 = reinterpret_cast<const uint4 *>(lut + 32 * c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 e = e4[q];
+                const uint32_t ee[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    box[(ee[k >> 1] >> (16 * (k & 1))) & 0xFFFFu] = uint8_t((word >> (8 * q + k)) & 1u);
+            }
+            stage[c] = 0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kPkHPT; ++j) {
+            const uint32_t src = hsrc[j];
+            const uint32_t ntile = src != kOutside ? T.nbr[t * 8 + (src >> 29)] : kOutside;
+            uint32_t v = 0;
+            if (ntile != kOutside) {
+                const uint32_t bit = ntile * K + (src & 0x1FFFFFFFu);
+                v = (in[bit >> 5] >> (bit & 31)) & 1u;
+            }
+            box[hdst[j]] = uint8_t(v);
+        }
+        __syncthreads();
+        // 2. the rule per block; its CB bits into the tile's output words
+#pragma unroll
+        for (uint32_t j = 0; j < kPkBPT; ++j) {
+            const uint32_t bi = tid + 256 * j;
+            if (bi < T.nblk) {
+                uint32_t next[4];
+                if (RT.perm)
+                    block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
+                else
+                    block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
+                uint32_t bits = 0;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t w = __builtin_amdgcn_perm(next[1], next[0], T.pack01[d]);
+                    if (BS >= 3) w |= __builtin_amdgcn_perm(next[3], next[2], T.pack23[d]);
+                    // four 0/1 bytes -> four bits (the partial products never overlap)
+                    bits |= ((w * 0x01020408u) >> 24 & 0xFu) << (4 * d);
+                }
+                bits &= cbmask;
+                const uint32_t pos = ph + bi * T.CB, sh = pos & 31;
+                atomicOr(&stage[pos >> 5], bits << sh);
+                if (sh + T.CB > 32) atomicOr(&stage[(pos >> 5) + 1], bits >> (32 - sh));
+            }
+        }
+        __syncthreads();
+        // 3. the output words: whole ones stored, the two shared ones merged
+        for (uint32_t c = tid; c < nw; c += 256) {
+            const uint32_t lo = c == 0 ? ph : 0;
+            const uint32_t hi = c + 1 == nw ? ((ph + K - 1) & 31) + 1 : 32;
+            const uint32_t mask = (hi == 32 ? 0xFFFFFFFFu : (1u << hi) - 1) & ~((1u << lo) - 1);
+            const uint32_t v = stage[c];
+            if (mask == 0xFFFFFFFFu) {
+                out[w0 + c] = v;
+            } else {
+                atomicAnd(&out[w0 + c], ~mask);
+                atomicOr(&out[w0 + c], v & mask);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Bounding-box step (section 4, method 1): every cell of the n x n box is
 // visited.  A thread owns 16 consecutive columns and walks down a band of
 // rows, keeping the horizontal 3-sums of three rows in registers, so each
@@ -1427,6 +1564,46 @@ hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_
     const uint32_t grid = std::min<uint32_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_batch_tiles, dim3(grid), dim3(256), 0, st, inst, ninst, total, rec, nbr);
     return hipGetLastError();
+}
+hipError_t launch_pack_bits(const uint8_t *bytes, uint32_t *words, uint64_t cells, int grid, hipStream_t st) {
+    const uint64_t nwords = (cells + 31) / 32;
+    if (!nwords) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_bits, dim3(grid), dim3(256), 0, st, bytes, words, cells, nwords);
+    return hipGetLastError();
+}
+hipError_t launch_unpack_bits(const uint32_t *words, uint8_t *bytes, uint64_t cells, int grid, hipStream_t st) {
+    const uint64_t nwords = (cells + 31) / 32;
+    if (!nwords) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack_bits, dim3(grid), dim3(256), 0, st, words, bytes, cells, nwords);
+    return hipGetLastError();
+}
+uint32_t packed_stage_words(const TileParams &T) { return (T.K + 62) / 32 + 1; }
+bool packed_fits(const TileParams &T) {
+    return T.nblk <= kPkBPT * 256 && T.halo_count <= kPkHPT * 256 && T.CB <= 16 &&
+           T.lds_total + 4 * packed_stage_words(T) <= 65536;
+}
+template <int BS, bool EDGE>
+static hipError_t launch_packed_t(const TileParams &T, const uint16_t *lutw, uint32_t stride, const uint32_t *in,
+                                  uint32_t *out, uint32_t rule, int cu_count, hipStream_t st) {
+    const uint32_t lds = T.lds_total + 4 * packed_stage_words(T);
+    const uint32_t grid = uint32_t(std::min<uint64_t>(T.ntiles, uint64_t(cu_count) * 8));
+    hipLaunchKernelGGL((k_step_packed<BS, EDGE>), dim3(grid), dim3(256), lds, st, T, lutw, stride, in, out, rule);
+    return hipGetLastError();
+}
+hipError_t launch_step_packed(const TileParams &T, const uint16_t *lutw, uint32_t stride, const uint32_t *in,
+                              uint32_t *out, uint32_t rule, int cu_count, hipStream_t st) {
+    if (!packed_fits(T) || stride % 32 || stride < 32 * ((T.K + 62) / 32)) return hipErrorInvalidValue;
+    if (!T.ntiles) return hipSuccess;
+    const bool edge = (rule >> 31) != 0;
+    switch (T.BS) {
+        case 2: return edge ? launch_packed_t<2, true>(T, lutw, stride, in, out, rule, cu_count, st)
+                            : launch_packed_t<2, false>(T, lutw, stride, in, out, rule, cu_count, st);
+        case 3: return edge ? launch_packed_t<3, true>(T, lutw, stride, in, out, rule, cu_count, st)
+                            : launch_packed_t<3, false>(T, lutw, stride, in, out, rule, cu_count, st);
+        case 4: return edge ? launch_packed_t<4, true>(T, lutw, stride, in, out, rule, cu_count, st)
+                            : launch_packed_t<4, false>(T, lutw, stride, in, out, rule, cu_count, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st) {
     const uint32_t gx = uint32_t((B.pitch / 16 + 255) / 256);

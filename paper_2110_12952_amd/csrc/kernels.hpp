@@ -65,5 +65,17 @@ hipError_t launch_set_words(uint32_t *dst, const uint32_t *src, uint32_t n, hipS
 hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_t total, uint32_t *rec,
                               uint32_t *nbr, hipStream_t st);
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st);
+// Bit-packed compact state (cell i = bit i % 32 of word i / 32): conversions
+// from and to one byte per cell (any non-zero byte packs as 1; words past the
+// last cell hold zero bits), and the tiled step on it.  lutw: 32 phase copies
+// of the plan's lut0, `stride` entries each (a multiple of 32, at least 32
+// words' worth past K + 31), copy p entry j = box offset of local cell j - p
+// or T.dummy.
+hipError_t launch_pack_bits(const uint8_t *bytes, uint32_t *words, uint64_t cells, int grid, hipStream_t st);
+hipError_t launch_unpack_bits(const uint32_t *words, uint8_t *bytes, uint64_t cells, int grid, hipStream_t st);
+uint32_t packed_stage_words(const TileParams &T);
+bool packed_fits(const TileParams &T);
+hipError_t launch_step_packed(const TileParams &T, const uint16_t *lutw, uint32_t stride, const uint32_t *in,
+                              uint32_t *out, uint32_t rule, int cu_count, hipStream_t st);
 
 }  // namespace nbb

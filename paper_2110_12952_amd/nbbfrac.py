@@ -114,6 +114,14 @@ def lib() -> ctypes.CDLL:
     L.nbb_blocked_to_compact.restype = st
     L.nbb_step_blocked.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
     L.nbb_step_blocked.restype = st
+    L.nbb_packed_bytes.argtypes = [vp]
+    L.nbb_packed_bytes.restype = u64
+    L.nbb_pack.argtypes = [vp, vp, vp, u64, vp]
+    L.nbb_pack.restype = st
+    L.nbb_unpack.argtypes = [vp, vp, u64, vp, vp]
+    L.nbb_unpack.restype = st
+    L.nbb_step_packed.argtypes = [vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int), vp]
+    L.nbb_step_packed.restype = st
     L.nbb_expand.argtypes = [vp, vp, vp, u64, u64, vp]
     L.nbb_expand.restype = st
     L.nbb_gather.argtypes = [vp, vp, u64, vp, u64, vp]
@@ -333,6 +341,32 @@ class Fractal:
         res = ctypes.c_int(0)
         _check(lib().nbb_step_blocked(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
                                       int(rule), ctypes.byref(res), _stream(stream)))
+        return b if res.value else a
+
+    # ---- bit-packed state (cell i = bit i % 8 of byte i / 8) ---------------
+    def packed_bytes(self) -> int:
+        return int(lib().nbb_packed_bytes(self._h))
+
+    def new_packed(self):
+        import torch
+        return torch.zeros(self.packed_bytes(), dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+
+    def pack(self, compact, out=None, stream=None):
+        pk = self.new_packed() if out is None else out
+        _check(lib().nbb_pack(self._h, _dev_ptr(compact, "uint8", self.cells), _dev_ptr(pk, "uint8"), pk.numel(),
+                              _stream(stream)))
+        return pk
+
+    def unpack(self, packed, out=None, stream=None):
+        c = self.new_compact() if out is None else out
+        _check(lib().nbb_unpack(self._h, _dev_ptr(packed, "uint8"), packed.numel(), _dev_ptr(c, "uint8", self.cells),
+                                _stream(stream)))
+        return c
+
+    def step_packed(self, a, b, steps: int, rule: int = NBB_RULE_B3S23, stream=None):
+        res = ctypes.c_int(0)
+        _check(lib().nbb_step_packed(self._h, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
+                                     int(rule), ctypes.byref(res), _stream(stream)))
         return b if res.value else a
 
     def expand(self, compact, out=None, stream=None):
