@@ -1127,25 +1127,61 @@ __global__ __launch_bounds__(256) void k_unpack_bits(const uint32_t *__restrict_
 }
 
 // The tiled step on the packed state.  Per tile (K cells from bit t K, any
-// phase within a word): lanes load the words covering the tile and scatter
-// their bits as bytes into the LDS box through a 32-phase copy of lut0 (copy
-// p entry j = box offset of local cell j - p, or the never-read byte); the
-// halo bits come one by one; the rule runs per block exactly as in the byte
-// step; a block's CB next states, gathered into compact order, become CB
-// bits that are OR-ed into an LDS copy of the tile's output words.  Words
-// wholly inside the tile are then stored; the first and last words, shared
-// with the neighbouring tiles (which other work-groups may be writing), are
-// updated with an atomic AND that clears the tile's bits and an atomic OR
-// that sets them (the two tiles touch disjoint bits, so the order does not
-// matter).  Bits past the last cell are never written.
-constexpr uint32_t kPkBPT = 4, kPkHPT = 4;
+// phase within a word): four lanes per word (8 bits each) scatter the tile's
+// bits as bytes into the LDS box through a 32-phase copy of lut0 (copy p entry
+// j = box offset of local cell j - p, or the never-read byte); the halo bits
+// come one per lane; the rule runs per block exactly as in the byte step; a
+// block's CB next states, gathered into compact order, become CB bits that
+// are OR-ed into an LDS copy of the tile's output words.  Words wholly inside
+// the tile are then stored; the first and last words, shared with the
+// neighbouring tiles (which other work-groups may be writing), are updated
+// with an atomic AND that clears the tile's bits and an atomic OR that sets
+// them (the two tiles touch disjoint bits, so the order does not matter).
+// Bits past the last cell are never written.  As in the byte step, the
+// work-groups are persistent over XCD-contiguous tile ranges and the next
+// tile's words, scatter offsets and halo bits are loaded into registers while
+// the current one computes; the output-word copy alternates between two LDS
+// buffers, so a tile takes two barriers.
+constexpr uint32_t kPkWPT = 4, kPkBPT = 4, kPkHPT = 4;  // word quarters, blocks, halo cells per thread
+struct PackedPrefetch {
+    uint32_t word[kPkWPT];
+    uint4 e[kPkWPT];
+    uint32_t halo[kPkHPT];
+};
+__device__ __forceinline__ void packed_prefetch(const TileParams &T, const uint16_t *lutw, uint32_t stride,
+                                                const uint32_t *in, uint32_t t, const uint32_t (&hsrc)[kPkHPT],
+                                                PackedPrefetch &pf) {
+    const uint32_t tid = threadIdx.x, K = T.K;
+    const uint32_t B = t * K, ph = B & 31, w0 = B >> 5, nq = 4 * ((ph + K + 31) >> 5);
+    const uint16_t *lut = lutw + ph * stride;
+#pragma unroll
+    for (uint32_t j = 0; j < kPkWPT; ++j) {
+        const uint32_t l = tid + 256 * j;  // quarter l & 3 of word l >> 2
+        if (l < nq) {
+            pf.word[j] = in[w0 + (l >> 2)];
+            pf.e[j] = *reinterpret_cast<const uint4 *>(lut + 8 * l);
+        }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPkHPT; ++j) {
+        const uint32_t src = hsrc[j];
+        const uint32_t ntile = src != kOutside ? T.nbr[uint64_t(t) * 8 + (src >> 29)] : kOutside;
+        uint32_t v = 0;
+        if (ntile != kOutside) {
+            const uint32_t bit = ntile * K + (src & 0x1FFFFFFFu);
+            v = (in[bit >> 5] >> (bit & 31)) & 1u;
+        }
+        pf.halo[j] = v;
+    }
+}
 template <int BS, bool EDGE>
 __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_t *__restrict__ lutw,
                                                      uint32_t lutw_stride, const uint32_t *__restrict__ in,
                                                      uint32_t *__restrict__ out, uint32_t rule) {
     extern __shared__ __align__(16) uint8_t lds[];
     uint8_t *box = lds;
-    uint32_t *stage = reinterpret_cast<uint32_t *>(lds + T.lds_total);
+    const uint32_t nsw = (T.K + 62) / 32 + 1;  // words of one output copy
+    uint32_t *stage0 = reinterpret_cast<uint32_t *>(lds + T.lds_total);
     const uint32_t tid = threadIdx.x, K = T.K;
     for (uint32_t o = tid * 16; o < T.lds_total; o += 256 * 16)
         *reinterpret_cast<uint4 *>(box + o) = make_uint4(0, 0, 0, 0);
@@ -1163,39 +1199,36 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
     const uint32_t W4 = T.W >> 2;
     const uint32_t cbmask = T.CB >= 32 ? 0xFFFFFFFFu : (1u << T.CB) - 1;
+    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
+    PackedPrefetch pf;
+    if (R.first < R.end) packed_prefetch(T, lutw, lutw_stride, in, uint32_t(R.first), hsrc, pf);
     __syncthreads();
 
-    for (uint32_t t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+    uint32_t it = 0;
+    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
+        const uint32_t t = uint32_t(t64);
         const uint32_t B = t * K;  // first cell of the tile (< 2^32)
         const uint32_t ph = B & 31, w0 = B >> 5, nw = (ph + K + 31) >> 5;
-        const uint16_t *lut = lutw + ph * lutw_stride;
+        uint32_t *stage = stage0 + (it & 1) * nsw;
         // 1. the tile's bits and its halo into the box; clear the output words
-        for (uint32_t c = tid; c < nw; c += 256) {
-            const uint32_t word = in[w0 + c];
-            const uint4 *e4 = reinterpret_cast<const uint4 *>(lut + 32 * c);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 e = e4[q];
-                const uint32_t ee[4] = {e.x, e.y, e.z, e.w};
+        for (uint32_t j = 0; j < kPkWPT; ++j) {
+            const uint32_t l = tid + 256 * j;
+            if (l < 4 * nw) {
+                const uint32_t bits8 = pf.word[j] >> (8 * (l & 3));
+                const uint32_t ee[4] = {pf.e[j].x, pf.e[j].y, pf.e[j].z, pf.e[j].w};
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    box[(ee[k >> 1] >> (16 * (k & 1))) & 0xFFFFu] = uint8_t((word >> (8 * q + k)) & 1u);
+                    box[(ee[k >> 1] >> (16 * (k & 1))) & 0xFFFFu] = uint8_t((bits8 >> k) & 1u);
             }
-            stage[c] = 0;
         }
 #pragma unroll
-        for (uint32_t j = 0; j < kPkHPT; ++j) {
-            const uint32_t src = hsrc[j];
-            const uint32_t ntile = src != kOutside ? T.nbr[t * 8 + (src >> 29)] : kOutside;
-            uint32_t v = 0;
-            if (ntile != kOutside) {
-                const uint32_t bit = ntile * K + (src & 0x1FFFFFFFu);
-                v = (in[bit >> 5] >> (bit & 31)) & 1u;
-            }
-            box[hdst[j]] = uint8_t(v);
-        }
+        for (uint32_t j = 0; j < kPkHPT; ++j) box[hdst[j]] = uint8_t(pf.halo[j]);
+        for (uint32_t c = tid; c < nw; c += 256) stage[c] = 0;
         __syncthreads();
-        // 2. the rule per block; its CB bits into the tile's output words
+        // 2. load the next tile while this one computes
+        if (t64 + R.step < R.end) packed_prefetch(T, lutw, lutw_stride, in, uint32_t(t64 + R.step), hsrc, pf);
+        // 3. the rule per block; its CB bits into the tile's output words
 #pragma unroll
         for (uint32_t j = 0; j < kPkBPT; ++j) {
             const uint32_t bi = tid + 256 * j;
@@ -1220,7 +1253,9 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
             }
         }
         __syncthreads();
-        // 3. the output words: whole ones stored, the two shared ones merged
+        // 4. the output words: whole ones stored, the two shared ones merged
+        //    (the box and this copy are next written after the next barrier
+        //    and two tiles on, respectively)
         for (uint32_t c = tid; c < nw; c += 256) {
             const uint32_t lo = c == 0 ? ph : 0;
             const uint32_t hi = c + 1 == nw ? ((ph + K - 1) & 31) + 1 : 32;
@@ -1233,7 +1268,6 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
                 atomicOr(&out[w0 + c], v & mask);
             }
         }
-        __syncthreads();
     }
 }
 
@@ -1577,16 +1611,28 @@ hipError_t launch_unpack_bits(const uint32_t *words, uint8_t *bytes, uint64_t ce
     hipLaunchKernelGGL(k_unpack_bits, dim3(grid), dim3(256), 0, st, words, bytes, cells, nwords);
     return hipGetLastError();
 }
-uint32_t packed_stage_words(const TileParams &T) { return (T.K + 62) / 32 + 1; }
+uint32_t packed_stage_words(const TileParams &T) { return 2 * ((T.K + 62) / 32 + 1); }
 bool packed_fits(const TileParams &T) {
     return T.nblk <= kPkBPT * 256 && T.halo_count <= kPkHPT * 256 && T.CB <= 16 &&
-           T.lds_total + 4 * packed_stage_words(T) <= 65536;
+           4 * ((T.K + 62) / 32) <= kPkWPT * 256 && T.lds_total + 4 * packed_stage_words(T) <= 65536;
 }
+// Persistent launch: as many work-groups as can be resident at once.
 template <int BS, bool EDGE>
 static hipError_t launch_packed_t(const TileParams &T, const uint16_t *lutw, uint32_t stride, const uint32_t *in,
                                   uint32_t *out, uint32_t rule, int cu_count, hipStream_t st) {
     const uint32_t lds = T.lds_total + 4 * packed_stage_words(T);
-    const uint32_t grid = uint32_t(std::min<uint64_t>(T.ntiles, uint64_t(cu_count) * 8));
+    static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
+    int per_cu = 0;
+    const uint64_t c = cached.load(std::memory_order_relaxed);
+    if (c >> 32 == lds && (c & 0xFFFFFFFFu)) {
+        per_cu = int(c & 0xFFFFFFFFu);
+    } else {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_packed<BS, EDGE>, 256, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
+    }
+    const uint32_t grid = uint32_t(std::min<uint64_t>(T.ntiles, uint64_t(per_cu) * cu_count));
     hipLaunchKernelGGL((k_step_packed<BS, EDGE>), dim3(grid), dim3(256), lds, st, T, lutw, stride, in, out, rule);
     return hipGetLastError();
 }
