@@ -294,6 +294,24 @@ def main():
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"compact: {ms_step * 1e3:.2f} us/step, {value:.3e} cell-updates/s, {achieved:.0f} GB/s")
 
+    # ---- the same generations on the bit-packed state (1 bit per cell) -----
+    packed = None
+    if info.strategy != N.STRATEGY_DIRECT:
+        Kp = min(K, 200)
+        pa = g.pack(init)
+        pb = torch.zeros_like(pa)
+        g.step_packed(pa.clone(), pb, 2, rule)
+        pa2 = pa.clone()
+        msp, resp = time_events(torch, lambda: g.step_packed(pa2, pb, Kp, rule))
+        refp = g.step_compact(init.clone(), torch.empty_like(init), Kp, rule)
+        packed = {"ms_per_step": msp / Kp, "steps": Kp, "bytes": pa.numel(),
+                  "cell_updates_per_s": g.cells * Kp / (msp * 1e-3),
+                  "alg_gbps": 2 * pa.numel() / (msp / Kp * 1e-3) / 1e9,
+                  "equals_byte_step": bool(torch.equal(g.unpack(resp), refp))}
+        log(f"packed state: {msp / Kp * 1e3:.1f} us/step over {pa.numel()} B, same as byte step: "
+            f"{packed['equals_byte_step']}")
+        del pa, pb, pa2, resp, refp
+
     # ---- box step (baseline) ----------------------------------------------
     bbox = None
     parity = None
@@ -411,6 +429,7 @@ def main():
         "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
         "maps": maps,
         "small_triangle_r10": small,
+        "packed_state": packed,
         "batch": batch,
         "serve": serve,
     }
