@@ -5,7 +5,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <array>
 #include <functional>
 #include <mutex>
 #include <new>
@@ -89,39 +88,34 @@ struct BatchDirect {
     uint64_t offset;
     uint32_t index;
 };
-// Small instances of one plan that run all their generations in LDS, one
-// work-group each, one launch per group.
-struct ResidentGroup {
-    TileParams tp;
-    const BatchInstance *inst = nullptr;  // device table, in `index` order
-    uint32_t *steps = nullptr;            // device: per-instance generation counts (nbb_batch_step_each)
-    std::vector<uint32_t> index;          // the instances (caller's numbering)
-    uint32_t teams = 1;                   // tiles per pass
-    uint32_t lds = 0;                     // LDS of the largest
-    std::vector<uint32_t> passes;         // passes per generation of each instance
+// The small instances that run all their generations in LDS: one launch,
+// one work-group each, every plan in one table.
+struct ResidentSet {
+    const TileParams *plans = nullptr;     // device table, one entry per plan
+    const ResidentInstance *inst = nullptr;  // device table, in `index` order
+    uint32_t *steps = nullptr;             // device: per-instance generation counts (nbb_batch_step_each)
+    std::vector<uint32_t> index;           // the instances (caller's numbering)
+    std::vector<uint32_t> passes;          // passes per generation of each
+    uint32_t lds = 0;                      // LDS of the largest
 };
 // An instance is stepped in LDS only if a generation takes at most this many
 // passes (each about a microsecond: a tile scatter, the rule, two barriers):
 // beyond that the per-generation group launches are faster.
 constexpr uint32_t kResidentMaxPasses = 8;
-// Resident groups of different plans run on up to this many streams of a
-// per-device pool, so that they overlap each other (and the group launches).
-constexpr int kResidentStreams = 4;
 struct nbb_batch {
     int device = 0;
     int cu_count = 256;
     uint32_t count = 0;
     uint64_t cells = 0, tiles = 0, arena_bytes = 0;
     std::vector<BatchGroup> groups;
-    std::vector<ResidentGroup> resident;
+    ResidentSet resident;
     std::vector<BatchDirect> direct;
     DevBlob dtab;
-    // the resident launches run on streams of the device's pool, forked from
-    // and joined back to the caller's stream, so that they overlap the
-    // per-generation launches and each other
-    hipStream_t side[kResidentStreams] = {};
-    hipEvent_t fork = nullptr, join[kResidentStreams] = {};
-    int nside = 0;
+    // with group or direct launches beside it, the resident launch runs on the
+    // device's side stream, forked from and joined back to the caller's
+    // stream, so that the two overlap
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -639,30 +633,27 @@ static const TileParams *resident_plan(const nbb_fractal *F, uint32_t *teams) {
     return &F->res_tp;
 }
 
-// The device's pool of streams for resident launches (created on first use,
+// The device's side stream for resident launches (created on first use,
 // kept until the process ends; default priority, non-blocking).
-static hipError_t resident_streams(int dev, hipStream_t (&out)[kResidentStreams]) {
+static hipError_t resident_stream(int dev, hipStream_t *out) {
     static std::mutex mu;
-    static std::vector<std::array<hipStream_t, kResidentStreams>> pool;
+    static std::vector<hipStream_t> pool;
     std::lock_guard<std::mutex> lock(mu);
-    if (pool.size() <= size_t(dev)) pool.resize(dev + 1, std::array<hipStream_t, kResidentStreams>{});
-    for (int i = 0; i < kResidentStreams; ++i) {
-        if (!pool[dev][i]) {
-            hipError_t e = hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking);
-            if (e != hipSuccess) {
-                pool[dev][i] = nullptr;
-                return e;
-            }
+    if (pool.size() <= size_t(dev)) pool.resize(dev + 1, nullptr);
+    if (!pool[dev]) {
+        hipError_t e = hipStreamCreateWithFlags(&pool[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            pool[dev] = nullptr;
+            return e;
         }
-        out[i] = pool[dev][i];
     }
+    *out = pool[dev];
     return hipSuccess;
 }
 
 static void batch_free(nbb_batch *B) {
     if (B->fork) (void)hipEventDestroy(B->fork);
-    for (hipEvent_t &j : B->join)
-        if (j) (void)hipEventDestroy(j);
+    if (B->join) (void)hipEventDestroy(B->join);
     blob_free(&B->dtab);
     delete B;
 }
@@ -780,7 +771,7 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
     // (2 words per tile) and the neighbour table (8 words per tile); per
     // resident group its instance table.
     const size_t ng = launch.reps.size(), nr = res.reps.size();
-    std::vector<size_t> off_inst(ng), off_rec(ng), off_nbr(ng), ntiles(ng), off_res(nr);
+    std::vector<size_t> off_inst(ng), off_rec(ng), off_nbr(ng), ntiles(ng);
     size_t total = 0;
     for (size_t g = 0; g < ng; ++g) {
         uint64_t t = 0;
@@ -801,14 +792,17 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
         off_nbr[g] = total;
         total += align256(std::max<size_t>(t * 32, 1));
     }
-    std::vector<size_t> off_rsteps(nr);
+    size_t nres = 0;
     for (size_t g = 0; g < nr; ++g) {
         for (const BatchInstance &I : res.members[g]) B->tiles += I.ntiles;
-        off_res[g] = total;
-        total += align256(res.members[g].size() * sizeof(BatchInstance));
-        off_rsteps[g] = total;
-        total += align256(res.members[g].size() * sizeof(uint32_t));
+        nres += res.members[g].size();
     }
+    const size_t off_plans = total;
+    total += nr ? align256(nr * sizeof(TileParams)) : 0;
+    const size_t off_rinst = total;
+    total += nres ? align256(nres * sizeof(ResidentInstance)) : 0;
+    const size_t off_rsteps = total;
+    total += nres ? align256(nres * sizeof(uint32_t)) : 0;
     if (total) {
         e = hipMalloc(&B->dtab.ptr, total);
         if (e != hipSuccess) {
@@ -846,46 +840,55 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
         B->groups.push_back(std::move(G));
         B->cu_count = launch.reps[g]->cu_count;
     }
-    const uint32_t lds_budget = nr ? device_lds_per_group() : 0;
-    for (size_t g = 0; g < nr; ++g) {
-        auto *inst = reinterpret_cast<BatchInstance *>(base + off_res[g]);
-        e = hipMemcpyAsync(inst, res.members[g].data(), res.members[g].size() * sizeof(BatchInstance),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (nr) {
+        // tiles per pass per plan: as many (up to 4) as the registers and LDS
+        // allow for the plan's largest instance
+        const uint32_t lds_budget = device_lds_per_group();
+        std::vector<TileParams> plans(nr);
+        std::vector<ResidentInstance> rinst;
+        ResidentSet &R = B->resident;
+        for (size_t g = 0; g < nr; ++g) {
+            plans[g] = res.reps[g]->res_tp;
+            uint32_t most = 1;
+            for (const BatchInstance &I : res.members[g]) most = std::max(most, I.ntiles);
+            uint32_t teams = 1;
+            for (uint32_t t : {4u, 2u})
+                if (t <= most && resident_fits(plans[g], t) && resident_lds_bytes(plans[g], most, t) <= lds_budget) {
+                    teams = t;
+                    break;
+                }
+            R.lds = std::max(R.lds, resident_lds_bytes(plans[g], most, teams));
+            for (size_t j = 0; j < res.members[g].size(); ++j) {
+                const BatchInstance &I = res.members[g][j];
+                rinst.push_back({I.nbr, I.base16, I.ntiles, uint32_t(g), teams});
+                R.index.push_back(res.index[g][j]);
+                R.passes.push_back((I.ntiles + teams - 1) / teams);
+            }
+        }
+        auto *dplans = reinterpret_cast<TileParams *>(base + off_plans);
+        auto *dinst = reinterpret_cast<ResidentInstance *>(base + off_rinst);
+        e = hipMemcpyAsync(dplans, plans.data(), nr * sizeof(TileParams), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dinst, rinst.data(), rinst.size() * sizeof(ResidentInstance), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host tables go out of scope
         if (e != hipSuccess) {
             batch_free(B);
             return hip_fail(e, "batch table build");
         }
-        ResidentGroup R;
-        R.tp = res.reps[g]->res_tp;
-        R.inst = inst;
-        R.steps = reinterpret_cast<uint32_t *>(base + off_rsteps[g]);
-        R.index = res.index[g];
-        // tiles per pass: as many (up to 4) as the registers and LDS allow
-        // for the group's largest instance
-        uint32_t most = 1;
-        for (const BatchInstance &I : res.members[g]) most = std::max(most, I.ntiles);
-        R.teams = 1;
-        for (uint32_t t : {4u, 2u})
-            if (t <= most && resident_fits(R.tp, t) && resident_lds_bytes(R.tp, most, t) <= lds_budget) {
-                R.teams = t;
-                break;
-            }
-        R.lds = resident_lds_bytes(R.tp, most, R.teams);
-        for (const BatchInstance &I : res.members[g]) R.passes.push_back((I.ntiles + R.teams - 1) / R.teams);
-        B->resident.push_back(std::move(R));
+        R.plans = dplans;
+        R.inst = dinst;
+        R.steps = reinterpret_cast<uint32_t *>(base + off_rsteps);
     }
     for (const BatchDirect &d : B->direct) B->cu_count = d.f->cu_count;
-    // side streams unless one resident group is all there is
-    if (!B->resident.empty() && (B->resident.size() > 1 || !B->groups.empty() || !B->direct.empty())) {
-        B->nside = int(std::min<size_t>(B->resident.size(), kResidentStreams));
-        e = resident_streams(dev, B->side);
+    // a side stream if the resident launch has group or direct launches beside it
+    if (!B->resident.index.empty() && (!B->groups.empty() || !B->direct.empty())) {
+        e = resident_stream(dev, &B->side);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
-        for (int i = 0; i < B->nside && e == hipSuccess; ++i)
-            e = hipEventCreateWithFlags(&B->join[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->join, hipEventDisableTiming);
         if (e != hipSuccess) {
+            B->side = nullptr;
             batch_free(B);
-            return hip_fail(e, "batch streams");
+            return hip_fail(e, "batch stream");
         }
     }
     *out = B;
@@ -902,7 +905,7 @@ nbb_status nbb_batch_query(const nbb_batch *B, nbb_batch_info *info) {
     info->instances = B->count;
     info->groups = uint32_t(B->groups.size());
     info->direct = uint32_t(B->direct.size());
-    for (const ResidentGroup &R : B->resident) info->resident += uint32_t(R.index.size());
+    info->resident = uint32_t(B->resident.index.size());
     info->cells = B->cells;
     info->tiles = B->tiles;
     info->arena_bytes = B->arena_bytes;
@@ -910,68 +913,43 @@ nbb_status nbb_batch_query(const nbb_batch *B, nbb_batch_info *info) {
     return NBB_OK;
 }
 
-// Enqueues the resident groups (instance i of the batch takes steps[i]
-// generations, or steps_all if steps is NULL): on the caller's stream if
-// nothing else runs, else on the batch's side stream, forked from it here;
-// batch_join_resident joins it back.  One launch per group: the per-instance
-// counts go to the group's device array first.
+// Enqueues the resident launch (instance i of the batch takes steps[i]
+// generations, or steps_all if steps is NULL; the per-instance counts go to
+// the batch's device array first): on the caller's stream if nothing else
+// runs, else on the side stream, forked from it here; batch_join_resident
+// joins it back.  *launched tells whether anything was enqueued.
 static hipError_t batch_fork_resident(const nbb_batch *B, uint8_t *a, uint8_t *b, uint32_t rule,
-                                      const uint32_t *steps, uint32_t steps_all, hipStream_t s) {
-    if (B->resident.empty()) return hipSuccess;
-    if (B->nside) {
-        hipError_t e = hipEventRecord(B->fork, s);
-        for (int i = 0; i < B->nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(B->side[i], B->fork, 0);
-        if (e != hipSuccess) return e;
-    }
-    // Each launch lasts about (its instances' largest passes x generations)
-    // passes: longest first, each to the stream with the least work so far.
-    const size_t ng = B->resident.size();
-    std::vector<uint64_t> cost(ng, 0);
-    for (size_t g = 0; g < ng; ++g) {
-        const ResidentGroup &R = B->resident[g];
-        for (size_t j = 0; j < R.index.size(); ++j)
-            cost[g] = std::max<uint64_t>(cost[g], uint64_t(R.passes[j]) * (steps ? steps[R.index[j]] : steps_all));
-    }
-    std::vector<size_t> order(ng);
-    std::iota(order.begin(), order.end(), size_t(0));
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    uint64_t load[kResidentStreams] = {};
+                                      const uint32_t *steps, uint32_t steps_all, hipStream_t s, bool *launched_) {
+    *launched_ = false;
+    const ResidentSet &R = B->resident;
+    const uint32_t count = uint32_t(R.index.size());
+    if (!count) return hipSuccess;
     std::vector<uint32_t> n;
-    for (size_t g : order) {
-        const ResidentGroup &R = B->resident[g];
-        if (!cost[g]) continue;  // no instance of the group takes a generation
-        hipStream_t rs = s;
-        if (B->nside) {
-            int best = 0;
-            for (int i = 1; i < B->nside; ++i)
-                if (load[i] < load[best]) best = i;
-            load[best] += cost[g];
-            rs = B->side[best];
-        }
-        const uint32_t count = uint32_t(R.index.size());
-        const uint32_t *steps_of = nullptr;
-        if (steps) {
-            n.resize(count);
-            for (uint32_t j = 0; j < count; ++j) n[j] = steps[R.index[j]];
-            hipError_t e = launch_set_words(R.steps, n.data(), count, rs);
-            if (e != hipSuccess) return e;
-            steps_of = R.steps;
-        }
-        hipError_t e = launch_step_resident(R.tp, R.inst, count, steps_of, steps_all, R.teams, R.lds, a, b, rule, rs);
+    bool any = steps_all != 0;
+    if (steps) {
+        n.resize(count);
+        for (uint32_t j = 0; j < count; ++j) any |= (n[j] = steps[R.index[j]]) != 0;
+    }
+    if (!any) return hipSuccess;
+    hipStream_t rs = s;
+    if (B->side) {
+        hipError_t e = hipEventRecord(B->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(B->side, B->fork, 0);
+        if (e != hipSuccess) return e;
+        rs = B->side;
+    }
+    if (steps) {
+        hipError_t e = launch_set_words(R.steps, n.data(), count, rs);
         if (e != hipSuccess) return e;
     }
-    for (int i = 0; i < B->nside; ++i) {
-        hipError_t e = hipEventRecord(B->join[i], B->side[i]);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipError_t e = launch_step_resident(R.plans, R.inst, count, steps ? R.steps : nullptr, steps_all, R.lds, a, b,
+                                        rule, rs);
+    if (e == hipSuccess && B->side) e = hipEventRecord(B->join, B->side);
+    *launched_ = e == hipSuccess;
+    return e;
 }
-static hipError_t batch_join_resident(const nbb_batch *B, hipStream_t s) {
-    for (int i = 0; i < B->nside; ++i) {
-        hipError_t e = hipStreamWaitEvent(s, B->join[i], 0);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+static hipError_t batch_join_resident(const nbb_batch *B, hipStream_t s, bool launched_) {
+    return (launched_ && B->side) ? hipStreamWaitEvent(s, B->join, 0) : hipSuccess;
 }
 
 nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
@@ -989,7 +967,8 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     if (result_in_b) *result_in_b = int(steps & 1);
     if (!steps) return NBB_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = batch_fork_resident(B, a, b, rule, nullptr, steps, s);
+    bool res_launched = false;
+    e = batch_fork_resident(B, a, b, rule, nullptr, steps, s, &res_launched);
     if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
     uint8_t *in = a, *out = b;
     for (uint32_t i = 0; i < steps; ++i) {
@@ -1005,7 +984,7 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
         }
         std::swap(in, out);
     }
-    e = batch_join_resident(B, s);
+    e = batch_join_resident(B, s, res_launched);
     return e == hipSuccess ? NBB_OK : hip_fail(e, "batch resident join");
 }
 
@@ -1033,13 +1012,9 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     // than g steps; instance i's state alternates a -> b -> a ... like the
     // whole batch's, so its result ends in b iff steps[i] is odd.
     hipStream_t s = static_cast<hipStream_t>(stream);
-    uint32_t most_res = 0;
-    for (const ResidentGroup &R : B->resident)
-        for (uint32_t i : R.index) most_res = std::max(most_res, steps[i]);
-    if (most_res) {
-        e = batch_fork_resident(B, a, b, rule, steps, 0, s);
-        if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
-    }
+    bool res_launched = false;
+    e = batch_fork_resident(B, a, b, rule, steps, 0, s, &res_launched);
+    if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
     std::vector<size_t> live(B->groups.size());
     for (size_t k = 0; k < B->groups.size(); ++k) live[k] = B->groups[k].index.size();
     uint8_t *in = a, *out = b;
@@ -1062,10 +1037,8 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
         }
         std::swap(in, out);
     }
-    if (most_res) {
-        e = batch_join_resident(B, s);
-        if (e != hipSuccess) return hip_fail(e, "batch resident join");
-    }
+    e = batch_join_resident(B, s, res_launched);
+    if (e != hipSuccess) return hip_fail(e, "batch resident join");
     return NBB_OK;
 }
 

@@ -963,8 +963,9 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 // ---------------------------------------------------------------------------
 // Batched step, LDS-resident form for small instances: work-group w owns
 // instance w of the launch (steps_of[w] generations, or steps_all for every
-// instance if steps_of is NULL) and runs all of them without touching
-// global memory in between.  LDS holds `teams` tile boxes, two copies of the
+// instance if steps_of is NULL; its tile plan from the launch's plan table,
+// so instances of every shape share one launch) and runs all of them
+// without touching global memory in between.  LDS holds `teams` tile boxes, two copies of the
 // instance's state (this generation and the next; tile t at bytes
 // [t Kp, t Kp + K), Kp = K rounded up to 16, so every tile starts a 16-byte
 // chunk and the phase-0 scatter table serves all of them) and the
@@ -982,17 +983,13 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 // ---------------------------------------------------------------------------
 constexpr uint32_t kResCPT = 2, kResHPT = 4, kResBPT = 4;
 template <int BS, bool EDGE>
-__global__ __launch_bounds__(256) void k_step_resident(TileParams T, const BatchInstance *__restrict__ inst,
-                                                       const uint32_t *__restrict__ steps_of, uint32_t steps_all,
-                                                       uint32_t teams, uint8_t *__restrict__ a,
-                                                       uint8_t *__restrict__ b, uint32_t rule) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    const uint32_t steps = steps_of ? steps_of[blockIdx.x] : steps_all;
-    if (!steps) return;
+__device__ __forceinline__ void resident_body(const TileParams &T, const ResidentInstance &I, uint32_t steps,
+                                              uint8_t *lds, uint8_t *__restrict__ a, uint8_t *__restrict__ b,
+                                              uint32_t rule) {
     const uint32_t tid = threadIdx.x;
+    const uint32_t teams = I.teams;
     const uint32_t tsize = 256 / teams;
     const uint32_t team = tid / tsize, lt = tid % tsize;
-    const BatchInstance I = inst[blockIdx.x];
     const uint32_t K = T.K, Kp = (K + 15) & ~15u, nt = I.ntiles;
     const uint32_t cells = nt * K;
     uint8_t *box = lds + team * T.lds_total;
@@ -1097,6 +1094,23 @@ __global__ __launch_bounds__(256) void k_step_resident(TileParams T, const Batch
     for (uint32_t i = tid; i < cells; i += 256) {
         const uint32_t t = udiv(T.divK, i);
         gout[i] = cur[t * Kp + (i - t * K)];
+    }
+}
+template <bool EDGE>
+__global__ __launch_bounds__(256) void k_step_resident(const TileParams *__restrict__ plans,
+                                                       const ResidentInstance *__restrict__ inst,
+                                                       const uint32_t *__restrict__ steps_of, uint32_t steps_all,
+                                                       uint8_t *__restrict__ a, uint8_t *__restrict__ b,
+                                                       uint32_t rule) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint32_t steps = steps_of ? steps_of[blockIdx.x] : steps_all;
+    if (!steps) return;
+    const ResidentInstance I = inst[blockIdx.x];
+    const TileParams T = plans[I.plan];
+    switch (T.BS) {  // uniform over the work-group
+        case 2: resident_body<2, EDGE>(T, I, steps, lds, a, b, rule); break;
+        case 3: resident_body<3, EDGE>(T, I, steps, lds, a, b, rule); break;
+        default: resident_body<4, EDGE>(T, I, steps, lds, a, b, rule); break;
     }
 }
 
@@ -1532,28 +1546,17 @@ bool resident_fits(const TileParams &T, uint32_t teams) {
     return teams && 256 % teams == 0 && nchunks <= kResCPT * tsize && T.halo_count <= kResHPT * tsize &&
            T.nblk <= kResBPT * tsize;
 }
-template <int BS, bool EDGE>
-static hipError_t launch_resident_t(const TileParams &T, const BatchInstance *inst, uint32_t count,
-                                    const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
-                                    uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st) {
-    hipLaunchKernelGGL((k_step_resident<BS, EDGE>), dim3(count), dim3(256), lds, st, T, inst, steps_of, steps_all,
-                       teams, a, b, rule);
-    return hipGetLastError();
-}
-hipError_t launch_step_resident(const TileParams &T, const BatchInstance *inst, uint32_t count,
-                                const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
-                                uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st) {
+hipError_t launch_step_resident(const TileParams *plans, const ResidentInstance *inst, uint32_t count,
+                                const uint32_t *steps_of, uint32_t steps_all, uint32_t lds, uint8_t *a, uint8_t *b,
+                                uint32_t rule, hipStream_t st) {
     if (!count) return hipSuccess;
-    if (!resident_fits(T, teams)) return hipErrorInvalidValue;
-    const bool edge = (rule >> 31) != 0;
-#define NBB_RES(BS_, E_) launch_resident_t<BS_, E_>(T, inst, count, steps_of, steps_all, teams, lds, a, b, rule, st)
-    switch (T.BS) {
-        case 2: return edge ? NBB_RES(2, true) : NBB_RES(2, false);
-        case 3: return edge ? NBB_RES(3, true) : NBB_RES(3, false);
-        case 4: return edge ? NBB_RES(4, true) : NBB_RES(4, false);
-        default: return hipErrorInvalidValue;
-    }
-#undef NBB_RES
+    if ((rule >> 31) != 0)
+        hipLaunchKernelGGL(k_step_resident<true>, dim3(count), dim3(256), lds, st, plans, inst, steps_of, steps_all,
+                           a, b, rule);
+    else
+        hipLaunchKernelGGL(k_step_resident<false>, dim3(count), dim3(256), lds, st, plans, inst, steps_of,
+                           steps_all, a, b, rule);
+    return hipGetLastError();
 }
 __global__ __launch_bounds__(256) void k_set_words(uint32_t *__restrict__ dst, WordChunk w, uint32_t n) {
     if (threadIdx.x < n) dst[threadIdx.x] = w.v[threadIdx.x];

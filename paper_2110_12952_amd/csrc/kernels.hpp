@@ -50,14 +50,15 @@ uint32_t resident_lds_bytes(const TileParams &T, uint32_t ntiles, uint32_t teams
 // Whether a tile of plan T fits the per-thread registers of the resident step
 // when a work-group works on `teams` (1, 2 or 4) tiles at a time.
 bool resident_fits(const TileParams &T, uint32_t teams);
-// All generations of `count` small instances of plan T, one work-group each
-// (inst: device table; instance w takes steps_of[w] generations, a device
-// array, or steps_all if steps_of is NULL; `teams` tiles at a time; lds =
-// resident_lds_bytes of the largest).  Instance w's result ends in a if its
-// generation count is even, else in b.
-hipError_t launch_step_resident(const TileParams &T, const BatchInstance *inst, uint32_t count,
-                                const uint32_t *steps_of, uint32_t steps_all, uint32_t teams, uint32_t lds,
-                                uint8_t *a, uint8_t *b, uint32_t rule, hipStream_t st);
+// All generations of `count` small instances, one work-group each (inst:
+// device table; plans: device table of the plans inst[w].plan indexes, each
+// checked with resident_fits for its instances' teams; instance w takes
+// steps_of[w] generations, a device array, or steps_all if steps_of is NULL;
+// lds = the largest resident_lds_bytes).  Instance w's result ends in a if
+// its generation count is even, else in b.
+hipError_t launch_step_resident(const TileParams *plans, const ResidentInstance *inst, uint32_t count,
+                                const uint32_t *steps_of, uint32_t steps_all, uint32_t lds, uint8_t *a, uint8_t *b,
+                                uint32_t rule, hipStream_t st);
 // Stores n host words at dst (device) in stream order, through kernels that
 // take them as arguments (no host memory is read after the call returns).
 hipError_t launch_set_words(uint32_t *dst, const uint32_t *src, uint32_t n, hipStream_t st);

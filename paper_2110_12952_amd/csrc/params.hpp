@@ -99,6 +99,17 @@ struct BatchInstance {
     uint32_t tail_partial;  // 1 if k^r is not a multiple of 16
 };
 
+// One small instance of a batch stepped in LDS: its state at byte
+// 16 * base16 of the arenas, `ntiles` tiles of plan `plan` (an index into the
+// launch's plan table) taken `teams` at a time, its own neighbour table.
+struct ResidentInstance {
+    const uint32_t *nbr;
+    uint32_t base16;
+    uint32_t ntiles;
+    uint32_t plan;
+    uint32_t teams;
+};
+
 // Up to 256 words passed by value to a kernel that stores them.
 constexpr uint32_t kWordChunk = 256;
 struct WordChunk {
