@@ -297,11 +297,11 @@ nbb_status nbb_autotune(nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, ui
  * generations of it in one launch, with no global traffic between
  * generations, at a tile level of its own (the one with the fewest passes;
  * built with the descriptor on the first batch that needs it, and independent
- * of nbb_configure).  These launches, one per plan, run on streams of a
- * per-device pool of the library (4 streams, kept until the process ends)
- * that are forked from `stream` at the start of each step call and joined
- * back to it before the call's last enqueued work (so, seen from `stream`,
- * the call's work is ordered as before).  Step calls on one batch
+ * of nbb_configure).  All of them share one launch; beside group or direct
+ * launches it runs on a side stream of the library (one per device, kept
+ * until the process ends) that is forked from `stream` at the start of each
+ * step call and joined back to it before the call's last enqueued work (so,
+ * seen from `stream`, the call's work is ordered as before).  Step calls on one batch
  * share its small device tables: enqueue them from one host thread, and order
  * calls made on different streams (an event) before the later one starts.
  *
