@@ -492,9 +492,10 @@ struct TilePrefetch {
 // length is not a multiple of 16, so its last chunk may not be read whole.
 // The scatter offsets depend only on the tile's phase (t K mod 16), and a
 // worker's tiles usually share it (consecutive tiles of a worker are a
-// multiple of 16 tiles apart), so they are reloaded only when the phase
-// differs from `pf_ph`, the phase of the offsets held in pf.e.
-template <int TEAM, int CPT, int HPT>
+// multiple of 16 tiles apart), so with KEEP they are reloaded only when the
+// phase differs from `pf_ph`, the phase of the offsets held in pf.e.  (Over
+// the tiles of a batch, measured slower: the batched step reloads always.)
+template <int TEAM, int CPT, int HPT, bool KEEP>
 __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t *__restrict__ in,
                                               uint32_t t, bool tail, uint32_t cells, const uint32_t *nb,
                                               const uint32_t *hsrc, TilePrefetch<CPT, HPT> &pf, uint32_t &pf_ph) {
@@ -504,7 +505,7 @@ __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t
     const uint32_t nchunks = (ph + T.K + 15) >> 4;
     const uint8_t *gin = in + (B & ~15u);  // uniform; chunk c at gin + 16 c
     const uint16_t *lut = T.lut0p + ph * T.lut0_stride;
-    const bool reload = ph != pf_ph;       // uniform
+    const bool reload = !KEEP || ph != pf_ph;  // uniform
     pf_ph = ph;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -903,7 +904,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     uint32_t pf_ph = 0xFFFFFFFFu;  // no offsets loaded yet
     if (R.first < R.end) {
         locate(R.first, nbr[0]);
-        tile_prefetch<TEAM, CPT, HPT>(T, src, local, tail, cells, nbr[0], hsrc, pf, pf_ph);
+        tile_prefetch<TEAM, CPT, HPT, !BATCH>(T, src, local, tail, cells, nbr[0], hsrc, pf, pf_ph);
     }
 
     const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
@@ -935,7 +936,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
         if (t64 + R.step < R.end) {
             const uint32_t *e = nbr[(it + 1) & 1];
             locate(t64 + R.step, e);
-            tile_prefetch<TEAM, CPT, HPT>(T, src, local, tail, cells, e, hsrc, pf, pf_ph);
+            tile_prefetch<TEAM, CPT, HPT, !BATCH>(T, src, local, tail, cells, e, hsrc, pf, pf_ph);
         }
         uint32_t nb2 = kOutside;
         if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
