@@ -385,9 +385,16 @@ def main():
         ms_m, _ = time_events(torch, lambda: g.lam(out=(x2, y2), method=method), args.map_reps)
         maps[f"lambda_{name}_gbps"] = 8 * g.cells * args.map_reps / (ms_m * 1e-3) / 1e9
         maps[f"lambda_{name}_matches_lut"] = bool(torch.equal(x2, x) and torch.equal(y2, y))
-    msd, _ = time_events(torch, lambda: g.nu(x, y, out=idx, method=N.MAP_DIGITS), args.map_reps)
-    maps["nu_digits_gbps"] = 12 * g.cells * args.map_reps / (msd * 1e-3) / 1e9
-    del x2, y2
+    idx2 = torch.empty_like(idx)
+    for name, method in (("digits", N.MAP_DIGITS), ("mfma", N.MAP_MFMA)):
+        try:
+            g.nu(x, y, out=idx2, method=method)
+        except N.NbbError:
+            continue
+        ms_n, _ = time_events(torch, lambda: g.nu(x, y, out=idx2, method=method), args.map_reps)
+        maps[f"nu_{name}_gbps"] = 12 * g.cells * args.map_reps / (ms_n * 1e-3) / 1e9
+        maps[f"nu_{name}_matches_lut"] = bool(torch.equal(idx2, idx))
+    del x2, y2, idx2
     log("maps: " + ", ".join(f"{k} {v:.0f}" if isinstance(v, float) else f"{k} {v}" for k, v in maps.items()))
     del x, y, idx
 

@@ -144,9 +144,10 @@ nbb_status nbb_nu(const nbb_fractal *f, const int32_t *x, const int32_t *y, uint
  * The same maps evaluated three ways (results identical):
  *   NBB_MAP_LUT    chunked look-up tables (the default of nbb_lambda / nbb_nu);
  *   NBB_MAP_DIGITS one level per step, as the per-thread maps of section 3.1;
- *   NBB_MAP_MFMA   lambda only: digits per item as NBB_MAP_DIGITS, the
- *                  per-level sum as an int8 matrix-core contraction (the
- *                  matrix encoding of section 3.1 on gfx950 matrix cores;
+ *   NBB_MAP_MFMA   digits per item as NBB_MAP_DIGITS, the per-level sum as
+ *                  an int8 matrix-core contraction (the matrix encoding of
+ *                  section 3.1 on gfx950 matrix cores: one-hot digits, resp.
+ *                  replica ids, times 7-bit planes of o_j s^mu, resp. j k^mu;
  *                  needs r*k <= 192 and n <= 2^28, else NBB_E_INVALID).
  * Same arguments, results and errors as nbb_lambda / nbb_nu otherwise.
  */

@@ -258,13 +258,14 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
 
 nbb_status upload_mfma(nbb_fractal *F) {
     if (!F->mfma.ktiles) return NBB_OK;
-    const void *src[1] = {F->mfma.A.data()};
-    size_t bytes[1] = {F->mfma.A.size()};
-    void *dst[1];
-    nbb_status s = upload(&F->dmfma, src, bytes, 1, dst);
+    const void *src[2] = {F->mfma.A.data(), F->mfma.Anu.data()};
+    size_t bytes[2] = {F->mfma.A.size(), F->mfma.Anu.size()};
+    void *dst[2];
+    nbb_status s = upload(&F->dmfma, src, bytes, 2, dst);
     if (s != NBB_OK) return s;
     F->ml.ktiles = F->mfma.ktiles;
     F->ml.A = static_cast<const int8_t *>(dst[0]);
+    F->ml.Anu = static_cast<const int8_t *>(dst[1]);
     return NBB_OK;
 }
 
@@ -1077,8 +1078,9 @@ nbb_status nbb_lambda(const nbb_fractal *F, const uint32_t *idx, uint64_t count,
 nbb_status nbb_nu_method(const nbb_fractal *F, uint32_t method, const int32_t *x, const int32_t *y, uint64_t count,
                          uint32_t *idx, void *stream) {
     if (!F) return fail(NBB_E_INVALID, "null descriptor");
-    if (method != NBB_MAP_LUT && method != NBB_MAP_DIGITS)
-        return fail(NBB_E_INVALID, "nu supports the look-up-table and digit methods");
+    if (method > NBB_MAP_MFMA) return fail(NBB_E_INVALID, "unknown map method");
+    if (method == NBB_MAP_MFMA && !F->ml.ktiles)
+        return fail(NBB_E_INVALID, "the matrix-core nu needs r*k <= 192 and n <= 2^28");
     if (count == 0) return NBB_OK;
     if (!x || !y || !idx) return fail(NBB_E_INVALID, "null argument");
     nbb_status st = check_device(F);
@@ -1086,6 +1088,8 @@ nbb_status nbb_nu_method(const nbb_fractal *F, uint32_t method, const int32_t *x
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (method == NBB_MAP_DIGITS)
         return launched(launch_nu_digits(F->mp, x, y, count, idx, map_grid(F, count), s), "nu launch");
+    if (method == NBB_MAP_MFMA)
+        return launched(launch_nu_mfma(F->mp, F->ml, x, y, count, idx, map_grid(F, count), s), "nu launch");
     return launched(launch_nu(F->mp, F->nu_halves, x, y, count, idx, map_grid(F, count), s), "nu launch");
 }
 

@@ -281,6 +281,66 @@ __global__ __launch_bounds__(256) void k_lambda_mfma(MapParams P, MfmaLambda M, 
     }
 }
 
+// nu with the per-level sum on the matrix cores: each lane takes one item,
+// extracts its r digit pairs (as k_nu_digits) and writes the one-hot bytes of
+// their replica ids; D = Anu B gives the five 7-bit planes of the index in
+// rows 0-4, i.e. rows 0-3 in lanes 0-15 and row 4 in lanes 16-31 of each
+// 16-item group, which one cross-lane read brings together.
+__global__ __launch_bounds__(256) void k_nu_mfma(MapParams P, MfmaLambda M, const int32_t *__restrict__ x,
+                                                 const int32_t *__restrict__ y, uint64_t count,
+                                                 uint32_t *__restrict__ idx) {
+    __shared__ uint8_t sox[256], soy[256], shl[256];
+    __shared__ uint8_t sbad[256];                      // item outside the fractal
+    extern __shared__ __align__(16) uint8_t onehot[];  // 256 items x 32 * ktiles bytes
+    load_small_tables(P, sox, soy, shl);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t KB = 32 * M.ktiles;
+    long afrag[8];
+#pragma unroll
+    for (int kt = 0; kt < 8; ++kt)
+        afrag[kt] = kt < int(M.ktiles)
+                        ? *reinterpret_cast<const long *>(M.Anu + (lane % 16) * KB + 8 * (lane / 16) + 32 * kt)
+                        : 0;
+    uint8_t *row = onehot + tid * KB;
+    const uint64_t ngroups = (count + 255) / 256;
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const uint64_t t = g * 256 + tid;
+        const int32_t X = t < count ? x[t] : -1, Y = t < count ? y[t] : -1;
+        bool bad = uint32_t(X) >= P.n || uint32_t(Y) >= P.n;
+        for (uint32_t o = 0; o < KB; o += 16) *reinterpret_cast<uint4 *>(row + o) = make_uint4(0, 0, 0, 0);
+        uint32_t ux = bad ? 0u : uint32_t(X), uy = bad ? 0u : uint32_t(Y);
+        for (uint32_t mu = 0; mu < P.r; ++mu) {
+            const uint32_t qx = udiv(P.divs, ux), qy = udiv(P.divs, uy);
+            const uint32_t h = shl[(ux - qx * P.s) + P.s * (uy - qy * P.s)];
+            bad |= h == 0xFFu;
+            row[mu * P.k + (h == 0xFFu ? 0u : h)] = 1;
+            ux = qx;
+            uy = qy;
+        }
+        sbad[tid] = bad;
+        __syncthreads();
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            v4i32 acc = {0, 0, 0, 0};
+            const uint32_t it = wave * 64 + grp * 16 + lane % 16;  // item within the work-group's 256
+            const uint8_t *col = onehot + it * KB + 8 * (lane / 16);
+#pragma unroll
+            for (int kt = 0; kt < 8; ++kt)
+                if (kt < int(M.ktiles))
+                    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(afrag[kt], *reinterpret_cast<const long *>(col + 32 * kt),
+                                                               acc, 0, 0, 0);
+            // planes 0-3 here (lanes 0-15), plane 4 in lane + 16; the index is
+            // below 2^32, so the sum wraps to it exactly
+            const uint32_t p4 = uint32_t(__shfl(acc[0], int((lane & 15) + 16)));
+            const uint32_t v = uint32_t(acc[0]) + (uint32_t(acc[1]) << 7) + (uint32_t(acc[2]) << 14) +
+                               (uint32_t(acc[3]) << 21) + (p4 << 28);
+            const uint64_t item = g * 256 + it;
+            if (lane < 16 && item < count) idx[item] = sbad[it] ? kOutside : v;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Initial state: SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) output number
 // key = y*n + x of the stream seeded with `seed`; alive iff its top 24 bits
@@ -1393,6 +1453,11 @@ hipError_t launch_nu_digits(const MapParams &P, const int32_t *x, const int32_t 
 hipError_t launch_lambda_mfma(const MapParams &P, const MfmaLambda &M, const uint32_t *idx, uint64_t count,
                               int32_t *x, int32_t *y, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_lambda_mfma, dim3(grid), dim3(256), size_t(256) * 32 * M.ktiles, st, P, M, idx, count, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_nu_mfma(const MapParams &P, const MfmaLambda &M, const int32_t *x, const int32_t *y, uint64_t count,
+                          uint32_t *idx, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_nu_mfma, dim3(grid), dim3(256), size_t(256) * 32 * M.ktiles, st, P, M, x, y, count, idx);
     return hipGetLastError();
 }
 hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, const int32_t *y,

@@ -15,6 +15,8 @@ hipError_t launch_nu_digits(const MapParams &P, const int32_t *x, const int32_t 
                             int grid, hipStream_t st);
 hipError_t launch_lambda_mfma(const MapParams &P, const MfmaLambda &M, const uint32_t *idx, uint64_t count,
                               int32_t *x, int32_t *y, int grid, hipStream_t st);
+hipError_t launch_nu_mfma(const MapParams &P, const MfmaLambda &M, const int32_t *x, const int32_t *y, uint64_t count,
+                          uint32_t *idx, int grid, hipStream_t st);
 hipError_t launch_nu(const MapParams &P, uint32_t nu_halves, const int32_t *x, const int32_t *y,
                      uint64_t count, uint32_t *idx, int grid, hipStream_t st);
 hipError_t launch_init_compact(const MapParams &P, uint32_t lam_words, uint8_t *state, uint64_t seed,

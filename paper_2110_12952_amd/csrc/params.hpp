@@ -48,9 +48,13 @@ struct MapParams {
 // contraction D = A B with B[(mu, j)][item] = [d_mu(item) == j] (one-hot
 // digits) and A[row][(mu, j)] = 7-bit plane p of o_j.c * s^mu; rows 0-3 hold
 // the four x planes, rows 4-7 the four y planes (coordinates < 2^28).
+// nu the same way: B[(mu, j)][item] = [H_mu(item) == j] (one-hot replica
+// ids of the digit pairs) and Anu[p][(mu, j)] = 7-bit plane p of j k^mu, rows
+// 0-4 (indices < 2^32 need five planes).
 struct MfmaLambda {
     uint32_t ktiles;        // K = 32 * ktiles >= r * k
     const int8_t *A;        // 16 x (32 * ktiles), row-major
+    const int8_t *Anu;      // 16 x (32 * ktiles), row-major
 };
 
 // The tiled compact step: a tile is an aligned run of K = k^m compact cells,

@@ -466,6 +466,12 @@ void build_mfma_tables(const Fractal &f, MfmaTables *t) {
                 t->A[p * KB + mu * f.k + j] = int8_t(((f.ox[j] * scale) >> (7 * p)) & 127);
                 t->A[(4 + p) * KB + mu * f.k + j] = int8_t(((f.oy[j] * scale) >> (7 * p)) & 127);
             }
+    // nu: row p = 7-bit plane p of j k^mu (five planes: indices < 2^32 <= 2^35)
+    t->Anu.assign(size_t(16) * KB, 0);
+    uint64_t kmu = 1;
+    for (uint32_t mu = 0; mu < f.r; ++mu, kmu *= f.k)
+        for (uint32_t j = 0; j < f.k; ++j)
+            for (uint32_t p = 0; p < 5; ++p) t->Anu[p * KB + mu * f.k + j] = int8_t(((j * kmu) >> (7 * p)) & 127);
 }
 
 uint64_t box_pitch(const Fractal &f) { return std::max<uint64_t>(16, (f.n + 15) & ~uint64_t(15)); }

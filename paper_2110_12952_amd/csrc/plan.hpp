@@ -66,11 +66,12 @@ uint32_t auto_tile_level(const Fractal &f);
 // per tile (256 or 64); false if it does not fit.
 bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg, uint32_t team = 256);
 
-// Matrix-core lambda: A (16 x 32*ktiles int8), see MfmaLambda in params.hpp.
-// ktiles == 0 when unsupported (r*k > 192 or n > 2^28).
+// Matrix-core maps: A for lambda and Anu for nu (16 x 32*ktiles int8 each),
+// see MfmaLambda in params.hpp.  ktiles == 0 when unsupported (r*k > 192 or
+// n > 2^28).
 struct MfmaTables {
     uint32_t ktiles = 0;
-    std::vector<int8_t> A;
+    std::vector<int8_t> A, Anu;
 };
 void build_mfma_tables(const Fractal &f, MfmaTables *t);
 

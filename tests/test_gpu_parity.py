@@ -106,13 +106,22 @@ def test_map_methods_agree(N, name, r):
         assert (host(x)[~ok] == -1).all() and (host(y)[~ok] == -1).all()
     yy, xx = np.mgrid[-1:o.n + 1, -1:o.n + 1]
     xs, ys = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
-    np.testing.assert_array_equal(host(g.nu(dev(xs), dev(ys), method=N.MAP_DIGITS)).astype(np.int64),
-                                  o.nu_many(xs, ys))
+    for m in methods:
+        np.testing.assert_array_equal(host(g.nu(dev(xs), dev(ys), method=m)).astype(np.int64),
+                                      o.nu_many(xs, ys), err_msg=f"nu method {m}")
     if r == 0 or r * fd.k > 192:
         with pytest.raises(N.NbbError):
             g.lam(method=N.MAP_MFMA)
+        with pytest.raises(N.NbbError):
+            g.nu(dev(xs), dev(ys), method=N.MAP_MFMA)
+    else:
+        # far outside and the int32 extremes
+        far = np.array([-2**31, 2**31 - 1, o.n + 5, -7, 0], dtype=np.int32)
+        gx, gy = np.repeat(far, 5), np.tile(far, 5)
+        np.testing.assert_array_equal(host(g.nu(dev(gx), dev(gy), method=N.MAP_MFMA)).astype(np.int64),
+                                      o.nu_many(gx, gy))
     with pytest.raises(N.NbbError):
-        g.nu(dev(xs), dev(ys), method=N.MAP_MFMA)
+        g.nu(dev(xs), dev(ys), method=3)
 
 
 def test_map_methods_full_size(N):
@@ -121,7 +130,25 @@ def test_map_methods_full_size(N):
     for m in (N.MAP_DIGITS, N.MAP_MFMA):
         x, y = g.lam(method=m)
         assert torch.equal(x, x0) and torch.equal(y, y0)
-    assert torch.equal(g.nu(x0, y0, method=N.MAP_DIGITS), g.nu(x0, y0))
+    ref = g.nu(x0, y0)
+    assert torch.equal(g.nu(x0, y0, method=N.MAP_DIGITS), ref)
+    assert torch.equal(g.nu(x0, y0, method=N.MAP_MFMA), ref)
+    assert torch.equal(ref.to(torch.int64), torch.arange(g.cells, device="cuda"))
+
+
+def test_nu_mfma_indices_past_2_28(N):
+    # triangle r = 18: indices up to 3^18 - 1 > 2^28 use the fifth 7-bit plane
+    fd = W.TRIANGLE
+    g = N.Fractal(fd.s, fd.offsets, 18)
+    o = O.Fractal(fd.s, fd.offsets, 18)
+    idx = np.concatenate([W.random_indices(18, 4096, o.cells), [0, 2**28 - 1, 2**28, o.cells - 1]]).astype(np.uint32)
+    x, y = g.lam(dev(idx.view(np.int32)))
+    got = host(g.nu(x, y, method=N.MAP_MFMA)).view(np.uint32)
+    np.testing.assert_array_equal(got, idx)
+    sample = idx[-64:].astype(np.int64)
+    ox, oy = o.lam_many(sample)
+    np.testing.assert_array_equal(host(x)[-64:], ox)
+    np.testing.assert_array_equal(o.nu_many(ox.astype(np.int32), oy.astype(np.int32)), sample)
 
 
 def test_maps_empty_count(N):
