@@ -78,6 +78,7 @@ RULES = {
     "B1357/S02468": ((1, 3, 5, 7), (0, 2, 4, 6, 8)),  # Fredkin (self XOR neighbours)
     "B36/S23": ((3, 6), (2, 3)),          # HighLife
     "B2/S": ((2,), ()),                   # Seeds
+    "B35/S0123456": ((3, 5), (0, 1, 2, 3, 4, 5, 6)),  # every survival count below 7 (table edge cases)
     "vN:B13/S13": ((1, 3), (1, 3), 4),    # 4-neighbour parity (XOR of the four)
     "vN:B13/S024": ((1, 3), (0, 2, 4), 4),  # 4-neighbour Fredkin (self XOR the four)
     "vN:B2/S12": ((2,), (1, 2), 4),       # a 4-neighbour life-like rule

@@ -16,7 +16,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 B3S23 = W.rule_mask("B3/S23")
-RULES = ["B3/S23", "B36/S23", "B1357/S02468", "B2/S", "vN:B2/S12", "vN:B13/S024"]
+RULES = ["B3/S23", "B36/S23", "B1357/S02468", "B1357/S1357", "B35/S0123456", "B2/S", "vN:B2/S12",
+         "vN:B13/S024"]
 
 
 @pytest.fixture(scope="module")
