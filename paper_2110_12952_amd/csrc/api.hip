@@ -233,6 +233,7 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     T->BS = p.BS;
     T->CB = p.CB;
     T->nblk = p.nblk;
+    T->brows = p.brows;
     T->box_bytes = p.box_bytes;
     T->lds_total = p.lds_total;
     T->rm = p.rm;

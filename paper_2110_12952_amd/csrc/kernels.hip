@@ -624,13 +624,16 @@ __device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
 //   rules without birth or survival at 8: two v_perm look up the birth and
 //   the survival byte of four positions at once and self picks between them;
 //   otherwise each byte indexes the rule word (neighbours + 16 * self).
-template <int BS, bool PERM, bool EDGE>
+// ROWS < BS: only the block's first ROWS rows hold fractal cells (e.g. the
+// chandelier's 3x3 blocks, whose third row is empty), so only ROWS + 2 window
+// rows are read and ROWS rows evaluated.
+template <int BS, bool PERM, bool EDGE, int ROWS = BS>
 __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, uint32_t base, uint32_t rule,
                                            const RuleTables &RT, uint32_t (&next)[4]) {
     const uint32_t a0 = base >> 2, sh = base & 3;
     uint32_t lo[BS + 2], hi[BS + 2], C[BS + 2], H[BS + 2];
 #pragma unroll
-    for (int rr = 0; rr < BS + 2; ++rr) {
+    for (int rr = 0; rr < ROWS + 2; ++rr) {
         const uint32_t d0 = box32[a0 + rr * W4], d1 = box32[a0 + rr * W4 + 1];
         if (BS == 4) {            // corner column is 4-aligned
             lo[rr] = d0;
@@ -649,7 +652,7 @@ __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, u
     }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-        if (rr >= BS) {
+        if (rr >= ROWS) {  // rows past ROWS hold no fractal cell
             next[rr] = 0;
             continue;
         }
@@ -893,7 +896,7 @@ __device__ __forceinline__ void team_sync() {
     }
 }
 
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
 __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
     MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule,
     const uint32_t *__restrict__ rec) {
@@ -1009,7 +1012,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {  // waves with no block left skip the work
                     uint32_t next[4];
-                    block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, true, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -1019,7 +1022,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {
                     uint32_t next[4];
-                    block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, false, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -1531,7 +1534,7 @@ hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint
 }
 // Persistent launch: as many work-groups as can be resident at once (the
 // occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE>
+template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
 static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     constexpr uint32_t kTeams = 256 / TEAM;
@@ -1545,32 +1548,32 @@ static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const 
         per_cu = int(c & 0xFFFFFFFFu);
     } else {
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE>, 256, lds);
+            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE, ROWS>, 256, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
     }
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, (T.ntiles + kTeams - 1) / kTeams);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE>), dim3(uint32_t(grid)), dim3(256), lds, st,
+    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE, ROWS>), dim3(uint32_t(grid)), dim3(256), lds, st,
                        P, T, in, out, rule, rec);
     return hipGetLastError();
 }
-template <int BS, int CPT, int HPT, bool BATCH, int TEAM, bool EDGE>
+template <int BS, int CPT, int HPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
 static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t bpt = (T.nblk + TEAM - 1) / TEAM;
-    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
+    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
-template <int BS, bool BATCH, int TEAM, bool EDGE>
+template <int BS, bool BATCH, int TEAM, bool EDGE, int ROWS>
 static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const uint32_t cpt = (T.K + 30 + 16 * TEAM - 1) / (16 * TEAM);
     const uint32_t hpt = (T.halo_count + TEAM - 1) / TEAM;
 #define NBB_TILED_CASE(C, H) \
-    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st)
+    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st)
     NBB_TILED_CASE(1, 1);
     NBB_TILED_CASE(1, 2);
     NBB_TILED_CASE(1, 4);
@@ -1584,9 +1587,11 @@ template <bool BATCH, int TEAM, bool EDGE>
 static hipError_t launch_tiled_bs(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                   uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     switch (T.BS) {
-        case 2: return launch_tiled_s<2, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
-        case 3: return launch_tiled_s<3, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
-        case 4: return launch_tiled_s<4, BATCH, TEAM, EDGE>(P, T, in, out, rule, rec, cu_count, st);
+        case 2: return launch_tiled_s<2, BATCH, TEAM, EDGE, 2>(P, T, in, out, rule, rec, cu_count, st);
+        case 3:  // 3x3 blocks whose third row holds no cell get the two-row form
+            return T.brows == 2 ? launch_tiled_s<3, BATCH, TEAM, EDGE, 2>(P, T, in, out, rule, rec, cu_count, st)
+                                : launch_tiled_s<3, BATCH, TEAM, EDGE, 3>(P, T, in, out, rule, rec, cu_count, st);
+        case 4: return launch_tiled_s<4, BATCH, TEAM, EDGE, 4>(P, T, in, out, rule, rec, cu_count, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -67,6 +67,7 @@ struct TileParams {
     uint32_t m, S, K, W;
     uint32_t q, BS, CB;   // block level, block side s^q, cells per block k^q
     uint32_t nblk;        // k^(m-q) blocks per tile
+    uint32_t brows;       // rows of a block that hold cells (its first brows rows)
     uint32_t box_bytes;   // LDS box allocation
     uint32_t lds_total;   // LDS per team
     uint32_t rm;          // coarse levels r - m

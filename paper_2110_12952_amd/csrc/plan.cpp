@@ -383,10 +383,14 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
         p->lut1[b] = uint16_t(Y * p->BS * p->W + X * p->BS);
     }
     std::memset(p->bid, 0xFF, sizeof(p->bid));
+    p->brows = 0;
     for (uint32_t rr = 0; rr < p->BS; ++rr)
         for (uint32_t c = 0; c < p->BS; ++c) {
             int64_t v = nu_levels(f, q, c, rr);
-            if (v >= 0) p->bid[c + p->BS * rr] = uint8_t(v);
+            if (v >= 0) {
+                p->bid[c + p->BS * rr] = uint8_t(v);
+                p->brows = rr + 1;
+            }
         }
     // Byte gathers from block rows to compact order: byte j of the block's
     // output is the cell with id j, at column c of row r; rows 0 and 1 feed

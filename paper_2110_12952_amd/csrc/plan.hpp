@@ -43,6 +43,7 @@ struct TilePlan {
     uint32_t team = 256;  // threads per tile: 256 (work-group) or 64 (wavefront)
     uint32_t m = 0, S = 0, K = 0, W = 0, q = 0, BS = 0, CB = 0, nblk = 0;
     uint32_t rows = 0;  // box rows read by the rule (<= S + 2)
+    uint32_t brows = 0;  // rows of a block that hold cells (the first brows rows)
     uint32_t box_bytes = 0, lds_total = 0;
     uint32_t rm = 0, Sc = 0, lut0_stride = 0, dummy = 0;
     uint8_t bid[16];
