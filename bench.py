@@ -68,7 +68,7 @@ def measured_traffic(per_launch_alg_bytes):
         return None
 
 
-def cpu_baseline(W, wl, seconds):
+def cpu_baseline(W, wl, seconds, one_thread=True):
     from oracle import oracle as O
     fd = wl.fractal
     o = O.Fractal(fd.s, fd.offsets, wl.r)
@@ -81,9 +81,23 @@ def cpu_baseline(W, wl, seconds):
         t += time.perf_counter() - t0
         steps += 1
         log(f"oracle step {steps}: {t:.1f} s")
-    return {"value": o.cells * steps / t, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{steps} generation(s) of the oracle's compact step (lambda, 8 x nu per cell) over "
-                      f"the full {o.cells}-cell state, {t:.1f} s"}
+    out = {"value": o.cells * steps / t, "unit": "cell-updates/s", "cores": O.threads(), "kind": "oracle",
+           "sample": f"{steps} generation(s) of the oracle's compact step (lambda, 8 x nu per cell) over "
+                     f"the full {o.cells}-cell state, {t:.1f} s"}
+    if one_thread:
+        # the same step on one host thread: one generation of the full state
+        cores = O.threads()
+        O.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            o.compact_steps(st, rule, 1)
+            t1 = time.perf_counter() - t0
+        finally:
+            O.set_threads(cores)
+        out["one_thread"] = {"value": o.cells / t1, "unit": "cell-updates/s", "cores": 1,
+                             "sample": f"1 generation of the full {o.cells}-cell state, {t1:.1f} s"}
+        log(f"oracle on one thread: {o.cells / t1:.3e} cell-updates/s")
+    return out
 
 
 def small_case(torch, N, W, rule):
@@ -246,6 +260,10 @@ def main():
     ap.add_argument("--batch-seq-steps", type=int, default=10,
                     help="generations of the one-launch-per-instance comparison")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-cpu-one-thread", action="store_true",
+                    help="skip the oracle's one-thread figure (one generation, ~10 s)")
+    ap.add_argument("--repeats", type=int, default=10,
+                    help="extra timed runs of the compact step for median / mean per-generation times")
     ap.add_argument("--no-small-batch", action="store_true",
                     help="skip timing the batch's small instances alone (in LDS and in group launches)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -293,6 +311,23 @@ def main():
     alg_bytes = 2 * g.cells  # read + write one byte per cell per generation
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"compact: {ms_step * 1e3:.2f} us/step, {value:.3e} cell-updates/s, {achieved:.0f} GB/s")
+    # repeats: R more timed runs of K/R generations each (per-generation spread)
+    repeats = None
+    if args.repeats > 0:
+        Kr = max(1, K // args.repeats)
+        ra, rb = init.clone(), torch.empty_like(init)  # the timed result above stays intact
+        per = []
+        for _ in range(args.repeats):
+            msr, _ = time_events(torch, lambda: g.step_compact(ra, rb, Kr, rule))
+            per.append(msr / Kr * 1e3)
+        del ra, rb
+        per.sort()
+        mid = len(per) // 2
+        repeats = {"runs": len(per), "steps_each": Kr,
+                   "median_us": per[mid] if len(per) % 2 else 0.5 * (per[mid - 1] + per[mid]),
+                   "mean_us": sum(per) / len(per), "min_us": per[0], "max_us": per[-1]}
+        log(f"compact, {len(per)} runs of {Kr}: median {repeats['median_us']:.2f} us, "
+            f"mean {repeats['mean_us']:.2f} us")
 
     # ---- the same generations on the bit-packed state (1 bit per cell) -----
     packed = None
@@ -403,7 +438,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(W, wl, args.cpu_seconds)
+        cpu = cpu_baseline(W, wl, args.cpu_seconds, not args.no_cpu_one_thread)
         log(f"oracle: {cpu['value']:.3e} cell-updates/s on {cpu['cores']} threads")
 
     # the committed counter summary covers the triangle r = 16 workload only
@@ -430,6 +465,7 @@ def main():
                      "kernel": "k_step_direct" if info.strategy == N.STRATEGY_DIRECT else "k_step_tiled",
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
+        "compact_repeats": repeats,
         "bbox": bbox,
         "speedup_vs_bbox": (bbox["ms_per_step"] / ms_step) if bbox else None,
         "compact_equals_bbox": parity,
