@@ -1235,18 +1235,23 @@ struct PackedPrefetch {
     uint4 e[kPkWPT];
     uint32_t halo[kPkHPT];
 };
+// The scatter offsets depend only on the tile's phase (t K mod 32); a
+// worker's tiles usually share it (they are a multiple of 32 tiles apart), so
+// they are reloaded only when it differs from `pf_ph`, the phase of pf.e.
 __device__ __forceinline__ void packed_prefetch(const TileParams &T, const uint16_t *lutw, uint32_t stride,
                                                 const uint32_t *in, uint32_t t, const uint32_t (&hsrc)[kPkHPT],
-                                                PackedPrefetch &pf) {
+                                                PackedPrefetch &pf, uint32_t &pf_ph) {
     const uint32_t tid = threadIdx.x, K = T.K;
     const uint32_t B = t * K, ph = B & 31, w0 = B >> 5, nq = 4 * ((ph + K + 31) >> 5);
     const uint16_t *lut = lutw + ph * stride;
+    const bool reload = ph != pf_ph;  // uniform
+    pf_ph = ph;
 #pragma unroll
     for (uint32_t j = 0; j < kPkWPT; ++j) {
         const uint32_t l = tid + 256 * j;  // quarter l & 3 of word l >> 2
         if (l < nq) {
             pf.word[j] = in[w0 + (l >> 2)];
-            pf.e[j] = *reinterpret_cast<const uint4 *>(lut + 8 * l);
+            if (reload) pf.e[j] = *reinterpret_cast<const uint4 *>(lut + 8 * l);
         }
     }
 #pragma unroll
@@ -1288,7 +1293,8 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
     const uint32_t cbmask = T.CB >= 32 ? 0xFFFFFFFFu : (1u << T.CB) - 1;
     const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles);
     PackedPrefetch pf;
-    if (R.first < R.end) packed_prefetch(T, lutw, lutw_stride, in, uint32_t(R.first), hsrc, pf);
+    uint32_t pf_ph = 0xFFFFFFFFu;  // no offsets loaded yet
+    if (R.first < R.end) packed_prefetch(T, lutw, lutw_stride, in, uint32_t(R.first), hsrc, pf, pf_ph);
     __syncthreads();
 
     uint32_t it = 0;
@@ -1314,7 +1320,8 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
         for (uint32_t c = tid; c < nw; c += 256) stage[c] = 0;
         __syncthreads();
         // 2. load the next tile while this one computes
-        if (t64 + R.step < R.end) packed_prefetch(T, lutw, lutw_stride, in, uint32_t(t64 + R.step), hsrc, pf);
+        if (t64 + R.step < R.end)
+            packed_prefetch(T, lutw, lutw_stride, in, uint32_t(t64 + R.step), hsrc, pf, pf_ph);
         // 3. the rule per block; its CB bits into the tile's output words
 #pragma unroll
         for (uint32_t j = 0; j < kPkBPT; ++j) {
