@@ -20,6 +20,11 @@ from now.  A request is admitted only if
     within `deadline_s` of admission:  C' <= T min_j(slack_j / R_j), with
     slack_j the time left before request j's deadline.
 A request that fails either test is rejected at once, with the reason.
+
+The device work goes through an executor (`DeviceExecutor`: the library's
+kernels on the current GPU); the loop itself only schedules, so another
+executor with the same four methods can stand in for it (the CPU tests run
+the loop on one that steps the states on the host).
 """
 from __future__ import annotations
 
@@ -134,26 +139,19 @@ class ServeStats:
                 "wait_p99_ms": float(np.percentile(wt, 99) * 1e3)}
 
 
-class Server:
-    """Serves automaton runs from two device arenas of `arena_bytes` each."""
+class DeviceExecutor:
+    """The loop's device work on the current GPU: two arenas of `arena_bytes`,
+    one shared descriptor per (fractal, r), the library's init kernel and its
+    batched step with per-instance step counts."""
 
-    def __init__(self, arena_bytes: int, rule: int = N.NBB_RULE_B3S23, deadline_s: float = 1.0,
-                 round_s: float = 0.02, max_gens: int = 64, throughput0: float = 1e12,
-                 tile_levels: Optional[Dict[str, int]] = None, safety: float = 0.8):
+    def __init__(self, arena_bytes: int, tile_levels: Optional[Dict[str, int]] = None):
         import torch
         self.torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
         self.arenas = [torch.zeros(arena_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
-        self.cur = 0                     # arena holding the active states
-        self.alloc = ArenaAllocator(arena_bytes)
-        self.rule = int(rule)
-        self.deadline_s = float(deadline_s)
-        self.round_s = float(round_s)
-        self.max_gens = int(max_gens)
-        self.throughput = float(throughput0)   # cell updates per second, measured
-        self.safety = float(safety)            # fraction of the measured throughput admission counts on
         self.tile_levels = dict(tile_levels or {})
         self._desc: Dict[Tuple[str, int], object] = {}
+        self._ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
 
     def descriptor(self, fd, r: int):
         """One shared descriptor per (fractal, r).  Instances of a fractal named
@@ -170,15 +168,52 @@ class Server:
             self._desc[key] = d
         return d
 
-    def run(self, requests: Sequence, on_complete: Optional[Callable] = None, log=None) -> ServeStats:
+    def init(self, desc, seed: int, p: float, arena: int, offset: int, cells: int) -> None:
+        desc.init_compact(seed, p, out=self.arenas[arena][offset:offset + cells])
+
+    def step_each(self, descs, offsets, steps, rule: int, arena: int) -> float:
+        """Instance j (descs[j] at offsets[j]) takes steps[j] generations from
+        arena `arena` (ending in the other one iff steps[j] is odd); returns
+        the device time in seconds."""
         torch = self.torch
+        stream = torch.cuda.current_stream()
+        batch = N.Batch(descs, offsets)
+        ev0, ev1 = self._ev
+        ev0.record(stream)
+        batch.step_each(self.arenas[arena], self.arenas[1 - arena], steps, rule)
+        ev1.record(stream)
+        ev1.synchronize()
+        del batch
+        return ev0.elapsed_time(ev1) * 1e-3
+
+    def view(self, arena: int, offset: int, cells: int):
+        return self.arenas[arena][offset:offset + cells]
+
+
+class Server:
+    """Serves automaton runs from two arenas of `arena_bytes` each (on the
+    current GPU unless another executor is given)."""
+
+    def __init__(self, arena_bytes: int, rule: int = N.NBB_RULE_B3S23, deadline_s: float = 1.0,
+                 round_s: float = 0.02, max_gens: int = 64, throughput0: float = 1e12,
+                 tile_levels: Optional[Dict[str, int]] = None, safety: float = 0.8, executor=None):
+        self.exe = executor if executor is not None else DeviceExecutor(arena_bytes, tile_levels)
+        self.cur = 0                     # arena holding the active states
+        self.alloc = ArenaAllocator(arena_bytes)
+        self.rule = int(rule)
+        self.deadline_s = float(deadline_s)
+        self.round_s = float(round_s)
+        self.max_gens = int(max_gens)
+        self.throughput = float(throughput0)   # cell updates per second, measured
+        self.safety = float(safety)            # fraction of the measured throughput admission counts on
+
+    def run(self, requests: Sequence, on_complete: Optional[Callable] = None, log=None) -> ServeStats:
+        exe = self.exe
         st = ServeStats(offered=len(requests))
         active: List[_Active] = []
         footprint = 0          # cells of the active requests
         tightest = float("inf")  # min over active requests of slack / generations left
         i = 0
-        stream = torch.cuda.current_stream()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         while i < len(requests) or active:
             now = time.perf_counter() - t0
@@ -195,8 +230,8 @@ class Server:
                 if off is None:
                     st.rejected_memory += 1
                     continue
-                d = self.descriptor(q.fractal, q.r)
-                d.init_compact(q.seed, q.p, out=self.arenas[self.cur][off:off + q.cells])
+                d = exe.descriptor(q.fractal, q.r)
+                exe.init(d, q.seed, q.p, self.cur, off, q.cells)
                 active.append(_Active(q, d, off, q.steps, now))
                 footprint, tightest = fp, tight
                 st.admitted += 1
@@ -214,14 +249,9 @@ class Server:
             for a in active:
                 if a.started is None:
                     a.started = start
-            batch = N.Batch([a.desc for a in active], [a.offset for a in active])
-            cur, other = self.arenas[self.cur], self.arenas[1 - self.cur]
-            ev0.record(stream)
-            batch.step_each(cur, other, steps, self.rule)
-            ev1.record(stream)
-            ev1.synchronize()
+            gpu_s = exe.step_each([a.desc for a in active], [a.offset for a in active], steps, self.rule,
+                                  self.cur)
             done_t = time.perf_counter() - t0
-            gpu_s = ev0.elapsed_time(ev1) * 1e-3
             upd = sum(s * c for s, c in zip(steps, (a.req.cells for a in active)))
             st.rounds += 1
             st.gpu_seconds += gpu_s
@@ -238,8 +268,8 @@ class Server:
                 st.latencies.append(done_t - a.req.t)
                 st.waits.append(a.started - a.req.t)
                 if on_complete is not None:
-                    res = other if (s_ & 1) else cur
-                    on_complete(a.req, res[a.offset:a.offset + a.req.cells])
+                    res = 1 - self.cur if (s_ & 1) else self.cur
+                    on_complete(a.req, exe.view(res, a.offset, a.req.cells))
                 self.alloc.free(a.offset)
             if G & 1:
                 self.cur = 1 - self.cur
@@ -247,7 +277,6 @@ class Server:
             footprint = sum(a.req.cells for a in active)
             tightest = min(((a.admitted + self.deadline_s - done_t) / a.remaining for a in active),
                            default=float("inf"))
-            del batch
             if log and st.rounds % 50 == 0:
                 log(f"serve: t={done_t:.1f}s rounds={st.rounds} active={len(active)} done={st.completed} "
                     f"rejected={st.rejected_deadline + st.rejected_memory} {self.throughput:.3e} cell-upd/s")
