@@ -288,3 +288,24 @@ def test_serve_workload_requests():
             if 3 - 0.5 <= r * np.log10(W.FRACTALS[f].k) <= 8 + 0.5} <= got
     st = np.log(np.array([q.steps for q in rq]))
     assert abs(st.mean() - (np.log(10) + np.log(2000)) / 2) < 0.05
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # no CPU fallback: with the library missing, every entry point raises
+    import os
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2110_12952_amd import nbbfrac as N\n"
+            "for call in (N.lib, lambda: N.Fractal(2, ((0, 0), (1, 0), (0, 1)), 4),\n"
+            "             lambda: N.plan_tables(2, ((0, 0), (1, 0), (0, 1)), 4)):\n"
+            "    try:\n"
+            "        call()\n"
+            "    except ImportError as e:\n"
+            "        assert 'missing' in str(e)\n"
+            "    else:\n"
+            "        raise SystemExit('no error')\n"
+            "print('raised')\n") % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, NBB_LIBRARY=str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "raised" in r.stdout, r.stdout + r.stderr
