@@ -1049,12 +1049,12 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 // team's box, then the rule per block with the block's next states written
 // in compact order into the other copy.  A thread's scatter offsets, halo
 // entries and block corners are the same for every tile and generation, so
-// they are loaded once into registers (at most 2 chunks, 4 halo cells and
+// they are loaded once into registers (at most 3 chunks, 5 halo cells and
 // 4 blocks per thread; the launcher picks `teams` so they fit).  The final
 // state goes to `a` if the instance's generation count is even, else to `b`
 // (like the launch-per-generation form, whose ping-pong ends there).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kResCPT = 2, kResHPT = 4, kResBPT = 4;
+constexpr uint32_t kResCPT = 3, kResHPT = 5, kResBPT = 4;
 template <int BS, bool EDGE>
 __device__ __forceinline__ void resident_body(const TileParams &T, const ResidentInstance &I, uint32_t steps,
                                               uint8_t *lds, uint8_t *__restrict__ a, uint8_t *__restrict__ b,
