@@ -120,7 +120,10 @@ nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
  * enough for one wavefront (k^m + 30 <= 2048 cells, at most 256 halo cells
  * and blocks, four LDS boxes within 64 KiB).  NBB_E_INVALID when the request
  * cannot be met (the descriptor keeps its previous plan).  Rebuilds and re-uploads the tile
- * tables; must not overlap other calls on the same descriptor.
+ * tables; must not overlap other calls on the same descriptor, and no
+ * enqueued work may still use the old tables (synchronise first).  The
+ * packed step's 32-phase table follows the new plan at its next call, with
+ * the same condition.
  */
 nbb_status nbb_configure(nbb_fractal *f, uint32_t strategy, uint32_t tile_level);
 
