@@ -157,3 +157,32 @@ def test_packed_rejects_bad_arguments(N):
     with pytest.raises(N.NbbError, match="tiled plan"):
         d.pack(d.new_compact(), out=torch.zeros(d.packed_bytes(), dtype=torch.uint8, device="cuda"))
     assert f.step_packed(a, torch.zeros_like(a), 0) is a
+
+
+@pytest.mark.parametrize("name,r", [("triangle", 8), ("carpet", 4)])
+def test_step_packed_in_a_captured_graph(N, name, r):
+    # after a first call (which builds the plan's 32-phase table) the packed
+    # step only enqueues kernels, so it can be captured; every replay, with
+    # eager work in between, must give the oracle's result
+    fd = W.FRACTALS[name]
+    f = N.Fractal(fd.s, fd.offsets, r)
+    o = O.Fractal(fd.s, fd.offsets, r)
+    s0 = o.init_compact(31, 0.5)
+    want = packed_of(o.compact_steps(s0, W.rule_mask("B3/S23"), 4))
+    a0 = f.pack(torch.from_numpy(s0).cuda())
+    a, b = a0.clone(), torch.zeros_like(a0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        f.step_packed(a, b, 2)           # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        res = f.step_packed(a, b, 4)
+    assert res is a
+    other = f.pack(f.init_compact(5, 0.5))
+    for rep in range(4):
+        a.copy_(a0)
+        graph.replay()
+        f.step_packed(other, torch.zeros_like(other), 3)   # eager work between replays
+        np.testing.assert_array_equal(host(a), want, err_msg=f"replay {rep}")

@@ -375,6 +375,38 @@ def test_blocked_layout(N, name, r, m):
                                           err_msg=f"{name} r={r} m={m} {rule} steps={steps}")
 
 
+def test_step_blocked_and_bbox_in_a_captured_graph(N):
+    # the blocked-layout and box steps only enqueue kernels too: captured
+    # once, replayed with eager work in between, each replay equal to the
+    # eager result
+    fd, o, g = pair("triangle", 8, N)
+    g.configure(N.STRATEGY_TILED, 4)
+    st0 = o.init_compact(17, 0.5)
+    want = o.compact_steps(st0, B3S23, 5)
+    blk0 = g.to_blocked(dev(st0))
+    box0 = g.expand(dev(st0))
+    a, b = blk0.clone(), torch.empty_like(blk0)
+    c, d = box0.clone(), torch.empty_like(box0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.step_blocked(a, b, 2)
+        g.step_bbox(c, d, 2)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rk = g.step_blocked(a, b, 5)
+        rb = g.step_bbox(c, d, 5)
+    assert rk is b and rb is d
+    for rep in range(3):
+        a.copy_(blk0)
+        c.copy_(box0)
+        graph.replay()
+        g.step_compact(dev(st0), torch.empty(o.cells, dtype=torch.uint8, device="cuda"), 3)  # eager work
+        np.testing.assert_array_equal(host(g.from_blocked(rk)), want, err_msg=f"blocked, replay {rep}")
+        np.testing.assert_array_equal(host(g.gather(rb)), want, err_msg=f"box, replay {rep}")
+
+
 def test_blocked_layout_needs_a_tiled_plan(N):
     fd, o, g = pair("carpet", 3, N)
     g.configure(N.STRATEGY_DIRECT)
