@@ -244,6 +244,41 @@ def serve_run(torch, W, args):
     return out
 
 
+def large_case(torch, N, W, name, rule, steps):
+    """One of the HBM-sized workloads (carpet r = 9: 134M cells, H r = 10:
+    282M cells; their double buffers exceed the 256 MB Infinity Cache): the
+    compact step and the box step for `steps` generations each, per-generation
+    times, roofline fractions and whether the two results agree."""
+    wl = W.WORKLOADS[name]
+    fd = wl.fractal
+    g = N.Fractal(fd.s, fd.offsets, wl.r)
+    a = g.init_compact(wl.seeds[0], wl.p)
+    b = torch.empty_like(a)
+    g.step_compact(a.clone(), b, 2, rule)
+    ms, res = time_events(torch, lambda: g.step_compact(a, b, steps, rule))
+    alg = 2 * g.cells
+    out = {"cells": g.cells, "n": g.n, "steps": steps, "tile_level": g.info().tile_level,
+           "ms_per_step": ms / steps, "cell_updates_per_s": g.cells * steps / (ms * 1e-3),
+           "alg_gbps": alg / (ms / steps * 1e-3) / 1e9}
+    out["roofline_frac"] = out["alg_gbps"] / HBM_PEAK_GBPS
+    res = res.clone()
+    del a, b
+    box = g.init_bbox(wl.seeds[0], wl.p)
+    box2 = torch.empty_like(box)
+    g.step_bbox(box.clone(), box2, 2, rule)
+    msb, resb = time_events(torch, lambda: g.step_bbox(box, box2, steps, rule))
+    out["bbox_ms_per_step"] = msb / steps
+    out["bbox_alg_gbps"] = 2 * g.n * g.n / (msb / steps * 1e-3) / 1e9
+    out["bbox_roofline_frac"] = out["bbox_alg_gbps"] / HBM_PEAK_GBPS
+    out["speedup_vs_bbox"] = msb / ms
+    out["compact_equals_bbox"] = bool(torch.equal(g.gather(resb), res))
+    log(f"{name}: compact {ms / steps * 1e3:.1f} us/step ({out['roofline_frac']:.3f} of HBM peak), box "
+        f"{msb / steps * 1e3:.1f} us/step, same={out['compact_equals_bbox']}")
+    del box, box2, resb, res
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,8 +301,10 @@ def main():
                     help="extra timed runs of the compact step for median / mean per-generation times")
     ap.add_argument("--no-small-batch", action="store_true",
                     help="skip timing the batch's small instances alone (in LDS and in group launches)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="arrival window of the served workload (its full length is 60 s); 0 skips it")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="arrival window of the served workload (the workload's full 60 s); 0 skips it")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="generations of each HBM-sized workload (carpet r9, H r10); 0 skips them")
     ap.add_argument("--serve-deadline", type=float, default=0.5,
                     help="admission: predicted drain time limit, seconds")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -311,10 +348,11 @@ def main():
     alg_bytes = 2 * g.cells  # read + write one byte per cell per generation
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     log(f"compact: {ms_step * 1e3:.2f} us/step, {value:.3e} cell-updates/s, {achieved:.0f} GB/s")
-    # repeats: R more timed runs of K/R generations each (per-generation spread)
+    # repeats: R more timed runs of at least 100 generations each (the
+    # per-generation spread; shorter runs would mostly time events and syncs)
     repeats = None
     if args.repeats > 0:
-        Kr = max(1, K // args.repeats)
+        Kr = max(100, K // args.repeats)
         ra, rb = init.clone(), torch.empty_like(init)  # the timed result above stays intact
         per = []
         for _ in range(args.repeats):
@@ -433,6 +471,11 @@ def main():
     log("maps: " + ", ".join(f"{k} {v:.0f}" if isinstance(v, float) else f"{k} {v}" for k, v in maps.items()))
     del x, y, idx
 
+    large = None
+    if args.large_steps > 0:
+        large = {nm: large_case(torch, N, W, nm, W.rule_mask(W.WORKLOADS[nm].rule), args.large_steps)
+                 for nm in ("carpet_r9", "hfractal_r10")}
+
     batch = None if args.no_batch else batch_run(torch, N, W, args)
     serve = serve_run(torch, W, args) if args.serve_seconds > 0 else None
 
@@ -472,6 +515,7 @@ def main():
         "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
         "maps": maps,
         "small_triangle_r10": small,
+        "large_workloads": large,
         "packed_state": packed,
         "batch": batch,
         "serve": serve,

@@ -92,6 +92,12 @@ typedef struct {
     uint32_t lds_bytes;    /* LDS used by one work-group of the tiled step */
     uint64_t bbox_pitch;   /* smallest pitch the box entry points accept */
     uint64_t device_table_bytes;
+    /* Membership in the box entry points: the low L levels as an SL x SL
+     * bitmap (SL = s^L <= 1024), the other r - L levels as an NH x NH byte
+     * map (NH = s^(r-L)); a 16-column group of the box step can span two
+     * high-level squares when SL is not a multiple of 16. */
+    uint32_t box_low_side;  /* SL */
+    uint32_t box_high_side; /* NH (0 when the box is too large to exist) */
 } nbb_info;
 
 /*
@@ -145,9 +151,13 @@ nbb_status nbb_nu(const nbb_fractal *f, const int32_t *x, const int32_t *y, uint
 
 /*
  * The same maps evaluated three ways (results identical):
- *   NBB_MAP_LUT    chunked look-up tables (the default of nbb_lambda / nbb_nu);
+ *   NBB_MAP_LUT    chunked look-up tables (the default of nbb_lambda / nbb_nu,
+ *                  and the fastest form on gfx950);
  *   NBB_MAP_DIGITS one level per step, as the per-thread maps of section 3.1;
- *   NBB_MAP_MFMA   digits per item as NBB_MAP_DIGITS, the per-level sum as
+ *   NBB_MAP_MFMA   measurement only (about ten times slower than
+ *                  NBB_MAP_LUT on MI355X, kept to compare against the
+ *                  paper's matrix-unit form, never chosen by any other call):
+ *                  digits per item as NBB_MAP_DIGITS, the per-level sum as
  *                  an int8 matrix-core contraction (the matrix encoding of
  *                  section 3.1 on gfx950 matrix cores: one-hot digits, resp.
  *                  replica ids, times 7-bit planes of o_j s^mu, resp. j k^mu;
@@ -169,7 +179,8 @@ nbb_status nbb_nu_method(const nbb_fractal *f, uint32_t method, const int32_t *x
  * are below floor(p * 2^24).  Both layouts therefore hold the same state.
  * nbb_init_compact: len must be k^r.  nbb_init_bbox: len must be n*pitch,
  * pitch as described above; non-members and padding are written 0.
- * p must lie in [0, 1].
+ * p must lie in [0, 1].  The state buffer must be 16-byte aligned
+ * (NBB_E_INVALID otherwise): the kernels write 16 cells per store.
  */
 nbb_status nbb_init_compact(const nbb_fractal *f, uint8_t *state, uint64_t len, uint64_t seed,
                             double p, void *stream);
@@ -181,8 +192,10 @@ nbb_status nbb_init_bbox(const nbb_fractal *f, uint8_t *state, uint64_t pitch, u
  * stencil procedure; section 4, Game of Life on the fractal).  The state
  * starts in a; buffers a and b alternate, and *result_in_b (if not NULL) is
  * set to steps & 1, i.e. whether the result ended in b.  len must be k^r;
- * a and b must not overlap; the rule may only use bits 0-8, 16-24 and 31; state
+ * a and b must not overlap and must both be 16-byte aligned (the tiled step
+ * reads 16-byte chunks); the rule may only use bits 0-8, 16-24 and 31; state
  * bytes must be 0 or 1.  steps == 0 leaves both buffers untouched.
+ * NBB_E_INVALID for a violation of any of these.
  */
 nbb_status nbb_step_compact(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len,
                             uint32_t steps, uint32_t rule, int *result_in_b, void *stream);
@@ -190,8 +203,10 @@ nbb_status nbb_step_compact(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64
 /*
  * The bounding-box baseline the paper compares against (section 4, method 1):
  * the same generations computed on the whole box, every box cell visited.
- * len must be n*pitch.  The input must hold 0 at non-members and padding;
- * the output does too.  Other rules as nbb_step_compact.
+ * len must be n*pitch; a and b must be 16-byte aligned (rows are read and
+ * written 16 bytes at a time) and must not overlap.  The input must hold 0
+ * at non-members and padding; the output does too.  Other rules as
+ * nbb_step_compact.
  */
 nbb_status nbb_step_bbox(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t pitch,
                          uint64_t len, uint32_t steps, uint32_t rule, int *result_in_b,
@@ -201,8 +216,9 @@ nbb_status nbb_step_bbox(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t 
  * The paper's lambda approach (section 4, second method): the same
  * generations on the box layout, but with one thread per fractal cell, which
  * finds its box position with lambda and reads its neighbours from the box
- * directly.  Arguments, result buffer and errors as nbb_step_bbox; the input
- * must hold 0 at non-members and padding, and b is cleared once per call
+ * directly.  Arguments, result buffer, alignment and errors as
+ * nbb_step_bbox; the input must hold 0 at non-members and padding, and b is
+ * cleared once per call
  * (steps >= 1) so that its non-members hold 0 too.
  */
 nbb_status nbb_step_lambda(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t pitch,
@@ -276,7 +292,8 @@ nbb_status nbb_gather(const nbb_fractal *f, const uint8_t *bbox, uint64_t pitch,
  * on the caller's
  * buffers a and b (their contents are overwritten: pass a copy of a
  * representative state), then configures the fastest, as nbb_configure would.
- * Waits for `stream`.  Arguments as nbb_step_compact; steps >= 1.  If info is
+ * Waits for `stream`.  Arguments as nbb_step_compact (a and b 16-byte
+ * aligned, not overlapping); steps >= 1.  If info is
  * not NULL it receives nbb_query's result for the chosen plan.  Must not
  * overlap other calls on the same descriptor.
  */

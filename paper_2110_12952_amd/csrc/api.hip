@@ -471,6 +471,8 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
     }
     info->bbox_pitch = box_pitch(F->f);
     info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes + F->dmfma.bytes;
+    info->box_low_side = F->box.SL;
+    info->box_high_side = F->box.high.empty() ? 0 : F->box.NH;
     return NBB_OK;
 }
 

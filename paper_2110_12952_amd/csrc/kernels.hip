@@ -13,51 +13,10 @@
 
 #include "kernels.hpp"
 
+#include "device_common.hpp"
+#include "tiled_launch.hpp"
+
 namespace nbb {
-
-static constexpr uint32_t kOutside = 0xFFFFFFFFu;
-
-__device__ __forceinline__ uint32_t udiv(const UDiv &u, uint32_t a) {
-    uint32_t t = __umulhi(a, u.m);
-    return (t + ((a - t) >> u.s1)) >> u.s2;
-}
-
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t sh) {
-    return __builtin_amdgcn_alignbyte(hi, lo, sh);
-}
-
-// Bit j of the 4-bit nibble -> byte j (value 0 or 1) of a dword.
-__device__ __forceinline__ uint32_t nibble_to_bytes(uint32_t nib) {
-    return __umul24(nib, 0x00204081u) & 0x01010101u;
-}
-
-// Work-group -> work-item mapping that keeps a contiguous range of items on
-// each XCD.  Work-groups are dispatched round-robin over the 8 XCDs
-// (blockIdx % 8), so group x of every 8 gets the x-th slice of the items and
-// walks it in order; neighbouring items then share that XCD's L2.
-struct XcdRange {
-    uint64_t first, end, step;
-};
-// With `sub` workers per work-group (worker w of group wg), the XCD's slice
-// is shared by all workers of its work-groups.
-__device__ __forceinline__ XcdRange xcd_range(uint32_t wg, uint32_t G, uint64_t T, uint32_t w = 0,
-                                              uint32_t sub = 1) {
-    XcdRange r;
-    if (G >= 8) {
-        uint32_t x = wg & 7, slot = (wg >> 3) * sub + w;
-        uint32_t cnt = (G - x + 7) >> 3;
-        uint64_t before = uint64_t(x) * (G >> 3) + min(x, G & 7);
-        uint64_t start = T * before / G;
-        r.end = T * (before + cnt) / G;
-        r.first = start + slot;
-        r.step = uint64_t(cnt) * sub;
-    } else {
-        r.first = uint64_t(wg) * sub + w;
-        r.end = T;
-        r.step = uint64_t(G) * sub;
-    }
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // lambda / nu, chunked look-up tables held in LDS (section 3: lambda maps
@@ -536,216 +495,6 @@ __global__ __launch_bounds__(512) void k_step_lambda(MapParams P, uint32_t lam_w
 }
 
 // ---------------------------------------------------------------------------
-// Compact step, tiled: the kernel and its helpers (the kernel's comment
-// describes the scheme).
-// ---------------------------------------------------------------------------
-// Registers holding the next tile's input while the current one computes.
-template <int CPT, int HPT>
-struct TilePrefetch {
-    uint4 v[CPT];      // 16 compact bytes per chunk
-    uint4 e[CPT][2];   // their 16 LDS-box offsets (u16)
-    uint32_t halo[HPT];
-};
-
-// Loads tile t (local index within the state array `in` of cells `cells`)
-// and its halo.  `tail`: the tile holds the last cell of an array whose
-// length is not a multiple of 16, so its last chunk may not be read whole.
-// The scatter offsets depend only on the tile's phase (t K mod 16), and a
-// worker's tiles usually share it (consecutive tiles of a worker are a
-// multiple of 16 tiles apart), so with KEEP they are reloaded only when the
-// phase differs from `pf_ph`, the phase of the offsets held in pf.e.  (Over
-// the tiles of a batch, measured slower: the batched step reloads always.)
-template <int TEAM, int CPT, int HPT, bool KEEP>
-__device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t *__restrict__ in,
-                                              uint32_t t, bool tail, uint32_t cells, const uint32_t *nb,
-                                              const uint32_t *hsrc, TilePrefetch<CPT, HPT> &pf, uint32_t &pf_ph) {
-    const uint32_t tid = threadIdx.x % TEAM;
-    const uint32_t B = t * T.K;
-    const uint32_t ph = B & 15;
-    const uint32_t nchunks = (ph + T.K + 15) >> 4;
-    const uint8_t *gin = in + (B & ~15u);  // uniform; chunk c at gin + 16 c
-    const uint16_t *lut = T.lut0p + ph * T.lut0_stride;
-    const bool reload = !KEEP || ph != pf_ph;  // uniform
-    pf_ph = ph;
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const uint32_t c = tid + TEAM * j;
-        if (c < nchunks) {
-            if (!tail || c + 1 < nchunks) {
-                pf.v[j] = *reinterpret_cast<const uint4 *>(gin + 16 * c);
-            } else {
-                uint32_t v[4] = {0, 0, 0, 0};
-                const uint32_t nb_ = cells & 15;
-                for (uint32_t b = 0; b < nb_; ++b) v[b >> 2] |= uint32_t(gin[16 * c + b]) << (8 * (b & 3));
-                pf.v[j] = make_uint4(v[0], v[1], v[2], v[3]);
-            }
-            if (reload) {
-                pf.e[j][0] = *reinterpret_cast<const uint4 *>(lut + 16 * c);
-                pf.e[j][1] = *reinterpret_cast<const uint4 *>(lut + 16 * c + 8);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const uint32_t src = hsrc[j];  // kOutside: this thread has no j-th halo cell
-        const uint32_t nt = src != kOutside ? nb[src >> 29] : kOutside;
-        pf.halo[j] = nt != kOutside ? in[nt * T.K + (src & 0x1FFFFFFFu)] : 0u;
-    }
-}
-
-// The rule as two byte tables for v_perm: byte c of born (c = 0..7) is the
-// birth bit for c live neighbours, byte c of surv the survival bit; counts
-// 0-3 sit in the low dword, 4-7 in the high one.  A count of 8 selects a sign
-// byte of the table (0, as every table byte is 0 or 1), so the tables serve
-// exactly the rules without birth or survival at 8 (`perm`).
-struct RuleTables {
-    uint32_t born_lo, born_hi, surv_lo, surv_hi;
-    bool perm;
-};
-__device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
-    RuleTables t{0, 0, 0, 0, (rule & ((1u << 8) | (1u << 24))) == 0};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        t.born_lo |= ((rule >> c) & 1u) << (8 * c);
-        t.born_hi |= ((rule >> (c + 4)) & 1u) << (8 * c);
-        t.surv_lo |= ((rule >> (c + 16)) & 1u) << (8 * c);
-        t.surv_hi |= ((rule >> (c + 20)) & 1u) << (8 * c);
-    }
-    return t;
-}
-
-// Next states of one block (a BS x BS square whose CB fractal cells are
-// consecutive in compact order), one byte per position: row r of the block
-// in next[r], byte c = column c (bytes past BS and rows past BS are
-// unspecified or 0).  The window is BS+2 rows of the LDS box starting one row
-// up and one column left of the block, read as two dwords per row; byte c of
-// H is the 3-sum of window columns c..c+2, so H[r] + H[r+1] + H[r+2] - self
-// is the live-neighbour count of every position of block row r at once.
-//   rules without birth or survival at 8: two v_perm look up the birth and
-//   the survival byte of four positions at once and self picks between them;
-//   otherwise each byte indexes the rule word (neighbours + 16 * self).
-// ROWS < BS: only the block's first ROWS rows hold fractal cells (e.g. the
-// chandelier's 3x3 blocks, whose third row is empty), so only ROWS + 2 window
-// rows are read and ROWS rows evaluated.
-template <int BS, bool PERM, bool EDGE, int ROWS = BS>
-__device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, uint32_t base, uint32_t rule,
-                                           const RuleTables &RT, uint32_t (&next)[4]) {
-    const uint32_t a0 = base >> 2, sh = base & 3;
-    uint32_t lo[BS + 2], hi[BS + 2], C[BS + 2], H[BS + 2];
-#pragma unroll
-    for (int rr = 0; rr < ROWS + 2; ++rr) {
-        const uint32_t d0 = box32[a0 + rr * W4], d1 = box32[a0 + rr * W4 + 1];
-        if (BS == 4) {            // corner column is 4-aligned
-            lo[rr] = d0;
-            hi[rr] = d1;
-        } else {
-            lo[rr] = alignbyte(d1, d0, sh);   // window columns 0..3
-            hi[rr] = d1 >> (8 * sh);          // window columns 4..
-        }
-        if (BS == 2) {
-            C[rr] = lo[rr] >> 8;
-            H[rr] = lo[rr] + C[rr] + (lo[rr] >> 16);
-        } else {
-            C[rr] = alignbyte(hi[rr], lo[rr], 1);
-            H[rr] = lo[rr] + C[rr] + alignbyte(hi[rr], lo[rr], 2);
-        }
-    }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        if (rr >= ROWS) {  // rows past ROWS hold no fractal cell
-            next[rr] = 0;
-            continue;
-        }
-        const uint32_t self = C[rr + 1];
-        // live neighbours per byte: the 3x3 sum minus self, or the cells
-        // above and below plus the left and right ones
-        uint32_t n;
-        if (EDGE)
-            n = C[rr] + C[rr + 2] + lo[rr + 1] +
-                (BS == 2 ? lo[rr + 1] >> 16 : alignbyte(hi[rr + 1], lo[rr + 1], 2));
-        else
-            n = H[rr] + H[rr + 1] + H[rr + 2] - self;
-        if (PERM) {
-            const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
-            const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
-            const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, self);  // 0xFF where alive
-            next[rr] = (born & ~smask) | (surv & smask);
-        } else {
-            // v_bfe takes its offset from the low 5 bits of the operand, and
-            // byte c of I (<= 24) is exactly those bits of I >> 8c
-            const uint32_t I = n + (self << 4);
-            uint32_t v = __builtin_amdgcn_ubfe(rule, I, 1);
-#pragma unroll
-            for (int cc = 1; cc < BS; ++cc) v |= __builtin_amdgcn_ubfe(rule, I >> (8 * cc), 1) << (8 * cc);
-            next[rr] = v;
-        }
-    }
-}
-
-__device__ __forceinline__ void store_u8(uint8_t *p, uint32_t v) { *p = uint8_t(v); }
-__device__ __forceinline__ void store_u16(uint8_t *p, uint32_t v) {
-    const uint16_t h = uint16_t(v);
-    __builtin_memcpy(p, &h, 2);
-}
-__device__ __forceinline__ void store_u32(uint8_t *p, uint32_t v) { __builtin_memcpy(p, &v, 4); }
-__device__ __forceinline__ void store_u64(uint8_t *p, uint32_t v0, uint32_t v1) {
-    const uint64_t v = uint64_t(v1) << 32 | v0;
-    __builtin_memcpy(p, &v, 8);
-}
-
-// Gathers the block's member bytes into compact order with v_perm and stores
-// its CB next states at p (any alignment: gfx950 global stores need none).
-// Blocks of 5 to 7 cells are written as two overlapping 4-byte stores of the
-// same lane (the overlap gets the same bytes twice; blocks of different
-// lanes never overlap).  CB is uniform, so the choice below is scalar
-// branches only.
-template <int BS>
-__device__ __forceinline__ void block_store(const TileParams &T, const uint32_t (&next)[4], uint8_t *p) {
-    uint32_t w[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        w[d] = __builtin_amdgcn_perm(next[1], next[0], T.pack01[d]);
-        if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], T.pack23[d]);
-    }
-    const uint32_t CB = T.CB;  // 1..16 bytes
-    if (CB == 16) {
-        store_u64(p, w[0], w[1]);
-        store_u64(p + 8, w[2], w[3]);
-    } else if (CB > 8) {
-        // (an overlapping second 8-byte store measured slower than the
-        // pieces for the 9-cell blocks of the triangle)
-        store_u64(p, w[0], w[1]);
-        uint32_t r = CB - 8, x = w[2];  // 1..7
-        p += 8;
-        if (r >= 4) {
-            store_u32(p, x);
-            p += 4;
-            r -= 4;
-            x = w[3];
-        }
-        if (r >= 2) {
-            store_u16(p, x);
-            p += 2;
-            r -= 2;
-            x >>= 16;
-        }
-        if (r) store_u8(p, x);
-    } else if (CB == 8) {
-        store_u64(p, w[0], w[1]);
-    } else if (CB > 4) {
-        store_u32(p, w[0]);
-        store_u32(p + (CB - 4), alignbyte(w[1], w[0], CB - 4));
-    } else if (CB == 4) {
-        store_u32(p, w[0]);
-    } else if (CB >= 2) {
-        store_u16(p, w[0]);
-        if (CB == 3) store_u16(p + 1, w[0] >> 8);
-    } else {
-        store_u8(p, w[0]);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Blocked layout (section 3, blocked approach: the compact space as a packed
 // collection of small bounding boxes): tile t of the tile plan is stored as
 // its whole S x S square at bytes [t S^2, (t+1) S^2), cell (x, y) of the
@@ -847,189 +596,6 @@ __global__ __launch_bounds__(256) void k_step_blocked(TileParams T, const uint8_
                 for (uint32_t b = 0; b < nb; ++b) p[b] = uint8_t(next >> (8 * b));
         }
         __syncthreads();
-    }
-}
-
-#ifndef NBB_TILED_WAVES_PER_SIMD
-#define NBB_TILED_WAVES_PER_SIMD 1
-#endif
-// Compact step, tiled (section 3, blocked approach, applied to compact
-// storage).  Tile t = compact cells [t K, (t+1) K), K = k^m: one level-m copy
-// of the fractal, covering the S x S block (S = s^m) of the box whose corner
-// is S * lambda_{r-m}(t).  Since every tile is the same copy of F_m, the
-// position of local cell i inside its block (lut0) and the list of neighbour
-// cells that touch the block (halo) are the same for every tile; only the
-// eight neighbour tiles differ.  Per tile a work-group
-//   1. scatters the tile's K bytes and its halo into an LDS box of
-//      rows x W bytes (cells outside the fractal stay 0),
-//   2. evaluates the rule for each block of CB cells (block_rows: four
-//      positions per dword), gathers the block's member bytes into compact
-//      order (block_store: v_perm) and stores its CB next states, which are
-//      consecutive compact cells, straight to global memory.
-// Work-groups are persistent and walk an XCD-contiguous range of tiles as a
-// software pipeline: the next tile's bytes and halo are loaded into registers
-// while the current tile computes, and the neighbour tiles are found two
-// tiles ahead by a few threads and passed on through LDS.
-//
-// BATCH: the tiles of many independent fractals that share the tile plan
-// (same k, s, offsets and m, any r), each state at its own place in one
-// arena.  Batch tile g is local tile rec[2g+1] (bit 31: the tail flag of
-// tile_prefetch) of the state at byte 16 rec[2g] of the arena, and T.nbr
-// holds its eight neighbours as local tiles of the same state.  The record
-// travels through LDS with the neighbour tiles, two tiles ahead.
-//
-// TEAM: threads per tile.  256 = the whole work-group works on one tile at a
-// time.  64 = each wavefront is a worker of its own with its own LDS box and
-// its own range of tiles, synchronising only within the wavefront; for small
-// tiles, whose few chunks, halo cells and blocks leave most of a work-group
-// idle, four independent pipelines per work-group hide more memory latency.
-template <int TEAM>
-__device__ __forceinline__ void team_sync() {
-    if (TEAM == 256) {
-        __syncthreads();
-    } else {
-        // one wavefront: its LDS accesses complete in program order, so only
-        // the compiler must be kept from moving them across this point
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
-__global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
-    MapParams P, TileParams T, const uint8_t *__restrict__ in, uint8_t *__restrict__ out, uint32_t rule,
-    const uint32_t *__restrict__ rec) {
-    extern __shared__ __align__(16) uint8_t lds_all[];
-    constexpr uint32_t kTeams = 256 / TEAM;
-    constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
-    constexpr uint32_t kLane0 = TEAM - kLanes;
-    __shared__ uint32_t nbr_all[kTeams][2][kLanes];
-    // the team index is uniform across a wavefront: keep it (and every tile
-    // index derived from it) in scalar registers
-    const uint32_t team = TEAM == 256 ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x / TEAM);
-    const uint32_t tid = TEAM == 256 ? threadIdx.x : threadIdx.x % TEAM;
-    uint8_t *lds = lds_all + team * T.lds_total;
-    uint8_t *box = lds;
-    uint32_t (*nbr)[kLanes] = nbr_all[team];
-    const uint32_t K = T.K;
-    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, T.ntiles, team, kTeams);
-    // word l of the per-tile LDS entry of tile t
-    auto entry = [&](uint64_t t, uint32_t l) -> uint32_t {
-        return (!BATCH || l < 8) ? T.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
-    };
-
-    for (uint32_t o = threadIdx.x * 16; o < kTeams * T.lds_total; o += 256 * 16)
-        *reinterpret_cast<uint4 *>(lds_all + o) = make_uint4(0, 0, 0, 0);
-    const RuleTables RT = rule_tables(rule);
-    uint32_t hsrc[HPT], hdst[HPT];
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const uint32_t h = tid + TEAM * j;
-        const bool ok = h < T.halo_count;
-        hsrc[j] = ok ? T.halo_src[h] : kOutside;
-        hdst[j] = ok ? T.halo_dst[h] : T.dummy;
-    }
-    // Block window corners (the same for every tile).
-    uint32_t blk[BPT];
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) blk[j] = T.lut1[min(tid + TEAM * j, T.nblk - 1)];
-    // Neighbour tiles go through LDS two tiles ahead: the last kLanes threads
-    // of the team load the entries of tile it+2 after the first barrier of
-    // tile it and publish them after its second barrier.
-    if (tid >= kLane0) {
-        if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
-        if (R.first + R.step < R.end) nbr[1][tid - kLane0] = entry(R.first + R.step, tid - kLane0);
-    }
-    __syncthreads();
-
-    // Where tile t lives: its state array, local index and tail flag.
-    const uint8_t *src = in;
-    uint8_t *dst = out;
-    uint32_t local = 0, cells = T.cells;
-    bool tail = false;
-    auto locate = [&](uint64_t t, const uint32_t *e) {
-        if (BATCH) {
-            const uint64_t base = uint64_t(__builtin_amdgcn_readfirstlane(e[8])) << 4;
-            const uint32_t w = __builtin_amdgcn_readfirstlane(e[9]);
-            src = in + base;
-            dst = out + base;
-            local = w & 0x7FFFFFFFu;
-            tail = (w >> 31) != 0;
-            cells = (local + 1) * K;  // only read when tail is set: the tile is the last one
-        } else {
-            local = uint32_t(t);
-            tail = (local * K + K == T.cells) && (T.cells & 15);
-        }
-    };
-
-    TilePrefetch<CPT, HPT> pf;
-    uint32_t pf_ph = 0xFFFFFFFFu;  // no offsets loaded yet
-    if (R.first < R.end) {
-        locate(R.first, nbr[0]);
-        tile_prefetch<TEAM, CPT, HPT, !BATCH>(T, src, local, tail, cells, nbr[0], hsrc, pf, pf_ph);
-    }
-
-    const uint32_t *box32 = reinterpret_cast<const uint32_t *>(box);
-    const uint32_t W4 = T.W >> 2;
-    uint32_t it = 0;
-    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
-        const uint32_t B = local * K;  // first cell of the tile in its state array (< 2^32)
-        uint8_t *gout = dst + B;
-        const uint32_t ph = B & 15;
-        const uint32_t nchunks = (ph + K + 15) >> 4;
-        // 1. scatter the prefetched tile and halo into the box.  Offsets of
-        //    bytes outside the tile point at a never-read byte.
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            if (tid + TEAM * j < nchunks) {
-                const uint32_t v[4] = {pf.v[j].x, pf.v[j].y, pf.v[j].z, pf.v[j].w};
-                const uint32_t e[8] = {pf.e[j][0].x, pf.e[j][0].y, pf.e[j][0].z, pf.e[j][0].w,
-                                       pf.e[j][1].x, pf.e[j][1].y, pf.e[j][1].z, pf.e[j][1].w};
-#pragma unroll
-                for (int b = 0; b < 16; ++b)
-                    box[(e[b >> 1] >> (16 * (b & 1))) & 0xFFFFu] = uint8_t(v[b >> 2] >> (8 * (b & 3)));
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) box[hdst[j]] = uint8_t(pf.halo[j]);
-        team_sync<TEAM>();
-
-        // 2. start loading the next tile
-        if (t64 + R.step < R.end) {
-            const uint32_t *e = nbr[(it + 1) & 1];
-            locate(t64 + R.step, e);
-            tile_prefetch<TEAM, CPT, HPT, !BATCH>(T, src, local, tail, cells, e, hsrc, pf, pf_ph);
-        }
-        uint32_t nb2 = kOutside;
-        if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
-
-        // 3. rule per block, next states straight to global memory (block b
-        //    holds the tile's cells [b CB, (b+1) CB))
-        if (RT.perm) {
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const uint32_t bi = tid + TEAM * j;
-                if (bi < T.nblk) {  // waves with no block left skip the work
-                    uint32_t next[4];
-                    block_rows<BS, true, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
-                    block_store<BS>(T, next, gout + bi * T.CB);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < BPT; ++j) {
-                const uint32_t bi = tid + TEAM * j;
-                if (bi < T.nblk) {
-                    uint32_t next[4];
-                    block_rows<BS, false, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
-                    block_store<BS>(T, next, gout + bi * T.CB);
-                }
-            }
-        }
-        // the box is read until here; the next tile's scatter comes after
-        team_sync<TEAM>();
-        if (tid >= kLane0) nbr[it & 1][tid - kLane0] = nb2;
     }
 }
 
@@ -1539,84 +1105,16 @@ hipError_t launch_step_lambda(const MapParams &P, uint32_t lam_words, const uint
                        pitch, rule);
     return hipGetLastError();
 }
-// Persistent launch: as many work-groups as can be resident at once (the
-// occupancy of this instantiation for its LDS size), capped by the tiles.
-template <int BS, int CPT, int HPT, int BPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
-static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    constexpr uint32_t kTeams = 256 / TEAM;
-    const size_t lds = size_t(kTeams) * T.lds_total;
-    // resident work-groups per CU for this instantiation and LDS size; the
-    // last answer is kept (one query per plan, not per launch)
-    static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
-    int per_cu = 0;
-    const uint64_t c = cached.load(std::memory_order_relaxed);
-    if (c >> 32 == lds && (c & 0xFFFFFFFFu)) {
-        per_cu = int(c & 0xFFFFFFFFu);
-    } else {
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE, ROWS>, 256, lds);
-        if (e != hipSuccess) return e;
-        if (per_cu < 1) per_cu = 1;
-        cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
-    }
-    // More than seven work-groups per CU measured slower where the occupancy
-    // allows eight (H r10: 186 us per generation at 8, 166 us at 7; the
-    // batch's H group 124 -> 111 us); at 7 and below nothing changes.
-    constexpr int kMaxPerCU = 7;
-    const uint64_t grid = std::min<uint64_t>(uint64_t(std::min(per_cu, kMaxPerCU)) * cu_count,
-                                             (T.ntiles + kTeams - 1) / kTeams);
-    hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE, ROWS>), dim3(uint32_t(grid)), dim3(256), lds, st,
-                       P, T, in, out, rule, rec);
-    return hipGetLastError();
-}
-template <int BS, int CPT, int HPT, bool BATCH, int TEAM, bool EDGE, int ROWS>
-static hipError_t launch_tiled_b(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    const uint32_t bpt = (T.nblk + TEAM - 1) / TEAM;
-    if (bpt <= 1) return launch_tiled_t<BS, CPT, HPT, 1, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 2) return launch_tiled_t<BS, CPT, HPT, 2, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
-    if (bpt <= 4) return launch_tiled_t<BS, CPT, HPT, 4, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st);
-    return hipErrorInvalidValue;
-}
-template <int BS, bool BATCH, int TEAM, bool EDGE, int ROWS>
-static hipError_t launch_tiled_s(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                 uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    const uint32_t cpt = (T.K + 30 + 16 * TEAM - 1) / (16 * TEAM);
-    const uint32_t hpt = (T.halo_count + TEAM - 1) / TEAM;
-#define NBB_TILED_CASE(C, H) \
-    if (cpt <= C && hpt <= H) return launch_tiled_b<BS, C, H, BATCH, TEAM, EDGE, ROWS>(P, T, in, out, rule, rec, cu_count, st)
-    NBB_TILED_CASE(1, 1);
-    NBB_TILED_CASE(1, 2);
-    NBB_TILED_CASE(1, 4);
-    NBB_TILED_CASE(2, 1);
-    NBB_TILED_CASE(2, 2);
-    NBB_TILED_CASE(2, 4);
-#undef NBB_TILED_CASE
-    return hipErrorInvalidValue;
-}
-template <bool BATCH, int TEAM, bool EDGE>
-static hipError_t launch_tiled_bs(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
-                                  uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
-    switch (T.BS) {
-        case 2: return launch_tiled_s<2, BATCH, TEAM, EDGE, 2>(P, T, in, out, rule, rec, cu_count, st);
-        case 3:  // 3x3 blocks whose third row holds no cell get the two-row form
-            return T.brows == 2 ? launch_tiled_s<3, BATCH, TEAM, EDGE, 2>(P, T, in, out, rule, rec, cu_count, st)
-                                : launch_tiled_s<3, BATCH, TEAM, EDGE, 3>(P, T, in, out, rule, rec, cu_count, st);
-        case 4: return launch_tiled_s<4, BATCH, TEAM, EDGE, 4>(P, T, in, out, rule, rec, cu_count, st);
-        default: return hipErrorInvalidValue;
-    }
-}
 template <bool BATCH>
 static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                                    uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const bool edge = (rule >> 31) != 0;  // four edge neighbours only
     if (T.team == 64)
-        return edge ? launch_tiled_bs<BATCH, 64, true>(P, T, in, out, rule, rec, cu_count, st)
-                    : launch_tiled_bs<BATCH, 64, false>(P, T, in, out, rule, rec, cu_count, st);
+        return edge ? launch_tiled_inst<BATCH, 64, true>(P, T, in, out, rule, rec, cu_count, st)
+                    : launch_tiled_inst<BATCH, 64, false>(P, T, in, out, rule, rec, cu_count, st);
     if (T.team == 256)
-        return edge ? launch_tiled_bs<BATCH, 256, true>(P, T, in, out, rule, rec, cu_count, st)
-                    : launch_tiled_bs<BATCH, 256, false>(P, T, in, out, rule, rec, cu_count, st);
+        return edge ? launch_tiled_inst<BATCH, 256, true>(P, T, in, out, rule, rec, cu_count, st)
+                    : launch_tiled_inst<BATCH, 256, false>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,

@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
                 ("strategy", ctypes.c_uint32), ("tile_level", ctypes.c_uint32),
                 ("tile_side", ctypes.c_uint32), ("halo_cells", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("bbox_pitch", ctypes.c_uint64),
-                ("device_table_bytes", ctypes.c_uint64)]
+                ("device_table_bytes", ctypes.c_uint64), ("box_low_side", ctypes.c_uint32),
+                ("box_high_side", ctypes.c_uint32)]
 
 
 class PlanView(ctypes.Structure):

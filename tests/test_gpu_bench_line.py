@@ -19,7 +19,7 @@ def test_bench_prints_one_complete_json_line():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1", "--bbox-steps", "5",
            "--map-reps", "1", "--cpu-seconds", "0.1", "--no-cpu-one-thread", "--repeats", "2",
-           "--batch-steps", "3", "--batch-seq-steps", "1", "--serve-seconds", "0"]
+           "--batch-steps", "3", "--batch-seq-steps", "1", "--serve-seconds", "0", "--large-steps", "3"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -42,6 +42,11 @@ def test_bench_prints_one_complete_json_line():
     assert d["packed_state"]["equals_byte_step"] is True
     assert d["batch"]["matches_sequential"] is True and d["batch"]["small_instances"]["same"] is True
     assert d["small_triangle_r10"]["graph_equals_eager"] is True
+    assert d["compact_repeats"]["steps_each"] >= 100
+    for nm in ("carpet_r9", "hfractal_r10"):
+        lw = d["large_workloads"][nm]
+        assert lw["compact_equals_bbox"] is True and lw["steps"] == 3
+        assert abs(lw["roofline_frac"] - lw["alg_gbps"] / 8000.0) < 1e-9
 
 
 def test_bench_refuses_several_gpus():

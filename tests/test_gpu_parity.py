@@ -316,6 +316,40 @@ def test_step_bbox_small(N, name, r):
                                           err_msg=f"{name} r={r} {rule} steps={steps}")
 
 
+# Levels whose box no longer fits the low-level membership bitmap (n > 1024):
+# membership then combines the low bitmap (s^L columns, s^L <= 1024) with the
+# high-level byte map, and for s = 3 (SL = 729, not a multiple of 16) a
+# 16-column group can straddle two high-level squares.  Every full-size box
+# workload runs this form.
+BOX_TWO_LEVEL = [("triangle", 11), ("triangle", 12), ("carpet", 7), ("carpet", 8), ("hfractal", 7),
+                 ("chandelier", 8)]
+BOX_TWO_LEVEL_RULES = ["B3/S23", "B36/S23", "B1357/S02468", "vN:B2/S12"]
+
+
+@pytest.mark.parametrize("name,r", BOX_TWO_LEVEL)
+def test_box_two_level_membership(N, name, r):
+    fd, o, g = pair(name, r, N)
+    info = g.info()
+    assert info.box_high_side > 1 and info.box_low_side * info.box_high_side == o.n
+    if fd.s == 3:
+        assert info.box_low_side == 729  # 16-column groups straddle high-level squares
+    seed, p = 300 + r, 0.45
+    st0 = o.init_bbox(seed, p)
+    np.testing.assert_array_equal(box_view(g, g.init_bbox(seed, p)), st0, err_msg=f"{name} r={r} init")
+    for rule in BOX_TWO_LEVEL_RULES:
+        rm = W.rule_mask(rule)
+        for steps in (1, 3):
+            want = o.bbox_steps(st0, rm, steps)
+            a = g.init_bbox(seed, p)
+            res = g.step_bbox(a, torch.full_like(a, 0x77), steps, rm)
+            np.testing.assert_array_equal(box_view(g, res), want, err_msg=f"{name} r={r} box {rule} {steps}")
+            del a, res
+            a = g.init_bbox(seed, p)
+            res = g.step_lambda(a, torch.full_like(a, 0x5A), steps, rm)
+            np.testing.assert_array_equal(box_view(g, res), want, err_msg=f"{name} r={r} lambda {rule} {steps}")
+            del a, res
+
+
 @pytest.mark.parametrize("name,r", SMALL)
 def test_step_lambda_small(N, name, r):
     # the lambda approach (threads over fractal cells, state in the box)
@@ -471,20 +505,28 @@ def test_large_triangle_workload(N):
 @pytest.mark.parametrize("wname", ["carpet_r9", "hfractal_r10"])
 def test_large_carpet_and_h_workloads(N, wname):
     # carpet r = 9 (134M cells) and H r = 10 (282M cells), Bernoulli(0.5):
-    # whole initial state against the oracle, sampled cells after 1 and 2
-    # steps (light-cone evaluation), then compact vs box on the GPU for 200 steps.
+    # whole initial state and whole state after 2 steps against the oracle,
+    # for the compact step and for the box step (its fractal cells equal the
+    # oracle's and no other box cell is alive: the box holds bytes, so equal
+    # sums leave nothing alive off the fractal); then compact vs box on the
+    # GPU for 200 steps.
     w = W.WORKLOADS[wname]
     fd, o, g = pair(w.fractal.name, w.r, N)
     st0 = o.init_compact(w.seeds[0], w.p)
     a = g.init_compact(w.seeds[0], w.p)
     np.testing.assert_array_equal(host(a), st0)
-    samp = W.random_indices(3, 20000, o.cells).astype(np.int64)
+    want2 = o.compact_steps(st0, B3S23, 2)
     b = torch.empty_like(a)
-    for steps in (1, 2):
-        res = g.step_compact(a.clone(), b, steps)
-        np.testing.assert_array_equal(host(res)[samp], o.cells_after(st0, samp, B3S23, steps))
-    res = g.step_compact(a, b, w.steps)
+    res = g.step_compact(a.clone(), b, 2)
+    np.testing.assert_array_equal(host(res), want2)
     box = g.init_bbox(w.seeds[0], w.p)
+    np.testing.assert_array_equal(host(g.gather(box)), st0)
+    assert int(box.sum(dtype=torch.int64)) == int(st0.sum(dtype=np.int64))
+    resb = g.step_bbox(box.clone(), torch.empty_like(box), 2)
+    np.testing.assert_array_equal(host(g.gather(resb)), want2)
+    assert int(resb.sum(dtype=torch.int64)) == int(want2.sum(dtype=np.int64))
+    del resb, want2
+    res = g.step_compact(a, b, w.steps)
     resb = g.step_bbox(box, torch.empty_like(box), w.steps)
     assert torch.equal(g.gather(resb), res)
 
