@@ -367,6 +367,23 @@ def main():
         log(f"compact, {len(per)} runs of {Kr}: median {repeats['median_us']:.2f} us, "
             f"mean {repeats['mean_us']:.2f} us")
 
+    # ---- the same step in the byte-scatter form (the tile scattered into an
+    # LDS box) at the same tile level, for comparison with the edge-record form
+    box_form = None
+    if info.strategy == N.STRATEGY_TILED and info.tiled_form == 1:
+        Kf = max(100, min(K, 200))
+        g.configure(N.STRATEGY_TILED_BOX, info.tile_level)
+        fa, fb = init.clone(), torch.empty_like(init)
+        g.step_compact(fa.clone(), fb, 2, rule)
+        msf, resf = time_events(torch, lambda: g.step_compact(fa, fb, Kf, rule))
+        g.configure(N.STRATEGY_TILED, info.tile_level)
+        refe = g.step_compact(init.clone(), torch.empty_like(init), Kf, rule)
+        box_form = {"us_per_step": msf / Kf * 1e3, "steps": Kf,
+                    "alg_gbps": alg_bytes / (msf / Kf * 1e-3) / 1e9,
+                    "equals_edge_form": bool(torch.equal(resf, refe))}
+        log(f"byte-scatter form: {box_form['us_per_step']:.2f} us/step, same: {box_form['equals_edge_form']}")
+        del fa, fb, resf, refe
+
     # ---- the same generations on the bit-packed state (1 bit per cell) -----
     packed = None
     if info.strategy != N.STRATEGY_DIRECT:
@@ -502,6 +519,7 @@ def main():
         "config": {"workload": wl.name, "fractal": f"F^{{{fd.k},{fd.s}}} {fd.name}", "r": wl.r, "n": g.n,
                    "cells": g.cells, "p": wl.p, "seed": wl.seeds[0], "rule": wl.rule,
                    "strategy": STRATEGY_NAMES[info.strategy],
+                   "tiled_form": {0: None, 1: "edge_records", 2: "byte_scatter"}[info.tiled_form],
                    "tile_level": info.tile_level},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
@@ -514,6 +532,7 @@ def main():
         "compact_equals_bbox": parity,
         "memory_ratio_bbox_over_compact": g.n * g.n / g.cells,
         "maps": maps,
+        "byte_scatter_form": box_form,
         "small_triangle_r10": small,
         "large_workloads": large,
         "packed_state": packed,

@@ -77,6 +77,7 @@ typedef enum {
 #define NBB_STRATEGY_TILED 1u  /* level-m tiles staged in LDS with their halo */
 #define NBB_STRATEGY_DIRECT 2u /* one thread per cell: lambda, 8 x nu, rule */
 #define NBB_STRATEGY_TILED_WAVE 3u /* TILED with one wavefront per tile: for small tiles */
+#define NBB_STRATEGY_TILED_BOX 4u  /* TILED, always in the byte-scatter form (see nbb_info.tiled_form) */
 
 typedef struct nbb_fractal nbb_fractal;
 
@@ -98,6 +99,13 @@ typedef struct {
      * high-level squares when SL is not a multiple of 16. */
     uint32_t box_low_side;  /* SL */
     uint32_t box_high_side; /* NH (0 when the box is too large to exist) */
+    /* How a tiled strategy runs the step: 1 = edge records (each block's
+     * cells loaded into registers, only the blocks' edge rows and columns
+     * exchanged through LDS; TILED where the tile level allows it),
+     * 2 = byte scatter (the tile's cells scattered into an LDS box: TILED
+     * elsewhere, TILED_BOX, TILED_WAVE); 0 for DIRECT. */
+    uint32_t tiled_form;
+    uint32_t reserved0;
 } nbb_info;
 
 /*
@@ -120,8 +128,10 @@ void nbb_destroy(nbb_fractal *f);
 nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
 
 /*
- * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED
- * and TILED_WAVE, the tile level m (0 = automatic; otherwise 1 <= m <= r).
+ * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED,
+ * TILED_BOX and TILED_WAVE, the tile level m (0 = automatic; otherwise
+ * 1 <= m <= r).  TILED_BOX is TILED held to the byte-scatter form (nbb_query
+ * then reports strategy TILED with tiled_form 2).
  * Both need 2 <= s <= 4 and r >= 1; TILED_WAVE also needs a tile small
  * enough for one wavefront (k^m + 30 <= 2048 cells, at most 256 halo cells
  * and blocks, four LDS boxes within 64 KiB).  NBB_E_INVALID when the request
@@ -411,6 +421,19 @@ const char *nbb_status_string(nbb_status s);
  *   halo_dst[h] = byte offset in the LDS box;
  *   nbr[8 t + d] = tile in direction d of tile t (same numbering), or
  *   0xFFFFFFFF where that block of the box holds no fractal cell.
+ *
+ * The edge-record form at the same level (edge_ok = 0 where it does not
+ * apply): blocks sit on an edge_grid x edge_grid slot grid (block b at
+ * lambda_{m-q}(b) in block units) with a one-slot ring; the grid keeps
+ * edge_rows rows of edge_grid + 2 slots of 16 bytes (edge_rec_bytes).
+ *   edge_blk[2b] = slot of block b | slot above << 16, edge_blk[2b+1] = slot
+ *   below | near << 31 (its 4 edge_nsrc-byte load would pass the tile's end,
+ *   so it loads the bytes ending at its last cell);
+ *   edge_halo[2h] = direction << 29 | block of that neighbour tile,
+ *   edge_halo[2h+1] = ring slot | near << 31, for edge_halo_count items;
+ *   edge_unpack / edge_pack: the v_perm selectors from a block's bytes to its
+ *   rows and from next-state rows back to compact order ([0..3] for rows or
+ *   output dwords 0-3 from the first pair of sources, [4..7] from the second).
  */
 typedef struct nbb_plan nbb_plan;
 typedef struct {
@@ -422,6 +445,10 @@ typedef struct {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;
+    uint32_t edge_ok, edge_grid, edge_rows, edge_rec_bytes, edge_halo_count, edge_nsrc, edge_nsh;
+    uint32_t edge_unpack[8], edge_pack[8];
+    const uint32_t *edge_blk;
+    const uint32_t *edge_halo;
 } nbb_plan_view;
 nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
                           uint32_t tile_level, nbb_plan **out, nbb_plan_view *view);

@@ -32,6 +32,10 @@ def units():
             for edge in (0, 1):
                 out.append(("tiled_inst.hip", f"tiled_b{batch}_t{team}_e{edge}.o",
                             [f"-DNBB_INST_BATCH={batch}", f"-DNBB_INST_TEAM={team}", f"-DNBB_INST_EDGE={edge}"]))
+    for batch in (0, 1):
+        for edge, rule in ((0, 0), (0, 1), (0, 2), (1, 1)):
+            out.append(("edges_inst.hip", f"edges_b{batch}_e{edge}_r{rule}.o",
+                        [f"-DNBB_INST_BATCH={batch}", f"-DNBB_INST_EDGE={edge}", f"-DNBB_INST_RULE={rule}"]))
     return out
 
 

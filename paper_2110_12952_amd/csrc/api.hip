@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/nbbfrac.h"
+#include "edges_launch.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -47,6 +48,13 @@ struct nbb_fractal {
     BoxTables box;
     MfmaTables mfma;
     uint32_t strategy = NBB_STRATEGY_DIRECT;
+    // The tiled step runs in edge-record form (k_step_edges) when its plan
+    // applies at the tile level and the strategy is TILED; otherwise (and for
+    // TILED_BOX / TILED_WAVE) in byte-scatter form (k_step_tiled).
+    EdgePlan edge;
+    bool use_edges = false;
+    DevBlob dedge;
+    EdgeParams ep{};
     int device = 0;
     int cu_count = 256;
     DevBlob dmap, dtile, dbox, dmfma;
@@ -73,12 +81,16 @@ struct nbb_fractal {
 struct nbb_plan {
     Fractal f;
     TilePlan tile;
+    EdgePlan edge;
 };
 
 // A batch: groups of instances that share a tile plan, each stepped by one
 // launch over the group's tiles, and instances stepped one by one.
 struct BatchGroup {
     TileParams tp;           // the plan of the group's first descriptor; nbr / ntiles are the batch's
+    bool edges = false;      // stepped in edge-record form (ep, with the batch's nbr / ntiles)
+    EdgeParams ep{};
+    uint32_t BS = 0, nsrc = 0;
     const uint32_t *rec = nullptr;
     std::vector<uint32_t> index;      // the group's instances (caller's numbering), in tile order
     std::vector<uint64_t> tiles_end;  // tiles of the first j+1 of them
@@ -257,6 +269,49 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     return NBB_OK;
 }
 
+// Uploads the edge plan's tables; the neighbour table is the tile plan's
+// (same level), already on the device at T.nbr.
+nbb_status upload_edges(const EdgePlan &p, const TileParams &T, DevBlob *blob, EdgeParams *E) {
+    const void *src[2] = {p.blk.data(), p.halo.data()};
+    size_t bytes[2] = {p.blk.size() * 4, p.halo.size() * 4};
+    void *dst[2];
+    nbb_status s = upload(blob, src, bytes, 2, dst);
+    if (s != NBB_OK) return s;
+    *E = EdgeParams{};
+    E->K = p.K;
+    E->CB = p.CB;
+    E->nblk = p.nblk;
+    E->nhalo = p.nhalo;
+    E->ntiles = T.ntiles;
+    E->rec_bytes = p.rec_bytes;
+    E->nsh = p.nsh;
+    std::memcpy(E->unpack01, p.unpack01, sizeof(E->unpack01));
+    std::memcpy(E->unpack23, p.unpack23, sizeof(E->unpack23));
+    std::memcpy(E->pack01, p.pack01, sizeof(E->pack01));
+    std::memcpy(E->pack23, p.pack23, sizeof(E->pack23));
+    E->blk = static_cast<const uint32_t *>(dst[0]);
+    E->halo = static_cast<const uint32_t *>(dst[1]);
+    E->nbr = T.nbr;
+    return NBB_OK;
+}
+
+// Builds and uploads the edge plan at the tile plan's level for a TILED
+// descriptor; leaves the byte-scatter form in place where it does not apply.
+nbb_status setup_edges(nbb_fractal *F) {
+    blob_free(&F->dedge);
+    F->use_edges = false;
+    F->edge = EdgePlan();
+    if (F->strategy != NBB_STRATEGY_TILED || F->tile.team != 256) return NBB_OK;
+    std::string msg;
+    EdgePlan p;
+    if (!build_edge_plan(F->f, F->tile.m, &p, &msg)) return NBB_OK;
+    nbb_status st = upload_edges(p, F->tp, &F->dedge, &F->ep);
+    if (st != NBB_OK) return st;
+    F->edge = std::move(p);
+    F->use_edges = true;
+    return NBB_OK;
+}
+
 nbb_status upload_mfma(nbb_fractal *F) {
     if (!F->mfma.ktiles) return NBB_OK;
     const void *src[2] = {F->mfma.A.data(), F->mfma.Anu.data()};
@@ -386,6 +441,22 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->halo_src = t.halo_src.data();
     view->halo_dst = t.halo_dst.data();
     view->nbr = t.nbr.data();
+    view->edge_ok = build_edge_plan(p->f, t.m, &p->edge, &msg) ? 1u : 0u;
+    const EdgePlan &e = p->edge;
+    view->edge_grid = e.G;
+    view->edge_rows = e.grid_rows;
+    view->edge_rec_bytes = e.rec_bytes;
+    view->edge_halo_count = e.nhalo;
+    view->edge_nsrc = e.nsrc;
+    view->edge_nsh = e.nsh;
+    for (int i = 0; i < 4; ++i) {
+        view->edge_unpack[i] = e.unpack01[i];
+        view->edge_unpack[4 + i] = e.unpack23[i];
+        view->edge_pack[i] = e.pack01[i];
+        view->edge_pack[4 + i] = e.pack23[i];
+    }
+    view->edge_blk = e.blk.data();
+    view->edge_halo = e.halo.data();
     *out = p;
     return NBB_OK;
 }
@@ -423,6 +494,7 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
             if (build_tile_plan(F->f, auto_tile_level(F->f), &F->tile, &msg)) {
                 st = upload_tile(F, F->tile, &F->dtile, &F->tp);
                 if (st == NBB_OK) F->strategy = NBB_STRATEGY_TILED;
+                if (st == NBB_OK) st = setup_edges(F);
             }
         }
     }
@@ -430,6 +502,7 @@ nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r
         blob_free(&F->dmap);
         blob_free(&F->dbox);
         blob_free(&F->dtile);
+        blob_free(&F->dedge);
         blob_free(&F->dmfma);
         delete F;
         return st;
@@ -445,6 +518,7 @@ void nbb_destroy(nbb_fractal *F) {
     blob_free(&F->dmap);
     blob_free(&F->dbox);
     blob_free(&F->dtile);
+    blob_free(&F->dedge);
     blob_free(&F->dmfma);
     delete F;
 }
@@ -470,7 +544,9 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
         info->tile_side = 1;
     }
     info->bbox_pitch = box_pitch(F->f);
-    info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes + F->dmfma.bytes;
+    info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes + F->dedge.bytes + F->dmfma.bytes;
+    if (F->use_edges) info->lds_bytes = F->edge.rec_bytes;
+    info->tiled_form = F->strategy == NBB_STRATEGY_DIRECT ? 0u : (F->use_edges ? 1u : 2u);
     info->box_low_side = F->box.SL;
     info->box_high_side = F->box.high.empty() ? 0 : F->box.NH;
     return NBB_OK;
@@ -484,9 +560,12 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     if (strategy == NBB_STRATEGY_DIRECT) {
         if (tile_level != 0) return fail(NBB_E_INVALID, "the direct strategy takes no tile level");
         F->strategy = NBB_STRATEGY_DIRECT;
+        blob_free(&F->dedge);
+        F->use_edges = false;
         return NBB_OK;
     }
-    if (strategy != NBB_STRATEGY_TILED && strategy != NBB_STRATEGY_TILED_WAVE)
+    if (strategy != NBB_STRATEGY_TILED && strategy != NBB_STRATEGY_TILED_WAVE &&
+        strategy != NBB_STRATEGY_TILED_BOX)
         return fail(NBB_E_INVALID, "unknown strategy");
     const uint32_t team = strategy == NBB_STRATEGY_TILED_WAVE ? 64u : 256u;
     std::string msg;
@@ -502,8 +581,14 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     F->dtile = blob;
     F->tile = std::move(plan);
     F->tp = T;
-    F->strategy = strategy;
-    return NBB_OK;
+    F->strategy = strategy == NBB_STRATEGY_TILED_BOX ? NBB_STRATEGY_TILED : strategy;
+    if (strategy == NBB_STRATEGY_TILED_BOX) {
+        blob_free(&F->dedge);
+        F->use_edges = false;
+        F->edge = EdgePlan();
+        return NBB_OK;
+    }
+    return setup_edges(F);
 }
 
 nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps, uint32_t rule,
@@ -534,7 +619,8 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
             uint64_t K = 1;
             for (uint32_t j = 0; j < fit[i]; ++j) K *= F->f.k;
             if (K >= 128 || i + 1 == fit.size()) {
-                cand.push_back({NBB_STRATEGY_TILED, fit[i]});
+                cand.push_back({NBB_STRATEGY_TILED, fit[i]});       // edge records where they apply
+                cand.push_back({NBB_STRATEGY_TILED_BOX, fit[i]});   // byte scatter
                 cand.push_back({NBB_STRATEGY_TILED_WAVE, fit[i]});  // skipped where it does not fit
             }
         }
@@ -706,8 +792,8 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
         for (uint32_t j = 0; j < x->f.k; ++j)
             if (x->f.ox[j] != y->f.ox[j] || x->f.oy[j] != y->f.oy[j]) return false;
         const TileParams &a = x->tp, &b = y->tp;
-        return x->strategy == y->strategy && a.team == b.team && a.m == b.m && a.W == b.W &&
-               a.lds_total == b.lds_total && a.halo_count == b.halo_count;
+        return x->strategy == y->strategy && x->use_edges == y->use_edges && a.team == b.team && a.m == b.m &&
+               a.W == b.W && a.lds_total == b.lds_total && a.halo_count == b.halo_count;
     };
     // Resident instances group by their resident plans.
     auto same_resident = [](const nbb_fractal *x, const nbb_fractal *y) {
@@ -838,6 +924,15 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
         G.tp.ntiles = uint32_t(ntiles[g]);
         G.tp.cells = 0;  // per instance, from the records
         G.rec = rec;
+        const nbb_fractal *rep = launch.reps[g];
+        if (rep->use_edges) {
+            G.edges = true;
+            G.ep = rep->ep;
+            G.ep.nbr = nbr;
+            G.ep.ntiles = uint32_t(ntiles[g]);
+            G.BS = rep->edge.BS;
+            G.nsrc = rep->edge.nsrc;
+        }
         G.index = launch.index[g];
         uint64_t acc = 0;
         for (const BatchInstance &I : launch.members[g]) G.tiles_end.push_back(acc += I.ntiles);
@@ -977,7 +1072,8 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     uint8_t *in = a, *out = b;
     for (uint32_t i = 0; i < steps; ++i) {
         for (const BatchGroup &G : B->groups) {
-            e = launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, s);
+            e = G.edges ? launch_step_edges(G.ep, G.BS, G.nsrc, in, out, rule, G.rec, B->cu_count, s)
+                        : launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, s);
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
         }
         for (const BatchDirect &d : B->direct) {
@@ -1027,9 +1123,16 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
             const BatchGroup &G = B->groups[k];
             while (live[k] && steps[G.index[live[k] - 1]] <= g) --live[k];
             if (!live[k]) continue;
-            TileParams T = G.tp;
-            T.ntiles = uint32_t(G.tiles_end[live[k] - 1]);
-            e = launch_step_tiled_batch(T, G.rec, in, out, rule, B->cu_count, s);
+            const uint32_t nt = uint32_t(G.tiles_end[live[k] - 1]);
+            if (G.edges) {
+                EdgeParams E = G.ep;
+                E.ntiles = nt;
+                e = launch_step_edges(E, G.BS, G.nsrc, in, out, rule, G.rec, B->cu_count, s);
+            } else {
+                TileParams T = G.tp;
+                T.ntiles = nt;
+                e = launch_step_tiled_batch(T, G.rec, in, out, rule, B->cu_count, s);
+            }
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
         }
         for (const BatchDirect &d : B->direct) {
@@ -1145,7 +1248,14 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     if (result_in_b) *result_in_b = int(steps & 1);
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *in = a, *out = b;
-    if (F->strategy != NBB_STRATEGY_DIRECT) {
+    if (F->use_edges) {
+        for (uint32_t i = 0; i < steps; ++i) {
+            hipError_t e = launch_step_edges(F->ep, F->edge.BS, F->edge.nsrc, in, out, rule, nullptr, F->cu_count,
+                                             s);
+            if (e != hipSuccess) return hip_fail(e, "edge step launch");
+            std::swap(in, out);
+        }
+    } else if (F->strategy != NBB_STRATEGY_DIRECT) {
         for (uint32_t i = 0; i < steps; ++i) {
             hipError_t e = launch_step_tiled(F->mp, F->tp, in, out, rule, F->cu_count, s);
             if (e != hipSuccess) return hip_fail(e, "tiled step launch");

@@ -1,0 +1,411 @@
+// The tiled compact step in edge-record form (k_step_edges) and its launchers.
+// Included by edges_inst.hip, which is compiled once per (BATCH, RULE) so the
+// instantiations build in parallel.
+//
+// Section 3's stencil procedure on the blocked approach, for compact storage:
+// tile t = compact cells [t K, (t+1) K) is one level-m copy of the fractal,
+// cut into level-q blocks whose CB cells are consecutive in compact order and
+// fill the same positions of a BS x BS square in every block.  Per tile a
+// work-group of 256 threads
+//   1. loads each block's CB bytes into registers (one load per block; every
+//      thread keeps its blocks for the whole launch), unpacks them into BS row
+//      dwords with v_perm (byte c of row r = cell (c, r), 0 off the fractal)
+//      and writes the block's edges as one 16-byte LDS record {top row,
+//      bottom row, left column, right column}; the blocks of the eight
+//      neighbour tiles that touch the tile's blocks do the same into the ring
+//      of the slot grid (zeros where a neighbour tile does not exist);
+//   2. reads, per block, the bottom rows of the three slots above, the top
+//      rows of the three below and the facing columns of the two beside it:
+//      with the block's own rows these are its whole (BS+2)-square window.
+//      Row 3-sums four positions per dword (SWAR: bytes never exceed 9),
+//      the rule per byte, v_perm back into compact order, and the block's CB
+//      next states go straight to global memory.
+// Work-groups are persistent over XCD-contiguous tile ranges; the next
+// tile's loads are issued before the current tile's rule, and its neighbour
+// tiles travel through LDS two tiles ahead.
+//
+// BATCH: tiles of many instances of one plan in an arena, as in the
+// byte-scatter form (k_step_tiled): batch tile g is local tile rec[2g+1]
+// (low 31 bits) of the state at byte 16 rec[2g] of the arena.
+//
+// RULE: 0 = B3/S23 (born with 3, survives with 2 or 3 <=> (neighbours |
+// self) == 3), 1 = any rule without birth or survival at 8 (two v_perm table
+// look-ups), 2 = any rule (per-byte bit extract from the rule word).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <atomic>
+
+#include "device_common.hpp"
+
+namespace nbb {
+
+template <int NSRC>
+struct RawBlock {
+    uint32_t d[NSRC];
+};
+
+// 4 NSRC bytes from any byte address (gfx950 global loads need no alignment).
+template <int NSRC>
+__device__ __forceinline__ RawBlock<NSRC> load_block(const uint8_t *p) {
+    RawBlock<NSRC> r;
+    __builtin_memcpy(&r, p, 4 * NSRC);
+    return r;
+}
+
+// The block's bytes were loaded ending at its last cell: move them down by
+// sh bytes (0 < sh < 4 NSRC, uniform).
+template <int NSRC>
+__device__ __forceinline__ void shift_block(RawBlock<NSRC> &r, uint32_t sh) {
+    uint32_t d[NSRC + 1];
+#pragma unroll
+    for (int i = 0; i < NSRC; ++i) d[i] = r.d[i];
+    d[NSRC] = 0;
+    for (uint32_t w = 0; w < (sh >> 2); ++w) {
+#pragma unroll
+        for (int i = 0; i < NSRC; ++i) d[i] = d[i + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NSRC; ++i) r.d[i] = alignbyte(d[i + 1], d[i], sh & 3);
+}
+
+template <int BS, int NSRC>
+__device__ __forceinline__ void unpack_rows(const EdgeParams &E, const RawBlock<NSRC> &r, uint32_t (&row)[BS]) {
+#pragma unroll
+    for (int rr = 0; rr < BS; ++rr) {
+        uint32_t v = __builtin_amdgcn_perm(r.d[1], r.d[0], E.unpack01[rr]);
+        if (NSRC == 4) v |= __builtin_amdgcn_perm(r.d[3], r.d[2], E.unpack23[rr]);
+        row[rr] = v;
+    }
+}
+
+// v_perm selector: bytes s0..s3 (s0 the lowest); 0-3 pick the second
+// operand's bytes, 4-7 the first's, 12 a zero byte.
+constexpr uint32_t sel4(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3) {
+    return s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
+}
+
+// The block's record: top row, bottom row, left column, right column (byte r
+// of a column = row r).
+template <int BS>
+__device__ __forceinline__ uint4 edge_record(const uint32_t (&row)[BS]) {
+    uint32_t left, right;
+    if (BS == 4) {
+        const uint32_t l01 = __builtin_amdgcn_perm(row[1], row[0], sel4(0, 4, 12, 12));
+        const uint32_t l23 = __builtin_amdgcn_perm(row[BS - 1], row[2], sel4(0, 4, 12, 12));
+        left = __builtin_amdgcn_perm(l23, l01, sel4(0, 1, 4, 5));
+        const uint32_t r01 = __builtin_amdgcn_perm(row[1], row[0], sel4(3, 7, 12, 12));
+        const uint32_t r23 = __builtin_amdgcn_perm(row[BS - 1], row[2], sel4(3, 7, 12, 12));
+        right = __builtin_amdgcn_perm(r23, r01, sel4(0, 1, 4, 5));
+    } else {
+        const uint32_t l01 = __builtin_amdgcn_perm(row[1], row[0], sel4(0, 4, 12, 12));
+        left = __builtin_amdgcn_perm(row[BS - 1], l01, sel4(0, 1, 4, 12));
+        const uint32_t r01 = __builtin_amdgcn_perm(row[1], row[0], sel4(2, 6, 12, 12));
+        right = __builtin_amdgcn_perm(row[BS - 1], r01, sel4(0, 1, 6, 12));
+    }
+    return make_uint4(row[0], row[BS - 1], left, right);
+}
+
+// Stores the CB compact bytes of w (any alignment).  CB is uniform, so the
+// choice below is scalar branches only.
+__device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB, uint8_t *p) {
+    if (CB == 16) {
+        store_u64(p, w[0], w[1]);
+        store_u64(p + 8, w[2], w[3]);
+    } else if (CB > 8) {
+        store_u64(p, w[0], w[1]);
+        uint32_t r = CB - 8, x = w[2];
+        p += 8;
+        if (r >= 4) {
+            store_u32(p, x);
+            p += 4;
+            r -= 4;
+            x = w[3];
+        }
+        if (r >= 2) {
+            store_u16(p, x);
+            p += 2;
+            r -= 2;
+            x >>= 16;
+        }
+        if (r) store_u8(p, x);
+    } else if (CB == 8) {
+        store_u64(p, w[0], w[1]);
+    } else if (CB > 4) {
+        store_u32(p, w[0]);
+        store_u32(p + (CB - 4), alignbyte(w[1], w[0], CB - 4));
+    } else if (CB == 4) {
+        store_u32(p, w[0]);
+    } else if (CB >= 2) {
+        store_u16(p, w[0]);
+        if (CB == 3) store_u16(p + 1, w[0] >> 8);
+    } else {
+        store_u8(p, w[0]);
+    }
+}
+
+// Next states of one block, rows in next[0..BS) (byte c = column c).
+// rec32: the record grid as dwords; so / sa / sb: the slots of the block and
+// of the blocks above and below it.
+template <int BS, bool EDGE, int RULE>
+__device__ __forceinline__ void edge_block_rule(const uint32_t *rec32, uint32_t so, uint32_t sa, uint32_t sb,
+                                                const uint32_t (&o)[BS], uint32_t rule, const RuleTables &RT,
+                                                uint32_t (&next)[4]) {
+    // the facing columns of the left and right neighbours
+    const uint32_t Lc = rec32[4 * (so - 1) + 3], Rc = rec32[4 * (so + 1) + 2];
+    // centre rows above and below (bottom row of the slot above, top row of the one below)
+    const uint32_t aC = rec32[4 * sa + 1], bC = rec32[4 * sb];
+    // lo: byte c = position c - 1, hi: byte c = position c + 1, for each window row
+    uint32_t lo[BS], hi[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+        lo[r] = __builtin_amdgcn_perm(o[r], Lc, sel4(r, 4, 5, 6));
+        hi[r] = BS == 4 ? __builtin_amdgcn_perm(Rc, o[r], sel4(1, 2, 3, 4 + r))
+                        : __builtin_amdgcn_perm(Rc, o[r], sel4(1, 2, 4 + r, 12));
+    }
+    uint32_t n[BS];
+    if (EDGE) {
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+            const uint32_t up = r == 0 ? aC : o[r - 1], dn = r == BS - 1 ? bC : o[r + 1];
+            n[r] = up + dn + lo[r] + hi[r];
+        }
+    } else {
+        const uint32_t aL = rec32[4 * (sa - 1) + 1], aR = rec32[4 * (sa + 1) + 1];
+        const uint32_t bL = rec32[4 * (sb - 1)], bR = rec32[4 * (sb + 1)];
+        uint32_t H[BS + 2];
+        if (BS == 4) {
+            H[0] = alignbyte(aC, aL, 3) + aC + alignbyte(aR, aC, 1);
+            H[BS + 1] = alignbyte(bC, bL, 3) + bC + alignbyte(bR, bC, 1);
+        } else {
+            H[0] = __builtin_amdgcn_perm(aC, aL, sel4(2, 4, 5, 6)) + aC +
+                   __builtin_amdgcn_perm(aR, aC, sel4(1, 2, 4, 12));
+            H[BS + 1] = __builtin_amdgcn_perm(bC, bL, sel4(2, 4, 5, 6)) + bC +
+                        __builtin_amdgcn_perm(bR, bC, sel4(1, 2, 4, 12));
+        }
+#pragma unroll
+        for (int r = 0; r < BS; ++r) H[r + 1] = lo[r] + o[r] + hi[r];
+#pragma unroll
+        for (int r = 0; r < BS; ++r) n[r] = H[r] + H[r + 1] + H[r + 2] - o[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r >= BS) {
+            next[r] = 0;
+            continue;
+        }
+        if (RULE == 0) {
+            next[r] = __builtin_amdgcn_perm(0u, 0x01000000u, n[r] | o[r]);
+        } else if (RULE == 1) {
+            const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n[r]);
+            const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n[r]);
+            const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, o[r]);  // 0xFF where alive
+            next[r] = (surv & smask) | (born & ~smask);
+        } else {
+            // v_bfe takes its offset from the low 5 bits of the operand
+            const uint32_t I = n[r] + (o[r] << 4);
+            uint32_t v = __builtin_amdgcn_ubfe(rule, I, 1);
+#pragma unroll
+            for (int c = 1; c < BS; ++c) v |= __builtin_amdgcn_ubfe(rule, I >> (8 * c), 1) << (8 * c);
+            next[r] = v;
+        }
+    }
+}
+
+template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE>
+__global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t *__restrict__ in,
+                                                    uint8_t *__restrict__ out, uint32_t rule,
+                                                    const uint32_t *__restrict__ rec) {
+    extern __shared__ __align__(16) uint8_t lds_e[];
+    constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
+    constexpr uint32_t kLane0 = 256 - kLanes;
+    __shared__ uint32_t nbr[2][kLanes];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t K = E.K, CB = E.CB;
+    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, E.ntiles);
+    auto entry = [&](uint64_t t, uint32_t l) -> uint32_t {
+        return (!BATCH || l < 8) ? E.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
+    };
+
+    for (uint32_t o = tid * 16; o < E.rec_bytes; o += 256 * 16)
+        *reinterpret_cast<uint4 *>(lds_e + o) = make_uint4(0, 0, 0, 0);
+    const RuleTables RT = rule_tables(rule);
+    // this thread's blocks and halo items (the same in every tile)
+    uint32_t so[BPT], sa[BPT], sb[BPT], boff[BPT], loff[BPT];
+    bool bnear[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const uint32_t bi = min(tid + 256 * j, E.nblk - 1);
+        const uint32_t w0 = E.blk[2 * bi], w1 = E.blk[2 * bi + 1];
+        so[j] = w0 & 0xFFFFu;
+        sa[j] = w0 >> 16;
+        sb[j] = w1 & 0xFFFFu;
+        bnear[j] = (w1 >> 31) != 0;
+        boff[j] = bi * CB;
+        loff[j] = boff[j] - (bnear[j] ? E.nsh : 0u);
+    }
+    uint32_t hdir[HPT], hoff[HPT], hslot[HPT];
+    bool hnear[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const uint32_t h = tid + 256 * j;
+        const bool ok = h < E.nhalo;
+        const uint32_t w0 = ok ? E.halo[2 * h] : 0u, w1 = ok ? E.halo[2 * h + 1] : 0u;
+        hdir[j] = ok ? (w0 >> 29) : 8u;  // 8: no item
+        hnear[j] = (w1 >> 31) != 0;
+        hoff[j] = (w0 & 0x1FFFFFFFu) * CB - (hnear[j] ? E.nsh : 0u);
+        hslot[j] = w1 & 0xFFFFu;
+    }
+    if (tid >= kLane0) {
+        if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
+        if (R.first + R.step < R.end) nbr[1][tid - kLane0] = entry(R.first + R.step, tid - kLane0);
+    }
+    __syncthreads();
+
+    // where a tile lives: its state array and local index
+    const uint8_t *src = in;
+    uint8_t *dst = out;
+    uint32_t local = 0;
+    auto locate = [&](uint64_t t, const uint32_t *e) {
+        if (BATCH) {
+            const uint64_t base = uint64_t(__builtin_amdgcn_readfirstlane(e[8])) << 4;
+            src = in + base;
+            dst = out + base;
+            local = __builtin_amdgcn_readfirstlane(e[9]) & 0x7FFFFFFFu;
+        } else {
+            local = uint32_t(t);
+        }
+    };
+    RawBlock<NSRC> raw[BPT], hraw[HPT];
+    auto prefetch = [&](const uint32_t *e) {
+        const uint8_t *tb = src + uint64_t(local) * K;
+#pragma unroll
+        for (int j = 0; j < BPT; ++j)
+            if (tid + 256 * j < E.nblk) raw[j] = load_block<NSRC>(tb + loff[j]);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const uint32_t nt = hdir[j] < 8 ? e[hdir[j]] : kOutside;
+            if (nt != kOutside) {
+                hraw[j] = load_block<NSRC>(src + uint64_t(nt) * K + hoff[j]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NSRC; ++i) hraw[j].d[i] = 0;
+            }
+        }
+    };
+    if (R.first < R.end) {
+        locate(R.first, nbr[0]);
+        prefetch(nbr[0]);
+    }
+
+    const uint32_t *rec32 = reinterpret_cast<const uint32_t *>(lds_e);
+    uint32_t it = 0;
+    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
+        uint8_t *gout = dst + uint64_t(local) * K;
+        // 1. records of the tile's blocks (kept as rows) and of the halo blocks
+        uint32_t rows[BPT][BS];
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            if (tid + 256 * j < E.nblk) {
+                if (bnear[j]) shift_block<NSRC>(raw[j], E.nsh);
+                unpack_rows<BS, NSRC>(E, raw[j], rows[j]);
+                *reinterpret_cast<uint4 *>(lds_e + 16 * so[j]) = edge_record<BS>(rows[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hdir[j] < 8) {
+                if (hnear[j]) shift_block<NSRC>(hraw[j], E.nsh);
+                uint32_t hr[BS];
+                unpack_rows<BS, NSRC>(E, hraw[j], hr);
+                *reinterpret_cast<uint4 *>(lds_e + 16 * hslot[j]) = edge_record<BS>(hr);
+            }
+        }
+        __syncthreads();
+        // 2. loads of the next tile
+        if (t64 + R.step < R.end) {
+            const uint32_t *e = nbr[(it + 1) & 1];
+            locate(t64 + R.step, e);
+            prefetch(e);
+        }
+        uint32_t nb2 = kOutside;
+        if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
+        // 3. the rule per block, next states straight to global memory
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            if (tid + 256 * j < E.nblk) {
+                uint32_t next[4];
+                edge_block_rule<BS, EDGE, RULE>(rec32, so[j], sa[j], sb[j], rows[j], rule, RT, next);
+                uint32_t w[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    w[d] = __builtin_amdgcn_perm(next[1], next[0], E.pack01[d]);
+                    if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
+                }
+                store_cells(w, CB, gout + boff[j]);
+            }
+        }
+        // the records are read until here; the next tile's come after
+        __syncthreads();
+        if (tid >= kLane0) nbr[it & 1][tid - kLane0] = nb2;
+    }
+}
+
+// Persistent launch: as many work-groups as can be resident at once, capped
+// by the tiles.
+template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE>
+static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
+                                 const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
+    const size_t lds = E.rec_bytes;
+    static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
+    int per_cu = 0;
+    const uint64_t c = cached.load(std::memory_order_relaxed);
+    if (c >> 32 == lds && (c & 0xFFFFFFFFu)) {
+        per_cu = int(c & 0xFFFFFFFFu);
+    } else {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE>, 256, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
+    }
+    if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
+    const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, E.ntiles);
+    if (!grid) return hipSuccess;
+    hipLaunchKernelGGL((k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE>), dim3(uint32_t(grid)), dim3(256), lds,
+                       st, E, in, out, rule, rec);
+    return hipGetLastError();
+}
+template <int BS, int NSRC, bool BATCH, bool EDGE, int RULE>
+static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
+                                 const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
+    const uint32_t bpt = (E.nblk + 255) / 256, hpt = (E.nhalo + 255) / 256;
+#define NBB_EDGES_CASE(B, H)                                                                              \
+    if (bpt <= B && hpt <= H)                                                                             \
+    return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st)
+    NBB_EDGES_CASE(1, 1);
+    NBB_EDGES_CASE(2, 1);
+    NBB_EDGES_CASE(4, 1);
+    NBB_EDGES_CASE(1, 2);
+    NBB_EDGES_CASE(2, 2);
+    NBB_EDGES_CASE(4, 2);
+#undef NBB_EDGES_CASE
+    return hipErrorInvalidValue;
+}
+// shape: BS 3 or 4, and 2 or 4 source dwords per block
+template <bool BATCH, bool EDGE, int RULE>
+static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in,
+                                     uint8_t *out, uint32_t rule, const uint32_t *rec, int cu_count, int max_per_cu,
+                                     hipStream_t st) {
+    if (BS == 3 && nsrc == 2)
+        return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+    if (BS == 3 && nsrc == 4)
+        return launch_edges_s<3, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+    if (BS == 4 && nsrc == 4)
+        return launch_edges_s<4, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nbb

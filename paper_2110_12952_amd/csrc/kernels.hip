@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 
 #include "device_common.hpp"
+#include "edges_launch.hpp"
 #include "tiled_launch.hpp"
 
 namespace nbb {
@@ -1116,6 +1117,24 @@ static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, cons
         return edge ? launch_tiled_inst<BATCH, 256, true>(P, T, in, out, rule, rec, cu_count, st)
                     : launch_tiled_inst<BATCH, 256, false>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
+}
+// Resident work-groups per CU of the edge-record step (0: as many as fit).
+static constexpr int kEdgesMaxPerCU = 0;
+hipError_t launch_step_edges(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
+                             uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+    const bool edge = (rule >> 31) != 0;
+    const int kind = edges_rule_kind(rule);
+    const int mx = kEdgesMaxPerCU;
+#define NBB_EDGES_GO(B)                                                                                  \
+    do {                                                                                                  \
+        if (edge) return launch_edges_inst<B, true, 1>(E, BS, nsrc, in, out, rule, rec, cu_count, mx, st); \
+        if (kind == 0) return launch_edges_inst<B, false, 0>(E, BS, nsrc, in, out, rule, rec, cu_count, mx, st); \
+        if (kind == 1) return launch_edges_inst<B, false, 1>(E, BS, nsrc, in, out, rule, rec, cu_count, mx, st); \
+        return launch_edges_inst<B, false, 2>(E, BS, nsrc, in, out, rule, rec, cu_count, mx, st);          \
+    } while (0)
+    if (rec) NBB_EDGES_GO(true);
+    NBB_EDGES_GO(false);
+#undef NBB_EDGES_GO
 }
 hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint8_t *in, uint8_t *out,
                              uint32_t rule, int cu_count, hipStream_t st) {

@@ -93,6 +93,35 @@ struct TileParams {
     uint32_t pack01[4], pack23[4];
 };
 
+// The edge-record form of the tiled step.  The tile is cut into the same
+// level-q blocks (side BS, CB cells, consecutive in compact order) placed on a
+// G x G grid of block slots (G = S / BS) with a ring of one slot around it for
+// the facing blocks of the eight neighbour tiles.  Each thread loads its
+// block's CB bytes into registers, unpacks them into BS row dwords (byte c of
+// row r = cell (c, r) of the block, 0 where the block has no cell) and writes
+// the block's edges as one 16-byte LDS record {top row, bottom row, left
+// column, right column} (column dword: byte r = row r).  A block's 3x3-window
+// ring is then the bottom rows of the three slots above it, the top rows of
+// the three below, and the facing columns of its left and right slots.  Rows
+// of the slot grid that no block occupies share one all-zero row.
+//
+// Loads are LW = 4 * NSRC bytes wide (NSRC = 2 for 3 x 3 blocks of at most 8
+// cells, else 4).  A block
+// whose LW bytes would run past the end of its tile ("near" the end) loads the
+// LW bytes that end with its last cell instead and shifts them down by
+// nsh = LW - CB bytes, so no load leaves the tile (tiles have K >= 2 LW cells).
+struct EdgeParams {
+    uint32_t K, CB, nblk, nhalo;
+    uint32_t ntiles;        // tiles of the launch (batch tiles for a batch)
+    uint32_t rec_bytes;     // LDS of the record grid (16 bytes per slot)
+    uint32_t nsh;           // LW - CB
+    uint32_t unpack01[4], unpack23[4];  // v_perm selectors: row r = perm(c1, c0, u01[r]) | perm(c3, c2, u23[r])
+    uint32_t pack01[4], pack23[4];      // compact dword d = perm(n1, n0, p01[d]) | perm(n3, n2, p23[d])
+    const uint32_t *blk;    // 2 per block: own slot | slot above << 16, slot below | near << 31
+    const uint32_t *halo;   // 2 per item: direction << 29 | local block, slot | near << 31
+    const uint32_t *nbr;    // 8 neighbour tiles per tile (0xFFFFFFFF = none)
+};
+
 // One instance of a batch (device table, sorted by tile0): its state starts
 // at byte 16 * base16 of the arena; its tiles are batch tiles
 // [tile0, tile0 + ntiles); nbr is its own 8-per-tile neighbour table.

@@ -456,6 +456,168 @@ bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg
     return true;
 }
 
+bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg) {
+    *p = EdgePlan();
+    if (!tiled_supported(f) || m < 1 || m > f.r) {
+        *msg = "the edge form needs a tiled fractal and 1 <= m <= r";
+        return false;
+    }
+    const uint32_t q = block_level(f, m);
+    const uint32_t BS = uint32_t(ipow64(f.s, q)), CB = uint32_t(ipow64(f.k, q));
+    const uint32_t G = uint32_t(ipow64(f.s, m - q));
+    const uint64_t nb = ipow64(f.k, m - q), K = ipow64(f.k, m);
+    // two source dwords for 3 x 3 blocks of up to 8 cells, else four
+    const uint32_t nsrc = (BS == 3 && CB <= 8) ? 2 : 4, LW = 4 * nsrc;
+    if (BS < 3 || CB > 16) {
+        *msg = "the edge form needs blocks of side 3 or 4";
+        return false;
+    }
+    if (K < 2 * LW) {
+        *msg = "tile too small for the edge form";
+        return false;
+    }
+    if (nb > 1024) {
+        *msg = "more than 1024 blocks per tile";
+        return false;
+    }
+    p->m = m;
+    p->q = q;
+    p->S = uint32_t(ipow64(f.s, m));
+    p->K = uint32_t(K);
+    p->BS = BS;
+    p->CB = CB;
+    p->G = G;
+    p->nblk = uint32_t(nb);
+    p->nsrc = nsrc;
+    p->nsh = LW - CB;
+    // block slots: block b of the tile sits at lambda_{m-q}(b) on the G x G grid
+    const int64_t Gi = G;
+    std::vector<int32_t> own(size_t(G + 2) * (G + 2), -1);  // (Y+1)*(G+2) + X+1 -> block
+    auto at = [&](int64_t X, int64_t Y) -> int32_t & { return own[size_t(Y + 1) * (G + 2) + size_t(X + 1)]; };
+    p->blk_xy.resize(2 * nb);
+    for (uint64_t b = 0; b < nb; ++b) {
+        int64_t X, Y;
+        lambda_levels(f, m - q, b, &X, &Y);
+        p->blk_xy[2 * b] = int32_t(X);
+        p->blk_xy[2 * b + 1] = int32_t(Y);
+        at(X, Y) = int32_t(b);
+    }
+    // halo items: blocks of the eight neighbour tiles that land on the ring
+    // next to one of the tile's blocks; direction numbering as the neighbour
+    // table (row-major over dy, dx in -1..1 without the centre)
+    auto touches = [&](int64_t X, int64_t Y) {
+        for (int64_t dy = -1; dy <= 1; ++dy)
+            for (int64_t dx = -1; dx <= 1; ++dx) {
+                const int64_t x = X + dx, y = Y + dy;
+                if (x >= 0 && y >= 0 && x < Gi && y < Gi && at(x, y) >= 0) return true;
+            }
+        return false;
+    };
+    std::vector<uint32_t> hd, hs;
+    uint32_t dir8 = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            for (uint64_t b = 0; b < nb; ++b) {
+                const int64_t X = p->blk_xy[2 * b] + dx * Gi, Y = p->blk_xy[2 * b + 1] + dy * Gi;
+                if (X < -1 || Y < -1 || X > Gi || Y > Gi || !touches(X, Y)) continue;
+                p->halo_xy.push_back(int32_t(X));
+                p->halo_xy.push_back(int32_t(Y));
+                hd.push_back((dir8 << 29) | uint32_t(b));
+            }
+            ++dir8;
+        }
+    p->nhalo = uint32_t(hd.size());
+    if (p->nhalo > 512) {
+        *msg = "more than 512 halo blocks per tile";
+        return false;
+    }
+    // slot-grid rows: rows holding a block or a halo item, in order; rows
+    // that are only read share one zero row
+    std::vector<int32_t> row_of(G + 2, -1);  // index Y + 1
+    for (uint64_t b = 0; b < nb; ++b) row_of[p->blk_xy[2 * b + 1] + 1] = 0;
+    for (uint32_t h = 0; h < p->nhalo; ++h) row_of[p->halo_xy[2 * h + 1] + 1] = 0;
+    uint32_t rows = 0;
+    for (auto &v : row_of)
+        if (v == 0) v = int32_t(rows++);
+    bool zero_row = false;
+    for (uint64_t b = 0; b < nb; ++b)
+        for (int dy = -1; dy <= 1; dy += 2)
+            if (row_of[p->blk_xy[2 * b + 1] + dy + 1] < 0) zero_row = true;
+    const uint32_t zrow = rows;
+    if (zero_row) ++rows;
+    p->grid_w = G + 2;
+    p->grid_rows = rows;
+    const uint64_t slots = uint64_t(rows) * p->grid_w;
+    if (slots * 16 > 65536) {
+        *msg = "record grid beyond 64 KiB";
+        return false;
+    }
+    p->rec_bytes = uint32_t(slots * 16);
+    auto slot = [&](int64_t X, int64_t Y) -> uint32_t {
+        const int32_t r = row_of[Y + 1];
+        return uint32_t(r < 0 ? zrow : uint32_t(r)) * p->grid_w + uint32_t(X + 1);
+    };
+    p->blk.resize(2 * nb);
+    for (uint64_t b = 0; b < nb; ++b) {
+        const int64_t X = p->blk_xy[2 * b], Y = p->blk_xy[2 * b + 1];
+        const uint32_t near = b * CB + LW > K ? 1u : 0u;
+        p->blk[2 * b] = slot(X, Y) | (slot(X, Y - 1) << 16);
+        p->blk[2 * b + 1] = slot(X, Y + 1) | (near << 31);
+    }
+    p->halo.resize(2 * size_t(p->nhalo));
+    for (uint32_t h = 0; h < p->nhalo; ++h) {
+        const uint32_t lb = hd[h] & 0x1FFFFFFFu;
+        const uint32_t near = uint64_t(lb) * CB + LW > K ? 1u : 0u;
+        p->halo[2 * h] = hd[h];
+        p->halo[2 * h + 1] = slot(p->halo_xy[2 * h], p->halo_xy[2 * h + 1]) | (near << 31);
+    }
+    // v_perm selectors: byte c of row r is cell bid(c, r) of the block's CB
+    // bytes (dwords c0..c3), 12 (a zero byte) where the block has no cell
+    uint8_t bid[16];
+    std::memset(bid, 0xFF, sizeof(bid));
+    for (uint32_t rr = 0; rr < BS; ++rr)
+        for (uint32_t c = 0; c < BS; ++c) {
+            const int64_t v = nu_levels(f, q, c, rr);
+            if (v >= 0) bid[c + BS * rr] = uint8_t(v);
+        }
+    for (uint32_t rr = 0; rr < 4; ++rr) {
+        uint32_t sa = 0, sb = 0;
+        for (uint32_t c = 0; c < 4; ++c) {
+            uint32_t a = 12, b = 12;
+            const uint32_t j = (rr < BS && c < BS) ? bid[c + BS * rr] : 0xFFu;
+            if (j != 0xFFu) {
+                if (j < 8) a = j;
+                else b = j - 8;
+            }
+            sa |= a << (8 * c);
+            sb |= b << (8 * c);
+        }
+        p->unpack01[rr] = sa;
+        p->unpack23[rr] = sb;
+    }
+    // compact dword d of the next states from rows (n0, n1) and (n2, n3)
+    for (uint32_t d = 0; d < 4; ++d) {
+        uint32_t s01 = 0, s23 = 0;
+        for (uint32_t b = 0; b < 4; ++b) {
+            uint32_t a = 12, h = 12;
+            const uint32_t j = 4 * d + b;
+            for (uint32_t pos = 0; pos < BS * BS; ++pos)
+                if (bid[pos] == j) {
+                    const uint32_t c = pos % BS, r = pos / BS;
+                    if (r < 2) a = r * 4 + c;
+                    else h = (r - 2) * 4 + c;
+                }
+            s01 |= a << (8 * b);
+            s23 |= h << (8 * b);
+        }
+        p->pack01[d] = s01;
+        p->pack23[d] = s23;
+    }
+    p->ok = true;
+    return true;
+}
+
 void build_mfma_tables(const Fractal &f, MfmaTables *t) {
     *t = MfmaTables();
     const uint64_t K = uint64_t(f.r) * f.k;

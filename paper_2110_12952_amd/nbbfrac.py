@@ -26,7 +26,7 @@ NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
 NBB_RULE_VON_NEUMANN = 1 << 31
 NBB_BATCH_NO_RESIDENT = 1  # nbb_batch_create_ex: small instances stepped by the group launches too
 NBB_BATCH_RESIDENT = 2     # nbb_batch_create_ex: every small instance stepped in LDS
-STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE = 0, 1, 2, 3
+STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE, STRATEGY_TILED_BOX = 0, 1, 2, 3, 4
 MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 
 
@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
                 ("tile_side", ctypes.c_uint32), ("halo_cells", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("bbox_pitch", ctypes.c_uint64),
                 ("device_table_bytes", ctypes.c_uint64), ("box_low_side", ctypes.c_uint32),
-                ("box_high_side", ctypes.c_uint32)]
+                ("box_high_side", ctypes.c_uint32), ("tiled_form", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32)]
 
 
 class PlanView(ctypes.Structure):
@@ -58,7 +59,12 @@ class PlanView(ctypes.Structure):
                 ("tiles", ctypes.c_uint64),
                 ("lut0", ctypes.POINTER(ctypes.c_uint16)), ("lut1", ctypes.POINTER(ctypes.c_uint16)),
                 ("halo_src", ctypes.POINTER(ctypes.c_uint32)), ("halo_dst", ctypes.POINTER(ctypes.c_uint32)),
-                ("nbr", ctypes.POINTER(ctypes.c_uint32))]
+                ("nbr", ctypes.POINTER(ctypes.c_uint32)),
+                ("edge_ok", ctypes.c_uint32), ("edge_grid", ctypes.c_uint32), ("edge_rows", ctypes.c_uint32),
+                ("edge_rec_bytes", ctypes.c_uint32), ("edge_halo_count", ctypes.c_uint32),
+                ("edge_nsrc", ctypes.c_uint32), ("edge_nsh", ctypes.c_uint32),
+                ("edge_unpack", ctypes.c_uint32 * 8), ("edge_pack", ctypes.c_uint32 * 8),
+                ("edge_blk", ctypes.POINTER(ctypes.c_uint32)), ("edge_halo", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class BatchInfo(ctypes.Structure):
@@ -188,6 +194,15 @@ def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: 
         out["halo_dst"] = np.ctypeslib.as_array(v.halo_dst, (v.halo_count,)).copy() if v.halo_count else \
             np.zeros(0, np.uint32)
         out["nbr"] = np.ctypeslib.as_array(v.nbr, (int(v.tiles) * 8,)).copy()
+        out["edge_ok"] = bool(v.edge_ok)
+        if v.edge_ok:
+            for f in ("edge_grid", "edge_rows", "edge_rec_bytes", "edge_halo_count", "edge_nsrc", "edge_nsh"):
+                out[f] = getattr(v, f)
+            out["edge_unpack"] = np.array(list(v.edge_unpack), np.uint32)
+            out["edge_pack"] = np.array(list(v.edge_pack), np.uint32)
+            out["edge_blk"] = np.ctypeslib.as_array(v.edge_blk, (2 * v.blocks,)).copy()
+            out["edge_halo"] = np.ctypeslib.as_array(v.edge_halo, (2 * v.edge_halo_count,)).copy() \
+                if v.edge_halo_count else np.zeros(0, np.uint32)
         return out
     finally:
         lib().nbb_plan_free(h)

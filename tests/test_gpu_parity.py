@@ -212,8 +212,9 @@ def tile_levels(fd, r):
             nbbfrac.plan_tables(fd.s, fd.offsets, r, m)
         except nbbfrac.NbbError:
             continue
-        out.append(("tiled", m))
-        out.append(("wave", m))  # one wavefront per tile, where the tile fits one
+        out.append(("tiled", m))  # edge records where the level allows them
+        out.append(("box", m))    # byte scatter
+        out.append(("wave", m))   # one wavefront per tile, where the tile fits one
     out.append(("direct", 0))
     return out
 
@@ -225,6 +226,10 @@ def configure(N, g, how):
         g.configure(N.STRATEGY_AUTO, 0)
     elif kind == "tiled":
         g.configure(N.STRATEGY_TILED, m)
+        assert g.info().tiled_form in (1, 2)
+    elif kind == "box":
+        g.configure(N.STRATEGY_TILED_BOX, m)
+        assert g.info().strategy == N.STRATEGY_TILED and g.info().tiled_form == 2
     elif kind == "wave":
         try:
             g.configure(N.STRATEGY_TILED_WAVE, m)
@@ -481,6 +486,40 @@ def test_small_triangle_workload(N):
         box = g.init_bbox(seed, w.p)
         resb = g.step_bbox(box, torch.empty_like(box), w.steps)
         np.testing.assert_array_equal(host(g.gather(resb)), host(res))
+
+
+def test_workloads_run_in_edge_form(N):
+    # the automatic plans of the workloads take the edge-record form, and the
+    # byte-scatter form can be asked for at the same level
+    for name, r in [("triangle", 16), ("carpet", 9), ("hfractal", 10), ("chandelier", 11), ("triangle", 10)]:
+        fd, o, g = pair(name, r, N)
+        inf = g.info()
+        assert inf.strategy == N.STRATEGY_TILED and inf.tiled_form == 1, name
+        g.configure(N.STRATEGY_TILED_BOX, inf.tile_level)
+        assert g.info().tiled_form == 2 and g.info().tile_level == inf.tile_level
+        g.configure(N.STRATEGY_TILED, inf.tile_level)
+        assert g.info().tiled_form == 1
+
+
+@pytest.mark.parametrize("name,r,m", [("triangle", 9, 7), ("triangle", 12, 6), ("carpet", 5, 3), ("carpet", 6, 4),
+                                      ("hfractal", 6, 3), ("hfractal", 6, 4), ("chandelier", 9, 4),
+                                      ("chandelier", 10, 5), ("grid4_12", 4, 3), ("fullsquare", 7, 5),
+                                      ("xfractal", 6, 4), ("cantordust", 7, 4)])
+def test_edge_form_against_oracle(N, name, r, m):
+    # the edge-record form at levels with several tiles, near-end blocks and
+    # shared zero rows, over every rule form (B3/S23, tables, bit extract,
+    # four-cell), against the oracle and against the byte-scatter form
+    fd, o, g = pair(name, r, N)
+    g.configure(N.STRATEGY_TILED, m)
+    assert g.info().tiled_form == 1
+    st0 = o.init_compact(808 + r, 0.45)
+    for rule in RULES:
+        rm = W.rule_mask(rule)
+        for steps in (1, 3):
+            a = dev(st0)
+            res = g.step_compact(a, torch.full_like(a, 0xEE), steps, rm)
+            np.testing.assert_array_equal(host(res), o.compact_steps(st0, rm, steps),
+                                          err_msg=f"{name} r={r} m={m} {rule} steps={steps}")
 
 
 def test_large_triangle_workload(N):
