@@ -17,9 +17,11 @@ measured) request j, with R_j generations left, finishes about R_j C / T
 from now.  A request is admitted only if
   - its state fits the arena now, and
   - with its cells added to C, every active request and itself still finish
-    within `deadline_s` of admission:  C' <= T min_j(slack_j / R_j), with
-    slack_j the time left before request j's deadline.
-A request that fails either test is rejected at once, with the reason.
+    within `deadline_s` of their arrival:  C' <= T min_j(slack_j / R_j), with
+    slack_j the time left before request j's deadline (arrival + deadline_s).
+A request that fails either test is rejected at once, with the reason; the
+latency percentiles cover completed requests only and are reported beside
+the fraction rejected.
 
 The device work goes through an executor (`DeviceExecutor`: the library's
 kernels on the current GPU); the loop itself only schedules, so another
@@ -126,8 +128,10 @@ class ServeStats:
     def summary(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
         wt = np.array(self.waits) if self.waits else np.zeros(1)
+        rejected = self.rejected_deadline + self.rejected_memory
         return {"offered": self.offered, "admitted": self.admitted, "completed": self.completed,
                 "rejected_deadline": self.rejected_deadline, "rejected_memory": self.rejected_memory,
+                "rejected_frac": rejected / max(self.offered, 1),
                 "rounds": self.rounds, "cell_updates": self.cell_updates,
                 "cell_updates_per_s": self.cell_updates / max(self.wall_seconds, 1e-9),
                 "gpu_busy_frac": self.gpu_seconds / max(self.wall_seconds, 1e-9),
@@ -152,6 +156,12 @@ class DeviceExecutor:
         self.tile_levels = dict(tile_levels or {})
         self._desc: Dict[Tuple[str, int], object] = {}
         self._ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        # the batch of the last round, reused while the next round steps the
+        # same instances in the same order (building one costs an allocation,
+        # table uploads and a synchronisation)
+        self._batch = None
+        self._batch_key = None
+        self.batches_built = 0
 
     def descriptor(self, fd, r: int):
         """One shared descriptor per (fractal, r).  Instances of a fractal named
@@ -177,13 +187,17 @@ class DeviceExecutor:
         the device time in seconds."""
         torch = self.torch
         stream = torch.cuda.current_stream()
-        batch = N.Batch(descs, offsets)
+        key = tuple((id(d), int(o)) for d, o in zip(descs, offsets))
+        if key != self._batch_key:
+            self._batch = None  # frees the old batch's tables first
+            self._batch = N.Batch(descs, offsets)
+            self._batch_key = key
+            self.batches_built += 1
         ev0, ev1 = self._ev
         ev0.record(stream)
-        batch.step_each(self.arenas[arena], self.arenas[1 - arena], steps, rule)
+        self._batch.step_each(self.arenas[arena], self.arenas[1 - arena], steps, rule)
         ev1.record(stream)
         ev1.synchronize()
-        del batch
         return ev0.elapsed_time(ev1) * 1e-3
 
     def view(self, arena: int, offset: int, cells: int):
@@ -222,7 +236,8 @@ class Server:
                 q = requests[i]
                 i += 1
                 fp = footprint + q.cells
-                tight = min(tightest, self.deadline_s / q.steps)
+                # the deadline runs from the request's arrival, not from now
+                tight = min(tightest, max(0.0, q.t + self.deadline_s - now) / q.steps)
                 if fp > self.safety * self.throughput * tight:
                     st.rejected_deadline += 1
                     continue
@@ -275,7 +290,7 @@ class Server:
                 self.cur = 1 - self.cur
             active = survivors
             footprint = sum(a.req.cells for a in active)
-            tightest = min(((a.admitted + self.deadline_s - done_t) / a.remaining for a in active),
+            tightest = min(((a.req.t + self.deadline_s - done_t) / a.remaining for a in active),
                            default=float("inf"))
             if log and st.rounds % 50 == 0:
                 log(f"serve: t={done_t:.1f}s rounds={st.rounds} active={len(active)} done={st.completed} "

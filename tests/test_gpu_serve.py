@@ -101,6 +101,9 @@ def test_serve_completes_every_admitted_request_exactly(N):
     _check_completed(results)
     s = st.summary()
     assert s["latency_p99_ms"] >= s["latency_p50_ms"] > 0
+    assert 0.0 <= s["rejected_frac"] < 0.1
+    # rounds over an unchanged set of instances reuse the previous round's batch
+    assert 0 < srv.exe.batches_built < st.rounds
     srv.alloc.check()
     assert srv.alloc.used_bytes == 0
 
