@@ -395,6 +395,30 @@ nbb_status nbb_batch_step(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64
 nbb_status nbb_batch_step_each(const nbb_batch *batch, uint8_t *a, uint8_t *b, uint64_t arena_len,
                                const uint32_t *steps, uint32_t rule, void *stream);
 
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Does what
+ * nbb_batch_create_ex(fractals, offsets, count, NBB_BATCH_NO_RESIDENT, ...),
+ * nbb_batch_step_each(..., steps, rule, stream) and nbb_batch_destroy do
+ * together, with the same arguments, checks and results, but calls no
+ * hipMalloc / hipFree and waits on nothing: the batch's tables (per instance
+ * 24 bytes, per tile 40 bytes, each group's part rounded up to 256) are
+ * rebuilt at every call, by kernels enqueued on `stream`, inside a static
+ * device array of the library of NBB_NOALLOC_SCRATCH_BYTES (one per device,
+ * held until the process ends).  Every instance goes through the
+ * per-generation group launches (none is stepped in LDS).  NBB_E_RANGE if the
+ * tables would exceed the array (about 400,000 tiles), before anything is
+ * enqueued.  All calls on one device share the array and leave their tables
+ * in it: calls enqueued on one stream are ordered and safe; calls that overlap
+ * on one device (other streams, other host threads without an event between
+ * them) race and give undefined results.  The descriptors must not be
+ * reconfigured while their work is enqueued.
+ */
+#define NBB_NOALLOC_SCRATCH_BYTES (16u << 20)
+nbb_status nbb_batch_step_each_noalloc(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                                       uint8_t *a, uint8_t *b, uint64_t arena_len, const uint32_t *steps,
+                                       uint32_t rule, void *stream);
+
 /* Smallest box pitch for this descriptor: n rounded up to a multiple of 16. */
 uint64_t nbb_bbox_pitch(const nbb_fractal *f);
 

@@ -748,8 +748,13 @@ static void batch_free(nbb_batch *B) {
     delete B;
 }
 
-nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
-                               uint32_t flags, void *stream, nbb_batch **out) {
+// Builds a batch.  Its device tables go to one fresh allocation, or, when
+// `fixed` is given, to those `fixed_cap` bytes (no allocation: the instance
+// tables are written by kernels whose arguments carry them, nothing waits on
+// the stream, and no instance is stepped in LDS, since those plans are built
+// on the device on first use).
+static nbb_status batch_create(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                               uint32_t flags, void *stream, uint8_t *fixed, size_t fixed_cap, nbb_batch **out) {
     if (!out) return fail(NBB_E_INVALID, "out is NULL");
     *out = nullptr;
     if (count && (!fractals || !offsets)) return fail(NBB_E_INVALID, "null argument");
@@ -893,7 +898,12 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
     total += nres ? align256(nres * sizeof(ResidentInstance)) : 0;
     const size_t off_rsteps = total;
     total += nres ? align256(nres * sizeof(uint32_t)) : 0;
-    if (total) {
+    if (fixed && total > fixed_cap) {
+        delete B;
+        return fail(NBB_E_RANGE, "batch tables (" + std::to_string(total) + " bytes) exceed the " +
+                                     std::to_string(fixed_cap) + "-byte no-allocation scratch");
+    }
+    if (total && !fixed) {
         e = hipMalloc(&B->dtab.ptr, total);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -904,14 +914,21 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
         B->dtab.bytes = total;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    char *base = static_cast<char *>(B->dtab.ptr);
+    char *base = fixed ? reinterpret_cast<char *>(fixed) : static_cast<char *>(B->dtab.ptr);
     for (size_t g = 0; g < ng; ++g) {
         auto *inst = reinterpret_cast<BatchInstance *>(base + off_inst[g]);
         auto *rec = reinterpret_cast<uint32_t *>(base + off_rec[g]);
         auto *nbr = reinterpret_cast<uint32_t *>(base + off_nbr[g]);
-        e = hipMemcpyAsync(inst, launch.members[g].data(), launch.members[g].size() * sizeof(BatchInstance),
-                           hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table goes out of scope
+        static_assert(sizeof(BatchInstance) % 4 == 0, "instance records upload as words");
+        if (fixed) {
+            e = launch_set_words(reinterpret_cast<uint32_t *>(inst),
+                                 reinterpret_cast<const uint32_t *>(launch.members[g].data()),
+                                 uint32_t(launch.members[g].size() * sizeof(BatchInstance) / 4), s);
+        } else {
+            e = hipMemcpyAsync(inst, launch.members[g].data(), launch.members[g].size() * sizeof(BatchInstance),
+                               hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table goes out of scope
+        }
         if (e == hipSuccess)
             e = launch_batch_tiles(inst, uint32_t(launch.members[g].size()), uint32_t(ntiles[g]), rec, nbr, s);
         if (e != hipSuccess) {
@@ -992,6 +1009,11 @@ nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_
     }
     *out = B;
     return NBB_OK;
+}
+
+nbb_status nbb_batch_create_ex(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                               uint32_t flags, void *stream, nbb_batch **out) {
+    return batch_create(fractals, offsets, count, flags, stream, nullptr, 0, out);
 }
 
 void nbb_batch_destroy(nbb_batch *B) {
@@ -1147,6 +1169,62 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     e = batch_join_resident(B, s, res_launched);
     if (e != hipSuccess) return hip_fail(e, "batch resident join");
     return NBB_OK;
+}
+
+// ---- the batched step without allocation ---------------------------------
+// The batch tables of nbb_batch_step_each_noalloc live in this array, one
+// copy per device (it is a device variable), held until the process ends.
+// Host code never passes the array's name to a kernel or a copy: on the host
+// it is only a stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) uint8_t scratch[NBB_NOALLOC_SCRATCH_BYTES];
+
+static nbb_status scratch_address(int dev, uint8_t **out) {
+    static std::mutex mu;
+    static std::vector<uint8_t *> addr;  // per device, null until looked up
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr.size() <= size_t(dev)) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        }
+        addr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = addr[dev];
+    return NBB_OK;
+}
+
+nbb_status nbb_batch_step_each_noalloc(const nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count,
+                                       uint8_t *a, uint8_t *b, uint64_t arena_len, const uint32_t *steps,
+                                       uint32_t rule, void *stream) {
+    // the arena checks of nbb_batch_step_each, before any table is enqueued
+    if (count && (!fractals || !offsets || !steps || !a || !b)) return fail(NBB_E_INVALID, "null argument");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
+    if (count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!fractals[i]) return fail(NBB_E_INVALID, "null descriptor in the batch");
+        const uint64_t end = offsets[i] + fractals[i]->f.cells;  // offsets < 2^36 are checked below
+        if (offsets[i] >= (uint64_t(1) << 36) || ((end + 15) & ~uint64_t(15)) > arena_len)
+            return offsets[i] >= (uint64_t(1) << 36) ? fail(NBB_E_RANGE, "instance offset beyond 2^36")
+                                                     : fail(NBB_E_INVALID, "arena shorter than the batch needs");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    uint8_t *tables = nullptr;
+    nbb_status st = scratch_address(dev, &tables);
+    if (st != NBB_OK) return st;
+    nbb_batch *B = nullptr;
+    st = batch_create(fractals, offsets, count, NBB_BATCH_NO_RESIDENT, stream, tables, NBB_NOALLOC_SCRATCH_BYTES,
+                      &B);
+    if (st != NBB_OK) return st;
+    st = nbb_batch_step_each(B, a, b, arena_len, steps, rule, stream);
+    batch_free(B);  // host bookkeeping only: B owns no device memory
+    return st;
 }
 
 uint64_t nbb_bbox_pitch(const nbb_fractal *F) { return F ? box_pitch(F->f) : 0; }

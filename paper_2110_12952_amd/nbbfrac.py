@@ -147,6 +147,8 @@ def lib() -> ctypes.CDLL:
     L.nbb_batch_step.restype = st
     L.nbb_batch_step_each.argtypes = [vp, vp, vp, u64, vp, u32, vp]
     L.nbb_batch_step_each.restype = st
+    L.nbb_batch_step_each_noalloc.argtypes = [vp, vp, u32, vp, vp, u64, vp, u32, vp]
+    L.nbb_batch_step_each_noalloc.restype = st
     L.nbb_bbox_pitch.argtypes = [vp]
     L.nbb_bbox_pitch.restype = u64
     L.nbb_last_error.restype = ctypes.c_char_p
@@ -428,6 +430,27 @@ def pack_offsets(cells: Sequence[int]) -> Tuple[list, int]:
         offs.append(o)
         o += (int(c) + 15) & ~15
     return offs, max(o, 16)
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20  # NBB_NOALLOC_SCRATCH_BYTES
+
+
+def batch_step_each_noalloc(fractals: Sequence["Fractal"], offsets: Sequence[int], a, b, steps: Sequence[int],
+                            rule: int = NBB_RULE_B3S23, stream=None) -> None:
+    """nbb_batch_step_each_noalloc: instance i (fractals[i], state at byte
+    offsets[i] of both arenas) takes steps[i] generations, its result in b
+    iff steps[i] is odd; the batch tables live in the library's static device
+    array, so the call allocates no device memory."""
+    if a.numel() != b.numel():
+        raise ValueError("arenas differ in length")
+    n = len(fractals)
+    if len(offsets) != n or len(steps) != n:
+        raise ValueError(f"expected {n} offsets and step counts")
+    hs = (ctypes.c_void_p * max(n, 1))(*[f._h.value for f in fractals])
+    offs = (ctypes.c_uint64 * max(n, 1))(*[int(o) for o in offsets])
+    arr = np.ascontiguousarray(steps, dtype=np.uint32) if n else np.zeros(1, np.uint32)
+    _check(lib().nbb_batch_step_each_noalloc(hs, offs, n, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(),
+                                             arr.ctypes.data, int(rule), _stream(stream)))
 
 
 class Batch:
