@@ -28,7 +28,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 STRATEGY_NAMES = {1: "tiled", 2: "direct", 3: "tiled_wave"}
 COUNTERS = os.path.join(ROOT, "profiles", "compact_step_triangle_r16_counters.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_12952_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2110_12952_amd", "csrc")
+# the device code of the step kernels: a counter summary taken on other sources is stale
+KERNEL_SOURCES = ("kernels.hip", "device_common.hpp", "params.hpp", "edges.hpp", "edges_inst.hip", "tiled.hpp",
+                  "tiled_inst.hip")
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -59,8 +69,7 @@ def measured_traffic(per_launch_alg_bytes):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
-    if vals.get("kernel_source_sha256_16") != src_hash:
+    if vals.get("kernel_sources_sha256_16") != kernel_sources_hash():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -307,6 +316,8 @@ def main():
                     help="generations of each HBM-sized workload (carpet r9, H r10); 0 skips them")
     ap.add_argument("--serve-deadline", type=float, default=0.5,
                     help="admission: predicted drain time limit, seconds")
+    ap.add_argument("--packed", action="store_true",
+                    help="also time the bit-packed state (a capacity form: 8x smaller state, slower step)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -384,9 +395,10 @@ def main():
         log(f"byte-scatter form: {box_form['us_per_step']:.2f} us/step, same: {box_form['equals_edge_form']}")
         del fa, fb, resf, refe
 
-    # ---- the same generations on the bit-packed state (1 bit per cell) -----
+    # ---- the same generations on the bit-packed state (1 bit per cell; a
+    # capacity form, slower than the byte step, timed only when asked for) --
     packed = None
-    if info.strategy != N.STRATEGY_DIRECT:
+    if args.packed and info.strategy != N.STRATEGY_DIRECT:
         Kp = min(K, 200)
         pa = g.pack(init)
         pb = torch.zeros_like(pa)
@@ -523,7 +535,8 @@ def main():
                    "tile_level": info.tile_level},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_step_direct" if info.strategy == N.STRATEGY_DIRECT else "k_step_tiled",
+                     "kernel": ("k_step_direct" if info.strategy == N.STRATEGY_DIRECT else
+                                "k_step_edges" if info.tiled_form == 1 else "k_step_tiled"),
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "compact_repeats": repeats,

@@ -19,7 +19,8 @@ def test_bench_prints_one_complete_json_line():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "1", "--bbox-steps", "5",
            "--map-reps", "1", "--cpu-seconds", "0.1", "--no-cpu-one-thread", "--repeats", "2",
-           "--batch-steps", "3", "--batch-seq-steps", "1", "--serve-seconds", "0", "--large-steps", "3"]
+           "--batch-steps", "3", "--batch-seq-steps", "1", "--serve-seconds", "0", "--large-steps", "3",
+           "--packed"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
