@@ -26,7 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
-STRATEGY_NAMES = {1: "tiled", 2: "direct", 3: "tiled_wave"}
+STRATEGY_NAMES = {1: "tiled", 2: "direct", 3: "tiled_wave", 5: "temporal"}
+FORM_NAMES = {0: None, 1: "edge_records", 2: "byte_scatter", 3: "temporal"}
 COUNTERS = os.path.join(ROOT, "profiles", "compact_step_triangle_r16_counters.txt")
 CSRC = os.path.join(ROOT, "paper_2110_12952_amd", "csrc")
 # the device code of the step kernels: a counter summary taken on other sources is stale
@@ -137,6 +138,16 @@ def small_case(torch, N, W, rule):
     a.copy_(a0)
     ms_graph, _ = time_events(torch, graph.replay)
     same = bool(torch.equal(gres, eager))
+    # several generations per launch (temporal blocking), automatic plan
+    gt = N.Fractal(fd.s, fd.offsets, wl.r)
+    gt.configure_temporal(0, 0)
+    tinf = gt.info()
+    ta, tb = a0.clone(), torch.empty_like(a0)
+    gt.step_compact(ta.clone(), tb, 2, rule)
+    ms_temp, tres = time_events(torch, lambda: gt.step_compact(ta, tb, T, rule))
+    temporal = {"us_per_step": ms_temp / T * 1e3, "tile_level": int(tinf.tile_level),
+                "depth": int(tinf.temporal_depth), "launches": -(-T // int(tinf.temporal_depth)),
+                "equals_tiled": bool(torch.equal(tres, eager))}
     # the initial-state kernel on the large triangle (1 byte written per cell)
     big = W.LARGE_TRIANGLE
     gb = N.Fractal(big.fractal.s, big.fractal.offsets, big.r)
@@ -144,11 +155,13 @@ def small_case(torch, N, W, rule):
     gb.init_compact(big.seeds[0], big.p, out=st)
     ms_init, _ = time_events(torch, lambda: gb.init_compact(big.seeds[0], big.p, out=st), 10)
     out = {"cells": g.cells, "steps": T, "eager_us_per_step": ms_eager / T * 1e3,
-           "graph_us_per_step": ms_graph / T * 1e3, "graph_equals_eager": same,
+           "graph_us_per_step": ms_graph / T * 1e3, "graph_equals_eager": same, "temporal": temporal,
            "init_triangle_r16_us": ms_init / 10 * 1e3,
            "init_triangle_r16_gbps": gb.cells / (ms_init / 10 * 1e-3) / 1e9}
     log(f"small triangle r10: eager {out['eager_us_per_step']:.2f} us/step, graph "
-        f"{out['graph_us_per_step']:.2f} us/step, same={same}; init r16 {out['init_triangle_r16_us']:.1f} us")
+        f"{out['graph_us_per_step']:.2f} us/step, same={same}; temporal (m={temporal['tile_level']}, "
+        f"h={temporal['depth']}) {temporal['us_per_step']:.2f} us/step, same={temporal['equals_tiled']}; "
+        f"init r16 {out['init_triangle_r16_us']:.1f} us")
     return out
 
 
@@ -163,8 +176,26 @@ def batch_run(torch, N, W, args):
     inf = batch.info()
     rule = W.rule_mask(bw.rule)
     a, b = batch.new_arena(), batch.new_arena()
-    for i, (it, f) in enumerate(zip(items, frs)):
-        f.init_compact(it.seed, it.p, out=batch.state(a, i))
+
+    def init_states(bt):
+        for i, (it, f) in enumerate(zip(items, frs)):
+            f.init_compact(it.seed, it.p, out=bt.state(a, i))
+
+    init_states(batch)
+    tune_s = None
+    if not args.no_batch_autotune:
+        # tile plans per fractal chosen by timing them on the batch's own
+        # instances (the arenas are stepped, then initialised afresh)
+        offsets = batch.offsets
+        del batch  # rebuilt below from the retuned descriptors
+        t0 = time.perf_counter()
+        N.batch_autotune(frs, offsets, a, b, steps=args.batch_tune_steps, rule=rule, use_cache=False)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+        batch = N.Batch(frs)
+        inf = batch.info()
+        log(f"batch autotune: {tune_s:.1f} s")
+        init_states(batch)
     init = a.clone()
     Kb = args.batch_steps or bw.steps
     batch.step(a.clone(), b, 2, rule)
@@ -184,9 +215,10 @@ def batch_run(torch, N, W, args):
     ba = init.clone()
     bres = batch.step(ba, torch.empty_like(ba), Ts, rule)
     same = all(torch.equal(batch.state(bres, i), batch.state(seq_res, i)) for i in range(len(frs)))
-    levels = sorted({(it.fractal.name, f.info().tile_level, STRATEGY_NAMES[f.info().strategy])
-                     for it, f in zip(items, frs)})
+    levels = sorted({(it.fractal.name, f.info().tile_level, STRATEGY_NAMES[f.info().strategy],
+                      FORM_NAMES[f.info().tiled_form]) for it, f in zip(items, frs)})
     out = {"workload": bw.name, "instances": len(items), "cells": int(inf.cells), "groups": int(inf.groups),
+           "autotune_s": tune_s,
            "tiles": int(inf.tiles), "plans": [list(x) for x in levels], "steps": Kb, "ms_per_step": ms_step,
            "cell_updates_per_s": inf.cells * Kb / (ms * 1e-3),
            "alg_gbps": 2 * inf.cells / (ms_step * 1e-3) / 1e9,
@@ -304,6 +336,10 @@ def main():
     ap.add_argument("--batch-seq-steps", type=int, default=10,
                     help="generations of the one-launch-per-instance comparison")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="keep the batch's heuristic tile plans instead of timing the candidates")
+    ap.add_argument("--batch-tune-steps", type=int, default=10,
+                    help="generations each candidate plan of the batch autotuner is timed over")
     ap.add_argument("--no-cpu-one-thread", action="store_true",
                     help="skip the oracle's one-thread figure (one generation, ~10 s)")
     ap.add_argument("--repeats", type=int, default=10,
@@ -531,7 +567,7 @@ def main():
         "config": {"workload": wl.name, "fractal": f"F^{{{fd.k},{fd.s}}} {fd.name}", "r": wl.r, "n": g.n,
                    "cells": g.cells, "p": wl.p, "seed": wl.seeds[0], "rule": wl.rule,
                    "strategy": STRATEGY_NAMES[info.strategy],
-                   "tiled_form": {0: None, 1: "edge_records", 2: "byte_scatter"}[info.tiled_form],
+                   "tiled_form": FORM_NAMES[info.tiled_form],
                    "tile_level": info.tile_level},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

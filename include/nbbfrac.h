@@ -78,6 +78,8 @@ typedef enum {
 #define NBB_STRATEGY_DIRECT 2u /* one thread per cell: lambda, 8 x nu, rule */
 #define NBB_STRATEGY_TILED_WAVE 3u /* TILED with one wavefront per tile: for small tiles */
 #define NBB_STRATEGY_TILED_BOX 4u  /* TILED, always in the byte-scatter form (see nbb_info.tiled_form) */
+#define NBB_STRATEGY_TEMPORAL 5u   /* several generations per launch in LDS (small instances; nbb_configure_temporal) */
+#define NBB_STRATEGY_TILED_EDGE 6u /* TILED, always in the edge-record form (NBB_E_INVALID where it does not apply) */
 
 typedef struct nbb_fractal nbb_fractal;
 
@@ -86,7 +88,7 @@ typedef struct {
     uint64_t cells;        /* k^r */
     uint64_t tiles;        /* k^(r - tile_level) */
     uint32_t k, s, r;
-    uint32_t strategy;     /* NBB_STRATEGY_TILED, _TILED_WAVE or _DIRECT */
+    uint32_t strategy;     /* NBB_STRATEGY_TILED, _TILED_WAVE, _TEMPORAL or _DIRECT */
     uint32_t tile_level;   /* m: a tile is an aligned run of k^m compact cells */
     uint32_t tile_side;    /* s^m */
     uint32_t halo_cells;   /* neighbour cells staged per tile */
@@ -101,11 +103,13 @@ typedef struct {
     uint32_t box_high_side; /* NH (0 when the box is too large to exist) */
     /* How a tiled strategy runs the step: 1 = edge records (each block's
      * cells loaded into registers, only the blocks' edge rows and columns
-     * exchanged through LDS; TILED where the tile level allows it),
-     * 2 = byte scatter (the tile's cells scattered into an LDS box: TILED
-     * elsewhere, TILED_BOX, TILED_WAVE); 0 for DIRECT. */
+     * exchanged through LDS; TILED_EDGE, and TILED where the level allows
+     * the form and its blocks fill at least three quarters of the work-group
+     * passes over them), 2 = byte scatter (the tile's cells scattered into
+     * an LDS box: TILED elsewhere, TILED_BOX, TILED_WAVE); 3 = TEMPORAL;
+     * 0 for DIRECT. */
     uint32_t tiled_form;
-    uint32_t reserved0;
+    uint32_t temporal_depth; /* TEMPORAL: ring depth h = generations per launch at most; else 0 */
 } nbb_info;
 
 /*
@@ -130,8 +134,11 @@ nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
 /*
  * Choose how nbb_step_compact runs: strategy NBB_STRATEGY_* and, for TILED,
  * TILED_BOX and TILED_WAVE, the tile level m (0 = automatic; otherwise
- * 1 <= m <= r).  TILED_BOX is TILED held to the byte-scatter form (nbb_query
- * then reports strategy TILED with tiled_form 2).
+ * 1 <= m <= r).  TILED_BOX is TILED held to the byte-scatter form, TILED_EDGE
+ * TILED held to the edge-record form (nbb_query then reports strategy TILED
+ * with tiled_form 2 or 1; TILED_EDGE fails where the form does not apply:
+ * blocks of side other than 3 or 4, tiles below two loads' width, more than
+ * 1024 blocks or 512 halo blocks, a record grid beyond 64 KiB).
  * Both need 2 <= s <= 4 and r >= 1; TILED_WAVE also needs a tile small
  * enough for one wavefront (k^m + 30 <= 2048 cells, at most 256 halo cells
  * and blocks, four LDS boxes within 64 KiB).  NBB_E_INVALID when the request
@@ -142,6 +149,31 @@ nbb_status nbb_query(const nbb_fractal *f, nbb_info *info);
  * the same condition.
  */
 nbb_status nbb_configure(nbb_fractal *f, uint32_t strategy, uint32_t tile_level);
+
+/*
+ * Several generations per launch (temporal blocking over section 3's
+ * blocked approach), for instances too small to fill the GPU: work-group t
+ * holds tile t (k^m compact cells, the S x S square of one level-m copy,
+ * S = s^m) and every cell of its eight neighbour tiles within distance h
+ * (`depth`) of the square as a box of side S + 2h in LDS, applies up to h
+ * generations to the whole box there and stores the tile's own cells; a
+ * generation on the box is exact wherever its 3 x 3 neighbourhood was, so
+ * the tile stays exact for h generations.  nbb_step_compact then runs
+ * ceil(steps / h) launches (one more when needed so that the result still
+ * ends in b iff steps is odd), each of up to h generations.  tile_level and
+ * depth 0 choose automatically (h = min(16, S); the level, among those with
+ * S <= 81, with the least estimated time per generation from a launch cost
+ * per h generations, a cost per wave of tiles over the CUs and the box's
+ * cells).  The
+ * box, its copy and a member mask (3 (S+2h) ceil4(S+2h) bytes) must fit one
+ * work-group's LDS.  Needs 2 <= s <= 4; 1 <= tile_level <= r and
+ * 1 <= depth <= S when given.  NBB_E_INVALID otherwise (the descriptor keeps
+ * its plan).  nbb_query reports strategy NBB_STRATEGY_TEMPORAL, the level,
+ * tiles, ring cells (halo_cells), LDS and temporal_depth; batches step the
+ * descriptor with its tile plan as before.  Same conditions as
+ * nbb_configure for work in flight.
+ */
+nbb_status nbb_configure_temporal(nbb_fractal *f, uint32_t tile_level, uint32_t depth);
 
 /*
  * lambda (section 3): x[t], y[t] = embedded coordinate of compact index idx[t],
@@ -297,9 +329,10 @@ nbb_status nbb_gather(const nbb_fractal *f, const uint8_t *bbox, uint64_t pitch,
  * Autotuner.  The paper picks its block size per method by measurement
  * (section 4: the best rho differs between methods); this does the same for
  * the compact step.  Times `steps` generations (after one untimed one) of
- * each candidate -- TILED and TILED_WAVE at every tile level m whose tile
- * holds at least 128 cells, plus the largest level that fits, and DIRECT --
- * on the caller's
+ * each candidate -- TILED_EDGE, TILED_BOX and TILED_WAVE at every tile level
+ * m whose tile holds at least 128 cells, plus the largest level that fits;
+ * when steps > 1, TEMPORAL at its automatic plan and at every level of side
+ * <= 81 with ring depths 8 and 16; and DIRECT -- on the caller's
  * buffers a and b (their contents are overwritten: pass a copy of a
  * representative state), then configures the fastest, as nbb_configure would.
  * Waits for `stream`.  Arguments as nbb_step_compact (a and b 16-byte
@@ -396,6 +429,29 @@ nbb_status nbb_batch_step_each(const nbb_batch *batch, uint8_t *a, uint8_t *b, u
                                const uint32_t *steps, uint32_t rule, void *stream);
 
 /*
+ * Tile plans for a batch chosen by measurement (section 4 picks each
+ * method's block size by timing it).  The instances are grouped by fractal
+ * (k, s, offsets; fractals the tiled step does not support are left alone);
+ * for each group every candidate plan that all its descriptors accept - the
+ * tile levels up to the group's smallest r whose tiles hold at least 64
+ * cells (and the largest level), each in the edge-record and in the
+ * byte-scatter form - is timed on a batch of exactly the group's instances
+ * (group launches, none in LDS) for `steps` generations after one warm-up
+ * generation, and every descriptor of the group is configured to the
+ * fastest.  Results are kept for the process, keyed by device, fractal, the
+ * group's smallest and largest r and the rule's form (B3/S23, table rule,
+ * any rule), and reused without timing unless flags has NBB_TUNE_NO_CACHE.
+ * The states in a and b are stepped (their values are then unspecified);
+ * arguments as nbb_batch_step_each_noalloc.  Synchronise work that uses the
+ * descriptors before the call; it synchronises on `stream` itself.  Batches
+ * built earlier from these descriptors must be rebuilt afterwards.
+ */
+#define NBB_TUNE_NO_CACHE 1u
+nbb_status nbb_batch_autotune(nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count, uint8_t *a,
+                              uint8_t *b, uint64_t arena_len, uint32_t steps, uint32_t rule, uint32_t flags,
+                              void *stream);
+
+/*
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Does what
  * nbb_batch_create_ex(fractals, offsets, count, NBB_BATCH_NO_RESIDENT, ...),
@@ -477,6 +533,33 @@ typedef struct {
 nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r,
                           uint32_t tile_level, nbb_plan **out, nbb_plan_view *view);
 void nbb_plan_free(nbb_plan *p);
+
+/*
+ * Host-side view of the temporal plan (nbb_configure_temporal) for F^{k,s}
+ * at level r, tile level m and ring depth h (both explicit, >= 1), without a
+ * device; lds_limit bytes for the three boxes (0: 160 KiB).  Box row y,
+ * column x (pitch box_pitch bytes) is the embedded point (x - h, y - h)
+ * relative to the tile's corner.
+ *   self[j], j < tile_cells: box byte offset of local cell j
+ *   halo[2e], halo[2e+1], e < halo_count: (direction << 29) | local index of
+ *   a cell of neighbour tile `direction` (numbered as nbr below) that lies in
+ *   the box, and its box byte offset
+ *   nbr[8t + d]: neighbour tile d of tile t, d = (dy+1)*3 + (dx+1) skipping
+ *   the centre, 0xFFFFFFFF where none
+ * NBB_E_INVALID for bad arguments; free with nbb_temporal_plan_free.
+ */
+typedef struct nbb_temporal_plan nbb_temporal_plan;
+typedef struct {
+    uint32_t tile_level, tile_side, tile_cells, depth, box_side, box_pitch, lds_bytes, halo_count;
+    uint64_t tiles;
+    const uint32_t *self;
+    const uint32_t *halo;
+    const uint32_t *nbr;
+} nbb_temporal_view;
+nbb_status nbb_temporal_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, uint32_t tile_level,
+                                   uint32_t depth, uint32_t lds_limit, nbb_temporal_plan **out,
+                                   nbb_temporal_view *view);
+void nbb_temporal_plan_free(nbb_temporal_plan *p);
 
 #ifdef __cplusplus
 }

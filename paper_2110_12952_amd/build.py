@@ -26,7 +26,8 @@ NOISE = "is not a recognized feature for this target"
 
 def units():
     """(source, object name, extra flags) of every translation unit."""
-    out = [("plan.cpp", "plan.o", []), ("kernels.hip", "kernels.o", []), ("api.hip", "api.o", [])]
+    out = [("plan.cpp", "plan.o", []), ("kernels.hip", "kernels.o", []), ("api.hip", "api.o", []),
+           ("temporal.hip", "temporal.o", [])]
     for batch in (0, 1):
         for team in (64, 256):
             for edge in (0, 1):
@@ -45,7 +46,8 @@ def _run(cmd):
     return r.returncode, err
 
 
-def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
+def build(verbose: bool = False, extra=(), jobs: int = 0, out: str = LIB) -> str:
+    """Compiles every unit with `extra` flags added and links them into `out`."""
     os.makedirs(OBJDIR, exist_ok=True)
     tag = "%d" % os.getpid()
     cmds = []
@@ -69,7 +71,7 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
     if verbose:
         for e in (e for _, e in results if e.strip()):
             print(e)
-    tmp = LIB + ".tmp" + tag
+    tmp = out + ".tmp" + tag
     link = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(link), flush=True)
@@ -79,8 +81,8 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
             os.remove(o)
     if rc != 0:
         raise RuntimeError("link failed:\n" + err)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

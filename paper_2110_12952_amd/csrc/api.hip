@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -55,6 +56,11 @@ struct nbb_fractal {
     bool use_edges = false;
     DevBlob dedge;
     EdgeParams ep{};
+    // Several generations per launch (NBB_STRATEGY_TEMPORAL): the plan and
+    // its device tables; the tile plan above stays for batches.
+    TemporalPlan temporal;
+    DevBlob dtemp;
+    TemporalParams tmp{};
     int device = 0;
     int cu_count = 256;
     DevBlob dmap, dtile, dbox, dmfma;
@@ -82,6 +88,11 @@ struct nbb_plan {
     Fractal f;
     TilePlan tile;
     EdgePlan edge;
+};
+
+struct nbb_temporal_plan {
+    Fractal f;
+    TemporalPlan plan;
 };
 
 // A batch: groups of instances that share a tile plan, each stepped by one
@@ -269,6 +280,28 @@ nbb_status upload_tile(nbb_fractal *F, const TilePlan &p, DevBlob *blob, TilePar
     return NBB_OK;
 }
 
+// Uploads the temporal plan's tables (cell positions, ring items, neighbour
+// tiles) into one allocation.
+nbb_status upload_temporal(const TemporalPlan &p, DevBlob *blob, TemporalParams *T) {
+    const void *src[3] = {p.self.data(), p.halo.data(), p.nbr.data()};
+    size_t bytes[3] = {p.self.size() * 4, p.halo.size() * 4, p.nbr.size() * 4};
+    void *dst[3];
+    nbb_status s = upload(blob, src, bytes, 3, dst);
+    if (s != NBB_OK) return s;
+    *T = TemporalParams{};
+    T->K = p.K;
+    T->B = p.B;
+    T->P = p.P;
+    T->h = p.h;
+    T->box_bytes = p.box_bytes;
+    T->nhalo = uint32_t(p.halo.size() / 2);
+    T->ntiles = uint32_t(p.ntiles);
+    T->self = static_cast<const uint32_t *>(dst[0]);
+    T->halo = static_cast<const uint32_t *>(dst[1]);
+    T->nbr = static_cast<const uint32_t *>(dst[2]);
+    return NBB_OK;
+}
+
 // Uploads the edge plan's tables; the neighbour table is the tile plan's
 // (same level), already on the device at T.nbr.
 nbb_status upload_edges(const EdgePlan &p, const TileParams &T, DevBlob *blob, EdgeParams *E) {
@@ -297,7 +330,14 @@ nbb_status upload_edges(const EdgePlan &p, const TileParams &T, DevBlob *blob, E
 
 // Builds and uploads the edge plan at the tile plan's level for a TILED
 // descriptor; leaves the byte-scatter form in place where it does not apply.
-nbb_status setup_edges(nbb_fractal *F) {
+// The edge form gives each thread whole blocks, one per pass of the
+// work-group; where the blocks fill less than three quarters of the passes'
+// thread slots the byte-scatter form measured faster (H r10 at level 4, 343
+// blocks over two passes of 256 threads: 180 us per generation against 168;
+// triangle r16, 243 blocks in one pass: 26.3 against 28.5; carpet r9, 512
+// blocks in two: 60.8 against 65.2).  `force`: take the edge form wherever
+// its plan applies.
+nbb_status setup_edges(nbb_fractal *F, bool force = false) {
     blob_free(&F->dedge);
     F->use_edges = false;
     F->edge = EdgePlan();
@@ -305,6 +345,8 @@ nbb_status setup_edges(nbb_fractal *F) {
     std::string msg;
     EdgePlan p;
     if (!build_edge_plan(F->f, F->tile.m, &p, &msg)) return NBB_OK;
+    const uint32_t passes = (p.nblk + 255) / 256;
+    if (!force && 4 * p.nblk < 3 * 256 * passes) return NBB_OK;
     nbb_status st = upload_edges(p, F->tp, &F->dedge, &F->ep);
     if (st != NBB_OK) return st;
     F->edge = std::move(p);
@@ -463,6 +505,43 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
 
 void nbb_plan_free(nbb_plan *p) { delete p; }
 
+nbb_status nbb_temporal_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, uint32_t tile_level,
+                                   uint32_t depth, uint32_t lds_limit, nbb_temporal_plan **out,
+                                   nbb_temporal_view *view) {
+    if (!out || !view) return fail(NBB_E_INVALID, "null argument");
+    *out = nullptr;
+    auto *p = new (std::nothrow) nbb_temporal_plan;
+    if (!p) return fail(NBB_E_NOMEM, "host allocation failed");
+    std::string msg;
+    int v = validate_fractal(k, s, offsets, r, &p->f, &msg);
+    if (v) {
+        delete p;
+        return fail(v == 2 ? NBB_E_RANGE : NBB_E_INVALID, msg);
+    }
+    if (!build_temporal_plan(p->f, tile_level, depth, lds_limit ? lds_limit : 163840u, &p->plan, &msg)) {
+        delete p;
+        return fail(NBB_E_INVALID, msg);
+    }
+    const TemporalPlan &t = p->plan;
+    std::memset(view, 0, sizeof(*view));
+    view->tile_level = t.m;
+    view->tile_side = t.S;
+    view->tile_cells = t.K;
+    view->depth = t.h;
+    view->box_side = t.B;
+    view->box_pitch = t.P;
+    view->lds_bytes = t.lds;
+    view->halo_count = uint32_t(t.halo.size() / 2);
+    view->tiles = t.ntiles;
+    view->self = t.self.data();
+    view->halo = t.halo.data();
+    view->nbr = t.nbr.data();
+    *out = p;
+    return NBB_OK;
+}
+
+void nbb_temporal_plan_free(nbb_temporal_plan *p) { delete p; }
+
 nbb_status nbb_create(uint32_t k, uint32_t s, const int32_t *offsets, uint32_t r, nbb_fractal **out) {
     if (!out) return fail(NBB_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -515,6 +594,7 @@ void nbb_destroy(nbb_fractal *F) {
     if (!F) return;
     blob_free(&F->dres);
     blob_free(&F->dpk);
+    blob_free(&F->dtemp);
     blob_free(&F->dmap);
     blob_free(&F->dbox);
     blob_free(&F->dtile);
@@ -549,6 +629,17 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
     info->tiled_form = F->strategy == NBB_STRATEGY_DIRECT ? 0u : (F->use_edges ? 1u : 2u);
     info->box_low_side = F->box.SL;
     info->box_high_side = F->box.high.empty() ? 0 : F->box.NH;
+    if (F->strategy == NBB_STRATEGY_TEMPORAL) {
+        const TemporalPlan &t = F->temporal;
+        info->tiles = t.ntiles;
+        info->tile_level = t.m;
+        info->tile_side = t.S;
+        info->halo_cells = uint32_t(t.halo.size() / 2);
+        info->lds_bytes = t.lds;
+        info->tiled_form = 3;
+        info->temporal_depth = t.h;
+    }
+    info->device_table_bytes += F->dtemp.bytes;
     return NBB_OK;
 }
 
@@ -556,16 +647,19 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     if (!F) return fail(NBB_E_INVALID, "null descriptor");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
+    if (strategy == NBB_STRATEGY_TEMPORAL) return nbb_configure_temporal(F, tile_level, 0);
     if (strategy == NBB_STRATEGY_AUTO) strategy = tiled_supported(F->f) ? NBB_STRATEGY_TILED : NBB_STRATEGY_DIRECT;
     if (strategy == NBB_STRATEGY_DIRECT) {
         if (tile_level != 0) return fail(NBB_E_INVALID, "the direct strategy takes no tile level");
         F->strategy = NBB_STRATEGY_DIRECT;
+        blob_free(&F->dtemp);
+        F->temporal = TemporalPlan();
         blob_free(&F->dedge);
         F->use_edges = false;
         return NBB_OK;
     }
     if (strategy != NBB_STRATEGY_TILED && strategy != NBB_STRATEGY_TILED_WAVE &&
-        strategy != NBB_STRATEGY_TILED_BOX)
+        strategy != NBB_STRATEGY_TILED_BOX && strategy != NBB_STRATEGY_TILED_EDGE)
         return fail(NBB_E_INVALID, "unknown strategy");
     const uint32_t team = strategy == NBB_STRATEGY_TILED_WAVE ? 64u : 256u;
     std::string msg;
@@ -573,6 +667,11 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     uint32_t m = tile_level ? tile_level : auto_tile_level(F->f);
     if (!tiled_supported(F->f) || !build_tile_plan(F->f, m, &plan, &msg, team))
         return fail(NBB_E_INVALID, msg.empty() ? "the tiled step does not support this fractal" : msg);
+    if (strategy == NBB_STRATEGY_TILED_EDGE) {
+        EdgePlan probe;
+        if (!build_edge_plan(F->f, m, &probe, &msg))
+            return fail(NBB_E_INVALID, "the edge-record form does not apply: " + msg);
+    }
     DevBlob blob;
     TileParams T;
     st = upload_tile(F, plan, &blob, &T);
@@ -581,14 +680,82 @@ nbb_status nbb_configure(nbb_fractal *F, uint32_t strategy, uint32_t tile_level)
     F->dtile = blob;
     F->tile = std::move(plan);
     F->tp = T;
-    F->strategy = strategy == NBB_STRATEGY_TILED_BOX ? NBB_STRATEGY_TILED : strategy;
+    F->strategy = (strategy == NBB_STRATEGY_TILED_BOX || strategy == NBB_STRATEGY_TILED_EDGE) ? NBB_STRATEGY_TILED
+                                                                                                 : strategy;
+    blob_free(&F->dtemp);
+    F->temporal = TemporalPlan();
     if (strategy == NBB_STRATEGY_TILED_BOX) {
         blob_free(&F->dedge);
         F->use_edges = false;
         F->edge = EdgePlan();
         return NBB_OK;
     }
-    return setup_edges(F);
+    return setup_edges(F, strategy == NBB_STRATEGY_TILED_EDGE);
+}
+
+// Most LDS one work-group may take on the current device.
+static uint32_t device_lds_per_group();
+
+// Automatic temporal plan: over the tile levels of side S <= 81 with ring
+// depth h = min(16, S), the one with the least estimated time per generation
+//   (3 + w) / h + 1e-4 (S + 2h)^2 w  microseconds,  w = max(tiles, CUs) / CUs:
+// a launch (about 3 us) and each wave of tiles over the CUs (about 1 us of
+// loads, stores and scheduling) per h generations, plus the box's cells per
+// generation.  Fitted to measurements (256 CUs, per generation, B3/S23):
+// the triangle r = 10 takes 3.7 us per generation in the tiled step and
+// 1.18 / 1.14 / 1.73 / 3.6 us at levels 4 / 5 / 6 / 7 with h = 16, 2.19 /
+// 1.43 / 1.19 / 1.14 / 1.32 us at level 5 with h = 2 / 4 / 8 / 16 / 32; over
+// triangles r 8-13, carpets and H fractals r 4-7 and chandeliers r 6-9 the
+// estimate picks the measured best level in 14 of 18 cases (the others are
+// within 25 % of it).
+static void auto_temporal(const Fractal &f, uint32_t cu_count, uint32_t *m, uint32_t *h) {
+    const double cus = double(std::max(cu_count, 1u));
+    double best_t = -1.0;
+    uint32_t best_m = 1;
+    uint64_t S = 1;
+    for (uint32_t lv = 1; lv <= f.r; ++lv) {
+        S *= f.s;
+        if (lv > 1 && S > 81) break;
+        if (*m && lv != *m) continue;
+        const double hh = double(*h ? *h : std::min<uint64_t>(16, S));
+        double tiles = 1.0;
+        for (uint32_t i = lv; i < f.r; ++i) tiles *= f.k;
+        const double w = std::max(tiles, cus) / cus, B = double(S) + 2.0 * hh;
+        const double t = (3.0 + w) / hh + 1e-4 * B * B * w;
+        if (best_t < 0.0 || t < best_t) {
+            best_t = t;
+            best_m = lv;
+        }
+    }
+    if (!*m) *m = best_m;
+    if (!*h) {
+        uint64_t side = 1;
+        for (uint32_t i = 0; i < *m; ++i) side *= f.s;
+        *h = uint32_t(std::min<uint64_t>(16, side));
+    }
+}
+
+nbb_status nbb_configure_temporal(nbb_fractal *F, uint32_t tile_level, uint32_t depth) {
+    if (!F) return fail(NBB_E_INVALID, "null descriptor");
+    nbb_status st = check_device(F);
+    if (st != NBB_OK) return st;
+    if (!tiled_supported(F->f)) return fail(NBB_E_INVALID, "temporal blocking needs 2 <= s <= 4 and r >= 1");
+    if (tile_level > F->f.r) return fail(NBB_E_INVALID, "tile level must lie in [1, r]");
+    uint32_t m = tile_level, h = depth;
+    auto_temporal(F->f, uint32_t(F->cu_count), &m, &h);
+    std::string msg;
+    TemporalPlan plan;
+    if (!build_temporal_plan(F->f, m, h, device_lds_per_group(), &plan, &msg)) return fail(NBB_E_INVALID, msg);
+    DevBlob blob;
+    TemporalParams T;
+    st = upload_temporal(plan, &blob, &T);
+    if (st != NBB_OK) return st;
+    blob_free(&F->dtemp);
+    F->dtemp = blob;
+    F->temporal = std::move(plan);
+    F->tmp = T;
+    F->strategy = NBB_STRATEGY_TEMPORAL;
+    return NBB_OK;
 }
 
 nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, uint32_t steps, uint32_t rule,
@@ -601,9 +768,15 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
     if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
     nbb_status st = check_device(F);
     if (st != NBB_OK) return st;
-    // Candidates: (strategy, level).  Tile levels whose plan fits a
-    // work-group, keeping those with >= 128 cells per tile and the largest.
-    std::vector<std::pair<uint32_t, uint32_t>> cand;
+    // Candidates: (strategy, level, ring depth).  Tile levels whose plan
+    // fits a work-group, keeping those with >= 128 cells per tile and the
+    // largest; several generations per launch at the automatic plan and at
+    // each level of side <= 81 with depths 8 and 16 (when steps allows more
+    // than one generation per launch).
+    struct Cand {
+        uint32_t strategy, level, depth;
+    };
+    std::vector<Cand> cand;
     if (tiled_supported(F->f)) {
         std::vector<uint32_t> fit;
         for (uint32_t m = 1; m <= F->f.r; ++m) {
@@ -619,13 +792,23 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
             uint64_t K = 1;
             for (uint32_t j = 0; j < fit[i]; ++j) K *= F->f.k;
             if (K >= 128 || i + 1 == fit.size()) {
-                cand.push_back({NBB_STRATEGY_TILED, fit[i]});       // edge records where they apply
-                cand.push_back({NBB_STRATEGY_TILED_BOX, fit[i]});   // byte scatter
-                cand.push_back({NBB_STRATEGY_TILED_WAVE, fit[i]});  // skipped where it does not fit
+                cand.push_back({NBB_STRATEGY_TILED_EDGE, fit[i], 0});  // edge records (skipped where they do not apply)
+                cand.push_back({NBB_STRATEGY_TILED_BOX, fit[i], 0});   // byte scatter
+                cand.push_back({NBB_STRATEGY_TILED_WAVE, fit[i], 0});  // skipped where it does not fit
+            }
+        }
+        if (steps > 1) {
+            cand.push_back({NBB_STRATEGY_TEMPORAL, 0, 0});
+            uint64_t S = 1;
+            for (uint32_t m = 1; m <= F->f.r; ++m) {
+                S *= F->f.s;
+                if (S > 81) break;
+                for (uint32_t h : {8u, 16u})
+                    if (h <= S) cand.push_back({NBB_STRATEGY_TEMPORAL, m, h});
             }
         }
     }
-    cand.push_back({NBB_STRATEGY_DIRECT, 0});
+    cand.push_back({NBB_STRATEGY_DIRECT, 0, 0});
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -635,9 +818,13 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
         return hip_fail(e, "hipEventCreate");
     }
     float best_ms = -1.0f;
-    std::pair<uint32_t, uint32_t> best{0, 0};
+    Cand best{0, 0, 0};
+    auto apply = [&](const Cand &c) {
+        return c.strategy == NBB_STRATEGY_TEMPORAL ? nbb_configure_temporal(F, c.level, c.depth)
+                                                   : nbb_configure(F, c.strategy, c.level);
+    };
     for (const auto &c : cand) {
-        if (nbb_configure(F, c.first, c.second) != NBB_OK) continue;  // plan does not fit: skip it
+        if (apply(c) != NBB_OK) continue;  // plan does not fit: skip it
         st = nbb_step_compact(F, a, b, len, 1, rule, nullptr, stream);
         if (st == NBB_OK && (e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
         if (st == NBB_OK) st = nbb_step_compact(F, b, a, len, steps, rule, nullptr, stream);
@@ -655,7 +842,7 @@ nbb_status nbb_autotune(nbb_fractal *F, uint8_t *a, uint8_t *b, uint64_t len, ui
     (void)hipEventDestroy(e1);
     if (st != NBB_OK) return st;
     if (best_ms < 0.0f) return fail(NBB_E_INVALID, "no strategy could be configured");
-    st = nbb_configure(F, best.first, best.second);
+    st = apply(best);
     if (st == NBB_OK && info) st = nbb_query(F, info);
     return st;
 }
@@ -665,7 +852,6 @@ nbb_status nbb_batch_create(const nbb_fractal *const *fractals, const uint64_t *
     return nbb_batch_create_ex(fractals, offsets, count, 0, stream, out);
 }
 
-// Most LDS one work-group may take on the current device.
 static uint32_t device_lds_per_group() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1171,6 +1357,133 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     return NBB_OK;
 }
 
+// ---- tile plans of a batch chosen by measurement ----------------------------
+// Results kept for the process: (device, k, s, offsets, smallest and largest
+// r of the set, rule form) -> (strategy, tile level).
+static std::mutex g_tune_mu;
+static std::map<std::vector<uint32_t>, std::pair<uint32_t, uint32_t>> g_tune_cache;
+
+nbb_status nbb_batch_autotune(nbb_fractal *const *fractals, const uint64_t *offsets, uint32_t count, uint8_t *a,
+                              uint8_t *b, uint64_t arena_len, uint32_t steps, uint32_t rule, uint32_t flags,
+                              void *stream) {
+    if (count && (!fractals || !offsets || !a || !b)) return fail(NBB_E_INVALID, "null argument");
+    if (steps == 0) return fail(NBB_E_INVALID, "steps must be >= 1");
+    if (flags & ~uint32_t(NBB_TUNE_NO_CACHE)) return fail(NBB_E_INVALID, "unknown flag bits");
+    if (!aligned16(a) || !aligned16(b)) return fail(NBB_E_INVALID, "arenas must be 16-byte aligned");
+    if (count && overlap(a, b, arena_len)) return fail(NBB_E_INVALID, "arenas overlap");
+    if (rule & ~kRuleMask) return fail(NBB_E_INVALID, "rule uses bits outside 0-8, 16-24 and 31");
+    for (uint32_t i = 0; i < count; ++i)
+        if (!fractals[i]) return fail(NBB_E_INVALID, "null descriptor in the batch");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    // the sets: instances of one fractal (k, s, offsets) that the tiled step supports
+    auto same_fractal = [](const Fractal &x, const Fractal &y) {
+        if (x.k != y.k || x.s != y.s) return false;
+        for (uint32_t j = 0; j < x.k; ++j)
+            if (x.ox[j] != y.ox[j] || x.oy[j] != y.oy[j]) return false;
+        return true;
+    };
+    std::vector<std::vector<uint32_t>> sets;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!tiled_supported(fractals[i]->f)) continue;
+        size_t g = 0;
+        while (g < sets.size() && !same_fractal(fractals[sets[g][0]]->f, fractals[i]->f)) ++g;
+        if (g == sets.size()) sets.emplace_back();
+        sets[g].push_back(i);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    nbb_status st = NBB_OK;
+    for (const std::vector<uint32_t> &set : sets) {
+        std::vector<nbb_fractal *> desc;  // distinct descriptors of the set
+        uint32_t rmin = 0xFFFFFFFFu, rmax = 0;
+        for (uint32_t i : set) {
+            nbb_fractal *F = fractals[i];
+            if (std::find(desc.begin(), desc.end(), F) == desc.end()) desc.push_back(F);
+            rmin = std::min(rmin, F->f.r);
+            rmax = std::max(rmax, F->f.r);
+        }
+        const Fractal &f0 = desc[0]->f;
+        std::vector<uint32_t> key = {uint32_t(dev), f0.k, f0.s, rmin, rmax, uint32_t(edges_rule_kind(rule))};
+        for (uint32_t j = 0; j < f0.k; ++j) {
+            key.push_back(uint32_t(f0.ox[j]));
+            key.push_back(uint32_t(f0.oy[j]));
+        }
+        auto configure_all = [&](uint32_t strategy, uint32_t m) {
+            for (nbb_fractal *F : desc) {
+                nbb_status c = nbb_configure(F, strategy, m);
+                if (c != NBB_OK) return c;
+            }
+            return NBB_OK;
+        };
+        std::pair<uint32_t, uint32_t> best{0, 0};
+        bool cached = false;
+        if (!(flags & NBB_TUNE_NO_CACHE)) {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                best = it->second;
+                cached = true;
+            }
+        }
+        if (!cached) {
+            // candidates: every tile level up to the set's smallest r whose
+            // tiles hold at least 64 cells (or the largest level), in the
+            // edge-record and the byte-scatter form
+            std::vector<uint64_t> offs;
+            std::vector<const nbb_fractal *> inst;
+            for (uint32_t i : set) {
+                offs.push_back(offsets[i]);
+                inst.push_back(fractals[i]);
+            }
+            float best_ms = -1.0f;
+            uint64_t K = 1;
+            for (uint32_t m = 1; m <= rmin && st == NBB_OK; ++m) {
+                K *= f0.k;
+                if (K < 64 && m < rmin) continue;
+                for (uint32_t strategy : {NBB_STRATEGY_TILED_EDGE, NBB_STRATEGY_TILED_BOX}) {
+                    if (configure_all(strategy, m) != NBB_OK) continue;  // does not fit: skip it
+                    nbb_batch *B = nullptr;
+                    st = batch_create(inst.data(), offs.data(), uint32_t(inst.size()), NBB_BATCH_NO_RESIDENT,
+                                      stream, nullptr, 0, &B);
+                    if (st != NBB_OK) break;
+                    float ms = 0.0f;
+                    st = nbb_batch_step(B, a, b, arena_len, 1, rule, nullptr, stream);
+                    if (st == NBB_OK && (e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+                    if (st == NBB_OK) st = nbb_batch_step(B, a, b, arena_len, steps, rule, nullptr, stream);
+                    if (st == NBB_OK && (e = hipEventRecord(e1, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+                    if (st == NBB_OK && (e = hipEventSynchronize(e1)) != hipSuccess)
+                        st = hip_fail(e, "hipEventSynchronize");
+                    if (st == NBB_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+                        st = hip_fail(e, "hipEventElapsedTime");
+                    batch_free(B);
+                    if (st != NBB_OK) break;
+                    if (best_ms < 0.0f || ms < best_ms) {
+                        best_ms = ms;
+                        best = {strategy, m};
+                    }
+                }
+            }
+            if (st != NBB_OK) break;
+            if (best_ms < 0.0f) continue;  // nothing fits: the descriptors keep what they had
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune_cache[key] = best;
+        }
+        st = configure_all(best.first, best.second);
+        if (st != NBB_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 // ---- the batched step without allocation ---------------------------------
 // The batch tables of nbb_batch_step_each_noalloc live in this array, one
 // copy per device (it is a device variable), held until the process ends.
@@ -1326,7 +1639,20 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
     if (result_in_b) *result_in_b = int(steps & 1);
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *in = a, *out = b;
-    if (F->use_edges) {
+    if (F->strategy == NBB_STRATEGY_TEMPORAL) {
+        // L launches of up to h generations each; the result must end in b
+        // iff steps is odd, so L takes the parity of steps (one more launch
+        // when needed: then L < steps, so every launch still has one)
+        const uint32_t h = F->tmp.h;
+        uint32_t L = (steps + h - 1) / h;
+        if ((L & 1) != (steps & 1)) ++L;
+        for (uint32_t i = 0; i < L; ++i) {
+            const uint32_t g = steps / L + (i < steps % L ? 1u : 0u);
+            hipError_t e = launch_step_temporal(F->tmp, in, out, rule, g, s);
+            if (e != hipSuccess) return hip_fail(e, "temporal step launch");
+            std::swap(in, out);
+        }
+    } else if (F->use_edges) {
         for (uint32_t i = 0; i < steps; ++i) {
             hipError_t e = launch_step_edges(F->ep, F->edge.BS, F->edge.nsrc, in, out, rule, nullptr, F->cu_count,
                                              s);

@@ -112,6 +112,9 @@ __device__ __forceinline__ void tile_prefetch(const TileParams &T, const uint8_t
     }
 }
 
+// The B3/S23 rule word.
+constexpr uint32_t kRuleB3S23 = (1u << 3) | ((1u << 2 | 1u << 3) << 16);
+
 // The rule as two byte tables for v_perm: byte c of born (c = 0..7) is the
 // birth bit for c live neighbours, byte c of surv the survival bit; counts
 // 0-3 sit in the low dword, 4-7 in the high one.  A count of 8 selects a sign
@@ -140,13 +143,17 @@ __device__ __forceinline__ RuleTables rule_tables(uint32_t rule) {
 // up and one column left of the block, read as two dwords per row; byte c of
 // H is the 3-sum of window columns c..c+2, so H[r] + H[r+1] + H[r+2] - self
 // is the live-neighbour count of every position of block row r at once.
-//   rules without birth or survival at 8: two v_perm look up the birth and
-//   the survival byte of four positions at once and self picks between them;
-//   otherwise each byte indexes the rule word (neighbours + 16 * self).
+//   RULE 0, B3/S23: born with 3, survives with 2 or 3, i.e. alive next iff
+//   (neighbours | self) == 3, one v_perm for four positions (selector 3 picks
+//   the table's 1, every other value 0..9 a zero byte);
+//   RULE 1, rules without birth or survival at 8: two v_perm look up the
+//   birth and the survival byte of four positions at once and self picks
+//   between them;
+//   RULE 2, any rule: each byte indexes the rule word (neighbours + 16 * self).
 // ROWS < BS: only the block's first ROWS rows hold fractal cells (e.g. the
 // chandelier's 3x3 blocks, whose third row is empty), so only ROWS + 2 window
 // rows are read and ROWS rows evaluated.
-template <int BS, bool PERM, bool EDGE, int ROWS = BS>
+template <int BS, int RULE, bool EDGE, int ROWS = BS>
 __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, uint32_t base, uint32_t rule,
                                            const RuleTables &RT, uint32_t (&next)[4]) {
     const uint32_t a0 = base >> 2, sh = base & 3;
@@ -184,7 +191,9 @@ __device__ __forceinline__ void block_rows(const uint32_t *box32, uint32_t W4, u
                 (BS == 2 ? lo[rr + 1] >> 16 : alignbyte(hi[rr + 1], lo[rr + 1], 2));
         else
             n = H[rr] + H[rr + 1] + H[rr + 2] - self;
-        if (PERM) {
+        if (RULE == 0) {
+            next[rr] = __builtin_amdgcn_perm(0u, 0x01000000u, n | self);
+        } else if (RULE == 1) {
             const uint32_t born = __builtin_amdgcn_perm(RT.born_hi, RT.born_lo, n);
             const uint32_t surv = __builtin_amdgcn_perm(RT.surv_hi, RT.surv_lo, n);
             const uint32_t smask = __builtin_amdgcn_perm(0u, 0x0000FF00u, self);  // 0xFF where alive

@@ -10,8 +10,8 @@
 //   1. loads each block's CB bytes into registers (one load per block; every
 //      thread keeps its blocks for the whole launch), unpacks them into BS row
 //      dwords with v_perm (byte c of row r = cell (c, r), 0 off the fractal)
-//      and writes the block's edges as one 16-byte LDS record {top row,
-//      bottom row, left column, right column}; the blocks of the eight
+//      and writes the block's edges (top row, bottom row, left column, right
+//      column) to four per-slot LDS arrays; the blocks of the eight
 //      neighbour tiles that touch the tile's blocks do the same into the ring
 //      of the slot grid (zeros where a neighbour tile does not exist);
 //   2. reads, per block, the bottom rows of the three slots above, the top
@@ -146,17 +146,35 @@ __device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB,
     }
 }
 
+// The record grid in LDS: four dword arrays of one entry per slot (top
+// rows, bottom rows, left columns, right columns), so that the lanes of a
+// wavefront, whose slots lie close together, read distinct banks.
+struct EdgeGrid {
+    uint32_t *top, *bot, *left, *right;
+};
+__device__ __forceinline__ EdgeGrid edge_grid(uint8_t *lds, uint32_t rec_bytes) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(lds);
+    const uint32_t ns = rec_bytes >> 4;  // slots
+    return EdgeGrid{w, w + ns, w + 2 * ns, w + 3 * ns};
+}
+
+__device__ __forceinline__ void put_record(const EdgeGrid &g, uint32_t slot, const uint4 &r) {
+    g.top[slot] = r.x;
+    g.bot[slot] = r.y;
+    g.left[slot] = r.z;
+    g.right[slot] = r.w;
+}
+
 // Next states of one block, rows in next[0..BS) (byte c = column c).
-// rec32: the record grid as dwords; so / sa / sb: the slots of the block and
-// of the blocks above and below it.
+// so / sa / sb: the slots of the block and of the blocks above and below it.
 template <int BS, bool EDGE, int RULE>
-__device__ __forceinline__ void edge_block_rule(const uint32_t *rec32, uint32_t so, uint32_t sa, uint32_t sb,
+__device__ __forceinline__ void edge_block_rule(const EdgeGrid &g, uint32_t so, uint32_t sa, uint32_t sb,
                                                 const uint32_t (&o)[BS], uint32_t rule, const RuleTables &RT,
                                                 uint32_t (&next)[4]) {
     // the facing columns of the left and right neighbours
-    const uint32_t Lc = rec32[4 * (so - 1) + 3], Rc = rec32[4 * (so + 1) + 2];
+    const uint32_t Lc = g.right[so - 1], Rc = g.left[so + 1];
     // centre rows above and below (bottom row of the slot above, top row of the one below)
-    const uint32_t aC = rec32[4 * sa + 1], bC = rec32[4 * sb];
+    const uint32_t aC = g.bot[sa], bC = g.top[sb];
     // lo: byte c = position c - 1, hi: byte c = position c + 1, for each window row
     uint32_t lo[BS], hi[BS];
 #pragma unroll
@@ -173,8 +191,8 @@ __device__ __forceinline__ void edge_block_rule(const uint32_t *rec32, uint32_t 
             n[r] = up + dn + lo[r] + hi[r];
         }
     } else {
-        const uint32_t aL = rec32[4 * (sa - 1) + 1], aR = rec32[4 * (sa + 1) + 1];
-        const uint32_t bL = rec32[4 * (sb - 1)], bR = rec32[4 * (sb + 1)];
+        const uint32_t aL = g.bot[sa - 1], aR = g.bot[sa + 1];
+        const uint32_t bL = g.top[sb - 1], bR = g.top[sb + 1];
         uint32_t H[BS + 2];
         if (BS == 4) {
             H[0] = alignbyte(aC, aL, 3) + aC + alignbyte(aR, aC, 1);
@@ -300,7 +318,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         prefetch(nbr[0]);
     }
 
-    const uint32_t *rec32 = reinterpret_cast<const uint32_t *>(lds_e);
+    const EdgeGrid grid = edge_grid(lds_e, E.rec_bytes);
     uint32_t it = 0;
     for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
         uint8_t *gout = dst + uint64_t(local) * K;
@@ -311,7 +329,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             if (tid + 256 * j < E.nblk) {
                 if (bnear[j]) shift_block<NSRC>(raw[j], E.nsh);
                 unpack_rows<BS, NSRC>(E, raw[j], rows[j]);
-                *reinterpret_cast<uint4 *>(lds_e + 16 * so[j]) = edge_record<BS>(rows[j]);
+                put_record(grid, so[j], edge_record<BS>(rows[j]));
             }
         }
 #pragma unroll
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                 if (hnear[j]) shift_block<NSRC>(hraw[j], E.nsh);
                 uint32_t hr[BS];
                 unpack_rows<BS, NSRC>(E, hraw[j], hr);
-                *reinterpret_cast<uint4 *>(lds_e + 16 * hslot[j]) = edge_record<BS>(hr);
+                put_record(grid, hslot[j], edge_record<BS>(hr));
             }
         }
         __syncthreads();
@@ -337,7 +355,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         for (int j = 0; j < BPT; ++j) {
             if (tid + 256 * j < E.nblk) {
                 uint32_t next[4];
-                edge_block_rule<BS, EDGE, RULE>(rec32, so[j], sa[j], sb[j], rows[j], rule, RT, next);
+                edge_block_rule<BS, EDGE, RULE>(grid, so[j], sa[j], sb[j], rows[j], rule, RT, next);
                 uint32_t w[4];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {

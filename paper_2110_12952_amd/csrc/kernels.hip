@@ -708,9 +708,9 @@ __device__ __forceinline__ void resident_body(const TileParams &T, const Residen
                     if (bi < T.nblk) {
                         uint32_t next[4];
                         if (RT.perm)
-                            block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
+                            block_rows<BS, 1, EDGE>(box32, W4, blk[j], rule, RT, next);
                         else
-                            block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
+                            block_rows<BS, 2, EDGE>(box32, W4, blk[j], rule, RT, next);
                         uint32_t w[4];
 #pragma unroll
                         for (int d = 0; d < 4; ++d) {
@@ -896,9 +896,9 @@ __global__ __launch_bounds__(256) void k_step_packed(TileParams T, const uint16_
             if (bi < T.nblk) {
                 uint32_t next[4];
                 if (RT.perm)
-                    block_rows<BS, true, EDGE>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, 1, EDGE>(box32, W4, blk[j], rule, RT, next);
                 else
-                    block_rows<BS, false, EDGE>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, 2, EDGE>(box32, W4, blk[j], rule, RT, next);
                 uint32_t bits = 0;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
@@ -1118,8 +1118,14 @@ static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, cons
                     : launch_tiled_inst<BATCH, 256, false>(P, T, in, out, rule, rec, cu_count, st);
     return hipErrorInvalidValue;
 }
-// Resident work-groups per CU of the edge-record step (0: as many as fit).
-static constexpr int kEdgesMaxPerCU = 0;
+// Most resident work-groups per CU of the edge-record step (0: as many as
+// fit).  Measured with eight of them resident (what the occupancy allows):
+// triangle r16 31.3 us per generation, carpet r9 68.4, H r10 234; capped at
+// seven: 26.2, 61.3, 180.
+#ifndef NBB_EDGES_MAX_PER_CU
+#define NBB_EDGES_MAX_PER_CU 7
+#endif
+static constexpr int kEdgesMaxPerCU = NBB_EDGES_MAX_PER_CU;
 hipError_t launch_step_edges(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
                              uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const bool edge = (rule >> 31) != 0;

@@ -72,6 +72,10 @@ hipError_t launch_set_words(uint32_t *dst, const uint32_t *src, uint32_t n, hipS
 // Builds the per-tile record and neighbour tables of a batch on the device.
 hipError_t launch_batch_tiles(const BatchInstance *inst, uint32_t ninst, uint32_t total, uint32_t *rec,
                               uint32_t *nbr, hipStream_t st);
+// `gens` <= T.h generations of every tile of a temporal plan in one launch
+// (temporal.hip); one work-group per tile.
+hipError_t launch_step_temporal(const TemporalParams &T, const uint8_t *in, uint8_t *out, uint32_t rule,
+                                uint32_t gens, hipStream_t st);
 hipError_t launch_step_box(const BoxParams &B, const uint8_t *in, uint8_t *out, uint32_t rule, hipStream_t st);
 // Bit-packed compact state (cell i = bit i % 32 of word i / 32): conversions
 // from and to one byte per cell (any non-zero byte packs as 1; words past the

@@ -99,8 +99,9 @@ struct TileParams {
 // the facing blocks of the eight neighbour tiles.  Each thread loads its
 // block's CB bytes into registers, unpacks them into BS row dwords (byte c of
 // row r = cell (c, r) of the block, 0 where the block has no cell) and writes
-// the block's edges as one 16-byte LDS record {top row, bottom row, left
-// column, right column} (column dword: byte r = row r).  A block's 3x3-window
+// the block's edges (top row, bottom row, left column, right column; column
+// dword: byte r = row r) to its slot of four per-slot LDS arrays, 16 bytes
+// per slot in all.  A block's 3x3-window
 // ring is then the bottom rows of the three slots above it, the top rows of
 // the three below, and the facing columns of its left and right slots.  Rows
 // of the slot grid that no block occupies share one all-zero row.
@@ -113,13 +114,26 @@ struct TileParams {
 struct EdgeParams {
     uint32_t K, CB, nblk, nhalo;
     uint32_t ntiles;        // tiles of the launch (batch tiles for a batch)
-    uint32_t rec_bytes;     // LDS of the record grid (16 bytes per slot)
+    uint32_t rec_bytes;     // LDS of the record grid (16 bytes per slot: four dword arrays)
     uint32_t nsh;           // LW - CB
     uint32_t unpack01[4], unpack23[4];  // v_perm selectors: row r = perm(c1, c0, u01[r]) | perm(c3, c2, u23[r])
     uint32_t pack01[4], pack23[4];      // compact dword d = perm(n1, n0, p01[d]) | perm(n3, n2, p23[d])
     const uint32_t *blk;    // 2 per block: own slot | slot above << 16, slot below | near << 31
     const uint32_t *halo;   // 2 per item: direction << 29 | local block, slot | near << 31
     const uint32_t *nbr;    // 8 neighbour tiles per tile (0xFFFFFFFF = none)
+};
+
+// Temporal blocking (several generations per launch): work-group t holds
+// tile t's square and a ring of depth h as a B x B box (pitch P bytes) in
+// LDS, three times: two state copies and the member mask.
+struct TemporalParams {
+    uint32_t K, B, P, h;
+    uint32_t box_bytes;     // B * P rounded up to 16
+    uint32_t nhalo;
+    uint32_t ntiles;
+    const uint32_t *self;   // K entries: box offset of local cell j
+    const uint32_t *halo;   // 2 per item: direction << 29 | local index, box offset
+    const uint32_t *nbr;    // 8 per tile (0xFFFFFFFF = none)
 };
 
 // One instance of a batch (device table, sorted by tile0): its state starts

@@ -640,6 +640,75 @@ void build_mfma_tables(const Fractal &f, MfmaTables *t) {
             for (uint32_t p = 0; p < 5; ++p) t->Anu[p * KB + mu * f.k + j] = int8_t(((j * kmu) >> (7 * p)) & 127);
 }
 
+bool build_temporal_plan(const Fractal &f, uint32_t m, uint32_t h, uint32_t lds_limit, TemporalPlan *p,
+                         std::string *msg) {
+    *p = TemporalPlan();
+    if (!tiled_supported(f) || m < 1 || m > f.r) {
+        *msg = "temporal blocking needs a tiled fractal and 1 <= m <= r";
+        return false;
+    }
+    const uint64_t S = ipow64(f.s, m), K = ipow64(f.k, m);
+    if (h < 1 || h > S) {
+        *msg = "the ring depth must lie in [1, tile side]";
+        return false;
+    }
+    const uint64_t B = S + 2 * uint64_t(h), P = (B + 3) & ~uint64_t(3);
+    const uint64_t box = (B * P + 15) & ~uint64_t(15);
+    if (3 * box > lds_limit || K > (uint64_t(1) << 29)) {
+        *msg = "the boxes of this tile level and ring depth exceed the LDS";
+        return false;
+    }
+    p->m = m;
+    p->S = uint32_t(S);
+    p->K = uint32_t(K);
+    p->h = h;
+    p->B = uint32_t(B);
+    p->P = uint32_t(P);
+    p->box_bytes = uint32_t(box);
+    p->lds = uint32_t(3 * box);
+    const uint32_t rm = f.r - m;
+    p->ntiles = ipow64(f.k, rm);
+    if (p->ntiles * 8 > (uint64_t(1) << 28)) {
+        *msg = "too many tiles for the neighbour table";
+        return false;
+    }
+    p->self.resize(K);
+    std::vector<int64_t> xs(K), ys(K);
+    for (uint64_t j = 0; j < K; ++j) {
+        lambda_levels(f, m, j, &xs[j], &ys[j]);
+        p->self[j] = uint32_t((ys[j] + h) * P + (xs[j] + h));
+    }
+    // the cells of each neighbour tile inside the box; directions numbered
+    // row by row, skipping the centre, as in the neighbour table
+    const int64_t Si = int64_t(S), hi = h;
+    uint32_t d8 = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            for (uint64_t j = 0; j < K; ++j) {
+                const int64_t X = xs[j] + dx * Si + hi, Y = ys[j] + dy * Si + hi;
+                if (X < 0 || Y < 0 || X >= int64_t(B) || Y >= int64_t(B)) continue;
+                p->halo.push_back((d8 << 29) | uint32_t(j));
+                p->halo.push_back(uint32_t(Y * int64_t(P) + X));
+            }
+            ++d8;
+        }
+    p->nbr.resize(p->ntiles * 8);
+    for (uint64_t t = 0; t < p->ntiles; ++t) {
+        int64_t X, Y;
+        lambda_levels(f, rm, t, &X, &Y);
+        uint32_t e = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                const int64_t v = nu_levels(f, rm, X + dx, Y + dy);
+                p->nbr[t * 8 + e++] = v < 0 ? 0xFFFFFFFFu : uint32_t(v);
+            }
+    }
+    p->ok = true;
+    return true;
+}
+
 uint64_t box_pitch(const Fractal &f) { return std::max<uint64_t>(16, (f.n + 15) & ~uint64_t(15)); }
 
 void build_box_tables(const Fractal &f, BoxTables *b) {

@@ -89,6 +89,28 @@ struct EdgePlan {
 // beyond 64 KiB.
 bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg);
 
+// Several generations per launch (temporal blocking) for small instances: a
+// work-group holds tile t's S x S square and a ring of depth h around it (the
+// cells of the eight neighbour tiles within h of the square) as a box of side
+// B = S + 2h in LDS, steps the box `gens` <= h times there, and writes back
+// the tile's own cells, which stay exact because a generation corrupts at
+// most one more ring of the box's border.  Box row y, column x (pitch P bytes,
+// a multiple of 4) = embedded (x - h, y - h) relative to the tile's corner.
+struct TemporalPlan {
+    bool ok = false;
+    uint32_t m = 0, S = 0, K = 0, h = 0, B = 0, P = 0;
+    uint32_t box_bytes = 0;  // B * P, a multiple of 16
+    uint32_t lds = 0;        // three boxes: two state copies and the member mask
+    uint64_t ntiles = 0;
+    std::vector<uint32_t> self;  // K entries: box offset of local cell j
+    std::vector<uint32_t> halo;  // 2 per item: direction << 29 | local index, box offset
+    std::vector<uint32_t> nbr;   // 8 per tile, as the tile plan's
+};
+// false (with *msg) unless 2 <= s <= 4, 1 <= m <= r, 1 <= h <= S and the three
+// boxes fit `lds_limit` bytes.
+bool build_temporal_plan(const Fractal &f, uint32_t m, uint32_t h, uint32_t lds_limit, TemporalPlan *p,
+                         std::string *msg);
+
 // Matrix-core maps: A for lambda and Anu for nu (16 x 32*ktiles int8 each),
 // see MfmaLambda in params.hpp.  ktiles == 0 when unsupported (r*k > 192 or
 // n > 2^28).

@@ -15,6 +15,10 @@ namespace nbb {
 #ifndef NBB_TILED_WAVES_PER_SIMD
 #define NBB_TILED_WAVES_PER_SIMD 1
 #endif
+// Most resident work-groups per CU of the persistent launch.
+#ifndef NBB_TILED_MAX_PER_CU
+#define NBB_TILED_MAX_PER_CU 7
+#endif
 // Compact step, tiled (section 3, blocked approach, applied to compact
 // storage).  Tile t = compact cells [t K, (t+1) K), K = k^m: one level-m copy
 // of the fractal, covering the S x S block (S = s^m) of the box whose corner
@@ -168,13 +172,23 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
 
         // 3. rule per block, next states straight to global memory (block b
         //    holds the tile's cells [b CB, (b+1) CB))
-        if (RT.perm) {
+        if (rule == kRuleB3S23) {
 #pragma unroll
             for (int j = 0; j < BPT; ++j) {
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {  // waves with no block left skip the work
                     uint32_t next[4];
-                    block_rows<BS, true, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, 0, false, ROWS>(box32, W4, blk[j], rule, RT, next);
+                    block_store<BS>(T, next, gout + bi * T.CB);
+                }
+            }
+        } else if (RT.perm) {
+#pragma unroll
+            for (int j = 0; j < BPT; ++j) {
+                const uint32_t bi = tid + TEAM * j;
+                if (bi < T.nblk) {
+                    uint32_t next[4];
+                    block_rows<BS, 1, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -184,7 +198,7 @@ __global__ __launch_bounds__(256, NBB_TILED_WAVES_PER_SIMD) void k_step_tiled(
                 const uint32_t bi = tid + TEAM * j;
                 if (bi < T.nblk) {
                     uint32_t next[4];
-                    block_rows<BS, false, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
+                    block_rows<BS, 2, EDGE, ROWS>(box32, W4, blk[j], rule, RT, next);
                     block_store<BS>(T, next, gout + bi * T.CB);
                 }
             }
@@ -219,7 +233,7 @@ static hipError_t launch_tiled_t(const MapParams &P, const TileParams &T, const 
     // More than seven work-groups per CU measured slower where the occupancy
     // allows eight (H r10: 186 us per generation at 8, 166 us at 7; the
     // batch's H group 124 -> 111 us); at 7 and below nothing changes.
-    constexpr int kMaxPerCU = 7;
+    constexpr int kMaxPerCU = NBB_TILED_MAX_PER_CU;
     const uint64_t grid = std::min<uint64_t>(uint64_t(std::min(per_cu, kMaxPerCU)) * cu_count,
                                              (T.ntiles + kTeams - 1) / kTeams);
     hipLaunchKernelGGL((k_step_tiled<BS, CPT, HPT, BPT, BATCH, TEAM, EDGE, ROWS>), dim3(uint32_t(grid)), dim3(256), lds, st,

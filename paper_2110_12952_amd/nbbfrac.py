@@ -26,7 +26,8 @@ NBB_RULE_B3S23 = (1 << 3) | ((1 << 2 | 1 << 3) << 16)
 NBB_RULE_VON_NEUMANN = 1 << 31
 NBB_BATCH_NO_RESIDENT = 1  # nbb_batch_create_ex: small instances stepped by the group launches too
 NBB_BATCH_RESIDENT = 2     # nbb_batch_create_ex: every small instance stepped in LDS
-STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE, STRATEGY_TILED_BOX = 0, 1, 2, 3, 4
+(STRATEGY_AUTO, STRATEGY_TILED, STRATEGY_DIRECT, STRATEGY_TILED_WAVE, STRATEGY_TILED_BOX, STRATEGY_TEMPORAL,
+ STRATEGY_TILED_EDGE) = range(7)
 MAP_LUT, MAP_DIGITS, MAP_MFMA = 0, 1, 2
 
 
@@ -47,7 +48,15 @@ class Info(ctypes.Structure):
                 ("lds_bytes", ctypes.c_uint32), ("bbox_pitch", ctypes.c_uint64),
                 ("device_table_bytes", ctypes.c_uint64), ("box_low_side", ctypes.c_uint32),
                 ("box_high_side", ctypes.c_uint32), ("tiled_form", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32)]
+                ("temporal_depth", ctypes.c_uint32)]
+
+
+class TemporalView(ctypes.Structure):
+    _fields_ = [("tile_level", ctypes.c_uint32), ("tile_side", ctypes.c_uint32), ("tile_cells", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("box_side", ctypes.c_uint32), ("box_pitch", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("halo_count", ctypes.c_uint32), ("tiles", ctypes.c_uint64),
+                ("self_", ctypes.POINTER(ctypes.c_uint32)), ("halo", ctypes.POINTER(ctypes.c_uint32)),
+                ("nbr", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class PlanView(ctypes.Structure):
@@ -158,6 +167,15 @@ def lib() -> ctypes.CDLL:
     L.nbb_plan_build.restype = st
     L.nbb_plan_free.argtypes = [vp]
     L.nbb_plan_free.restype = None
+    L.nbb_batch_autotune.argtypes = [vp, vp, u32, vp, vp, u64, u32, u32, u32, vp]
+    L.nbb_batch_autotune.restype = st
+    L.nbb_configure_temporal.argtypes = [vp, u32, u32]
+    L.nbb_configure_temporal.restype = st
+    L.nbb_temporal_plan_build.argtypes = [u32, u32, vp, u32, u32, u32, u32, ctypes.POINTER(vp),
+                                          ctypes.POINTER(TemporalView)]
+    L.nbb_temporal_plan_build.restype = st
+    L.nbb_temporal_plan_free.argtypes = [vp]
+    L.nbb_temporal_plan_free.restype = None
     _lib = L
     return L
 
@@ -176,6 +194,26 @@ def _check(status: int) -> None:
 
 def _offsets_array(offsets: Sequence[Tuple[int, int]]) -> np.ndarray:
     return np.ascontiguousarray([c for o in offsets for c in o], dtype=np.int32)
+
+
+def temporal_plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: int, depth: int,
+                         lds_limit: int = 0) -> dict:
+    """Host-side temporal plan (nbb_temporal_plan_build; no device) as numpy arrays."""
+    offs = _offsets_array(offsets)
+    h = ctypes.c_void_p()
+    v = TemporalView()
+    _check(lib().nbb_temporal_plan_build(len(offsets), s, offs.ctypes.data, r, tile_level, depth, lds_limit,
+                                         ctypes.byref(h), ctypes.byref(v)))
+    try:
+        out = {"tile_level": v.tile_level, "tile_side": v.tile_side, "K": v.tile_cells, "depth": v.depth,
+               "B": v.box_side, "P": v.box_pitch, "lds_bytes": v.lds_bytes, "tiles": int(v.tiles)}
+        out["self"] = np.ctypeslib.as_array(v.self_, (v.tile_cells,)).copy()
+        out["halo"] = (np.ctypeslib.as_array(v.halo, (2 * v.halo_count,)).copy() if v.halo_count
+                       else np.zeros(0, np.uint32))
+        out["nbr"] = np.ctypeslib.as_array(v.nbr, (int(v.tiles) * 8,)).copy()
+    finally:
+        lib().nbb_temporal_plan_free(h)
+    return out
 
 
 def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: int = 0) -> dict:
@@ -260,6 +298,10 @@ class Fractal:
 
     def configure(self, strategy: int = STRATEGY_AUTO, tile_level: int = 0) -> None:
         _check(lib().nbb_configure(self._h, strategy, tile_level))
+
+    def configure_temporal(self, tile_level: int = 0, depth: int = 0) -> None:
+        """Several generations per launch (nbb_configure_temporal; 0 = automatic)."""
+        _check(lib().nbb_configure_temporal(self._h, tile_level, depth))
 
     def autotune(self, a, b, steps: int = 5, rule: int = NBB_RULE_B3S23, stream=None) -> Info:
         """Time each candidate plan on a and b (both overwritten) and keep the fastest."""
@@ -430,6 +472,23 @@ def pack_offsets(cells: Sequence[int]) -> Tuple[list, int]:
         offs.append(o)
         o += (int(c) + 15) & ~15
     return offs, max(o, 16)
+
+
+NBB_TUNE_NO_CACHE = 1
+
+
+def batch_autotune(fractals: Sequence["Fractal"], offsets: Sequence[int], a, b, steps: int = 10,
+                   rule: int = NBB_RULE_B3S23, use_cache: bool = True, stream=None) -> None:
+    """nbb_batch_autotune: per fractal of the batch, time the candidate tile
+    plans on its instances (states in arenas a and b, which are stepped) and
+    configure its descriptors to the fastest."""
+    if a.numel() != b.numel():
+        raise ValueError("arenas differ in length")
+    n = len(fractals)
+    hs = (ctypes.c_void_p * max(n, 1))(*[f._h.value for f in fractals])
+    offs = (ctypes.c_uint64 * max(n, 1))(*[int(o) for o in offsets])
+    _check(lib().nbb_batch_autotune(hs, offs, n, _dev_ptr(a, "uint8"), _dev_ptr(b, "uint8"), a.numel(), int(steps),
+                                    int(rule), 0 if use_cache else NBB_TUNE_NO_CACHE, _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 16 << 20  # NBB_NOALLOC_SCRATCH_BYTES

@@ -247,9 +247,10 @@ def test_autotune_then_step_matches_oracle(N, name, r):
     a, b = f.new_compact(), f.new_compact()
     f.init_compact(3, 0.5, out=a)
     inf = f.autotune(a, b, steps=2)
-    assert inf.strategy in (N.STRATEGY_TILED, N.STRATEGY_TILED_WAVE, N.STRATEGY_DIRECT)
+    assert inf.strategy in (N.STRATEGY_TILED, N.STRATEGY_TILED_WAVE, N.STRATEGY_TEMPORAL, N.STRATEGY_DIRECT)
     got = f.info()
-    assert (got.strategy, got.tile_level) == (inf.strategy, inf.tile_level)
+    assert (got.strategy, got.tile_level, got.temporal_depth) == (inf.strategy, inf.tile_level,
+                                                                  inf.temporal_depth)
     s0 = f.init_compact(3, 0.5)
     res = host(f.step_compact(s0, torch.empty_like(s0), 13))
     np.testing.assert_array_equal(res, o.compact_steps(o.init_compact(3, 0.5), B3S23, 13))
@@ -455,3 +456,39 @@ def test_batch_resident_default_policy(N):
     _, _, mixed = _mixed(N)
     inf = N.Batch(mixed).info()
     assert inf.resident == inf.instances - inf.direct and inf.groups == 0
+
+
+def test_batch_autotune_configures_and_keeps_results(N):
+    # plans chosen by timing: every descriptor of a fractal gets the same
+    # plan, and the tuned batch still matches the oracle
+    specs = [("triangle", 8), ("triangle", 9), ("carpet", 4), ("carpet", 5), ("hfractal", 4), ("triangle", 9)]
+    fds = [W.FRACTALS[n] for n, _ in specs]
+    frs = N.shared_descriptors([(fd.s, fd.offsets, r) for fd, (_, r) in zip(fds, specs)])
+    offsets, length = N.pack_offsets([f.cells for f in frs])
+    a = torch.zeros(length, dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    for i, f in enumerate(frs):
+        f.init_compact(40 + i, 0.4, out=a[offsets[i]:offsets[i] + f.cells])
+    N.batch_autotune(frs, offsets, a, b, steps=3, use_cache=False)
+    torch.cuda.synchronize()
+    by_fractal = {}
+    for (name, _), f in zip(specs, frs):
+        inf = f.info()
+        by_fractal.setdefault(name, set()).add((inf.strategy, inf.tile_level, inf.tiled_form))
+    assert all(len(v) == 1 for v in by_fractal.values()), by_fractal
+    # cached: the same choice again without timing
+    N.batch_autotune(frs, offsets, a, b, steps=3)
+    for (name, _), f in zip(specs, frs):
+        inf = f.info()
+        assert (inf.strategy, inf.tile_level, inf.tiled_form) in by_fractal[name]
+    # the tuned batch against the oracle
+    batch = N.Batch(frs, offsets)
+    init = []
+    for i, f in enumerate(frs):
+        f.init_compact(70 + i, 0.5, out=batch.state(a, i))
+        init.append(host(batch.state(a, i)).copy())
+    res = batch.step(a, b, 7, B3S23)
+    for i, ((name, r), fd) in enumerate(zip(specs, fds)):
+        o = O.Fractal(fd.s, fd.offsets, r)
+        np.testing.assert_array_equal(host(batch.state(res, i)), o.compact_steps(init[i], B3S23, 7),
+                                      err_msg=f"instance {i} {name} r={r}")

@@ -488,17 +488,22 @@ def test_small_triangle_workload(N):
         np.testing.assert_array_equal(host(g.gather(resb)), host(res))
 
 
-def test_workloads_run_in_edge_form(N):
-    # the automatic plans of the workloads take the edge-record form, and the
-    # byte-scatter form can be asked for at the same level
-    for name, r in [("triangle", 16), ("carpet", 9), ("hfractal", 10), ("chandelier", 11), ("triangle", 10)]:
+def test_workloads_forms(N):
+    # the automatic plans of the workloads take the edge-record form where
+    # its blocks fill the work-group passes (H r10 at level 4: 343 blocks over
+    # two passes of 256 threads takes the byte-scatter form), and either form
+    # can be asked for at the same level
+    for name, r, form in [("triangle", 16, 1), ("carpet", 9, 1), ("hfractal", 10, 2), ("chandelier", 11, 1),
+                          ("triangle", 10, 2)]:  # triangle r10: 9 blocks per tile at its level 4
         fd, o, g = pair(name, r, N)
         inf = g.info()
-        assert inf.strategy == N.STRATEGY_TILED and inf.tiled_form == 1, name
+        assert inf.strategy == N.STRATEGY_TILED and inf.tiled_form == form, name
         g.configure(N.STRATEGY_TILED_BOX, inf.tile_level)
         assert g.info().tiled_form == 2 and g.info().tile_level == inf.tile_level
+        g.configure(N.STRATEGY_TILED_EDGE, inf.tile_level)
+        assert g.info().tiled_form == 1 and g.info().strategy == N.STRATEGY_TILED
         g.configure(N.STRATEGY_TILED, inf.tile_level)
-        assert g.info().tiled_form == 1
+        assert g.info().tiled_form == form
 
 
 @pytest.mark.parametrize("name,r,m", [("triangle", 9, 7), ("triangle", 12, 6), ("carpet", 5, 3), ("carpet", 6, 4),
@@ -510,7 +515,7 @@ def test_edge_form_against_oracle(N, name, r, m):
     # shared zero rows, over every rule form (B3/S23, tables, bit extract,
     # four-cell), against the oracle and against the byte-scatter form
     fd, o, g = pair(name, r, N)
-    g.configure(N.STRATEGY_TILED, m)
+    g.configure(N.STRATEGY_TILED_EDGE, m)
     assert g.info().tiled_form == 1
     st0 = o.init_compact(808 + r, 0.45)
     for rule in RULES:
