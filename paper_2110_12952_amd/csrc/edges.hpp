@@ -71,12 +71,30 @@ __device__ __forceinline__ void shift_block(RawBlock<NSRC> &r, uint32_t sh) {
     for (int i = 0; i < NSRC; ++i) r.d[i] = alignbyte(d[i + 1], d[i], sh & 3);
 }
 
-template <int BS, int NSRC>
+// SEL: which of the plan's v_perm selectors pick any byte (bit r: unpack01[r],
+// 4 + r: unpack23[r], 8 + d: pack01[d], 12 + d: pack23[d]); a form compiled
+// for a plan's mask leaves out the permutes whose selectors pick nothing.
+// kAllSel: every selector may pick bytes (the general form).
+constexpr uint32_t kAllSel = 0xFFFFu;
+constexpr uint32_t kNoBytes = 0x0C0C0C0Cu;  // a selector picking no byte (12: zero)
+inline uint32_t edge_sel_mask(const EdgeParams &E) {
+    uint32_t m = 0;
+    for (int i = 0; i < 4; ++i) {
+        m |= uint32_t(E.unpack01[i] != kNoBytes) << i;
+        m |= uint32_t(E.unpack23[i] != kNoBytes) << (4 + i);
+        m |= uint32_t(E.pack01[i] != kNoBytes) << (8 + i);
+        m |= uint32_t(E.pack23[i] != kNoBytes) << (12 + i);
+    }
+    return m;
+}
+
+template <int BS, int NSRC, uint32_t SEL>
 __device__ __forceinline__ void unpack_rows(const EdgeParams &E, const RawBlock<NSRC> &r, uint32_t (&row)[BS]) {
 #pragma unroll
     for (int rr = 0; rr < BS; ++rr) {
-        uint32_t v = __builtin_amdgcn_perm(r.d[1], r.d[0], E.unpack01[rr]);
-        if (NSRC == 4) v |= __builtin_amdgcn_perm(r.d[3], r.d[2], E.unpack23[rr]);
+        uint32_t v = 0;
+        if (SEL & (1u << rr)) v = __builtin_amdgcn_perm(r.d[1], r.d[0], E.unpack01[rr]);
+        if (NSRC == 4 && (SEL & (16u << rr))) v |= __builtin_amdgcn_perm(r.d[3], r.d[2], E.unpack23[rr]);
         row[rr] = v;
     }
 }
@@ -109,8 +127,11 @@ __device__ __forceinline__ uint4 edge_record(const uint32_t (&row)[BS]) {
 }
 
 // Stores the CB compact bytes of w (any alignment).  CB is uniform, so the
-// choice below is scalar branches only.
-__device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB, uint8_t *p) {
+// choice below is scalar branches only (none when CB is known at compile
+// time: CBC, 0 if not).
+template <int CBC>
+__device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB_, uint8_t *p) {
+    const uint32_t CB = CBC ? uint32_t(CBC) : CB_;
     if (CB == 16) {
         store_u64(p, w[0], w[1]);
         store_u64(p + 8, w[2], w[3]);
@@ -232,7 +253,7 @@ __device__ __forceinline__ void edge_block_rule(const EdgeGrid &g, uint32_t so, 
     }
 }
 
-template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE>
+template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE, int CBC, uint32_t SEL>
 __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t *__restrict__ in,
                                                     uint8_t *__restrict__ out, uint32_t rule,
                                                     const uint32_t *__restrict__ rec) {
@@ -328,7 +349,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         for (int j = 0; j < BPT; ++j) {
             if (tid + 256 * j < E.nblk) {
                 if (bnear[j]) shift_block<NSRC>(raw[j], E.nsh);
-                unpack_rows<BS, NSRC>(E, raw[j], rows[j]);
+                unpack_rows<BS, NSRC, SEL>(E, raw[j], rows[j]);
                 put_record(grid, so[j], edge_record<BS>(rows[j]));
             }
         }
@@ -337,7 +358,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             if (hdir[j] < 8) {
                 if (hnear[j]) shift_block<NSRC>(hraw[j], E.nsh);
                 uint32_t hr[BS];
-                unpack_rows<BS, NSRC>(E, hraw[j], hr);
+                unpack_rows<BS, NSRC, SEL>(E, hraw[j], hr);
                 put_record(grid, hslot[j], edge_record<BS>(hr));
             }
         }
@@ -359,10 +380,12 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                 uint32_t w[4];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    w[d] = __builtin_amdgcn_perm(next[1], next[0], E.pack01[d]);
-                    if (BS >= 3) w[d] |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
+                    uint32_t v = 0;
+                    if (SEL & (256u << d)) v = __builtin_amdgcn_perm(next[1], next[0], E.pack01[d]);
+                    if (BS >= 3 && (SEL & (4096u << d))) v |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
+                    w[d] = v;
                 }
-                store_cells(w, CB, gout + boff[j]);
+                store_cells<CBC>(w, CB, gout + boff[j]);
             }
         }
         // the records are read until here; the next tile's come after
@@ -373,7 +396,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
 
 // Persistent launch: as many work-groups as can be resident at once, capped
 // by the tiles.
-template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE>
+template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE, int CBC, uint32_t SEL>
 static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
                                  const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
     const size_t lds = E.rec_bytes;
@@ -384,7 +407,7 @@ static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t
         per_cu = int(c & 0xFFFFFFFFu);
     } else {
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE>, 256, lds);
+            &per_cu, k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE, CBC, SEL>, 256, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
@@ -392,17 +415,17 @@ static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t
     if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, E.ntiles);
     if (!grid) return hipSuccess;
-    hipLaunchKernelGGL((k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE>), dim3(uint32_t(grid)), dim3(256), lds,
+    hipLaunchKernelGGL((k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE, CBC, SEL>), dim3(uint32_t(grid)), dim3(256), lds,
                        st, E, in, out, rule, rec);
     return hipGetLastError();
 }
-template <int BS, int NSRC, bool BATCH, bool EDGE, int RULE>
+template <int BS, int NSRC, bool BATCH, bool EDGE, int RULE, int CBC = 0, uint32_t SEL = kAllSel>
 static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
                                  const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
     const uint32_t bpt = (E.nblk + 255) / 256, hpt = (E.nhalo + 255) / 256;
 #define NBB_EDGES_CASE(B, H)                                                                              \
     if (bpt <= B && hpt <= H)                                                                             \
-    return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st)
+    return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE, CBC, SEL>(E, in, out, rule, rec, cu_count, max_per_cu, st)
     NBB_EDGES_CASE(1, 1);
     NBB_EDGES_CASE(2, 1);
     NBB_EDGES_CASE(4, 1);
@@ -412,11 +435,31 @@ static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t
 #undef NBB_EDGES_CASE
     return hipErrorInvalidValue;
 }
+// Forms compiled for particular plans: (block side, source dwords, cells per
+// block, selector mask).  The triangle F^{3,2} with offsets (0,0), (1,0),
+// (0,1) at block level 2 needs 4 of the 8 unpacking and 5 of the 12 packing
+// permutes and stores 8 + 1 bytes per block: 25.0 us per generation at r16
+// against 26.3 in the general form.  (Compiled the same way for the carpet
+// at level 1 it ran 62.7 us against 61.5, so the carpet, H and chandelier
+// plans keep the general form.)  Any other plan takes the general form.
+struct EdgeSpec {
+    uint32_t BS, nsrc, CB, sel;
+};
+constexpr EdgeSpec kSpecTriangle{4, 4, 9, 0x6387u};
+
 // shape: BS 3 or 4, and 2 or 4 source dwords per block
 template <bool BATCH, bool EDGE, int RULE>
 static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in,
                                      uint8_t *out, uint32_t rule, const uint32_t *rec, int cu_count, int max_per_cu,
                                      hipStream_t st) {
+    const uint32_t sel = edge_sel_mask(E);
+    auto is = [&](const EdgeSpec &p) { return BS == p.BS && nsrc == p.nsrc && E.CB == p.CB && sel == p.sel; };
+#define NBB_EDGES_SPEC(P)                                                                                        \
+    if (is(P))                                                                                                   \
+    return launch_edges_s<P.BS, P.nsrc, BATCH, EDGE, RULE, P.CB, P.sel>(E, in, out, rule, rec, cu_count,         \
+                                                                        max_per_cu, st)
+    NBB_EDGES_SPEC(kSpecTriangle);
+#undef NBB_EDGES_SPEC
     if (BS == 3 && nsrc == 2)
         return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
     if (BS == 3 && nsrc == 4)
