@@ -293,8 +293,10 @@ nbb_status nbb_step_blocked(const nbb_fractal *f, uint8_t *a, uint8_t *b, uint64
 
 /*
  * Bit-packed compact state (the byte layout at one bit per cell, 8x fewer
- * bytes; stencils over bit rows are the usual way to cut the state's memory
- * traffic further than the compact form does): cell i is bit i % 32 of the
+ * bytes): a capacity form, for states that would not fit as bytes.  Its step
+ * scatters the bits into the byte step's LDS box and runs the byte rule, so it
+ * is slower than the byte step (triangle r16: 49 us per generation against
+ * 25-28); it does not cut the step's time.  Cell i is bit i % 32 of the
  * little-endian 32-bit word i / 32, i.e. bit i % 8 of byte i / 8.  Needs a
  * TILED or TILED_WAVE plan (NBB_E_INVALID otherwise).
  *   nbb_packed_bytes: 4 ceil(k^r / 32) (0 for NULL).  Bits past the last cell
