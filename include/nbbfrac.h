@@ -505,14 +505,19 @@ const char *nbb_status_string(nbb_status s);
  *   0xFFFFFFFF where that block of the box holds no fractal cell.
  *
  * The edge-record form at the same level (edge_ok = 0 where it does not
- * apply): blocks sit on an edge_grid x edge_grid slot grid (block b at
- * lambda_{m-q}(b) in block units) with a one-slot ring; the grid keeps
- * edge_rows rows of edge_grid + 2 slots of 16 bytes (edge_rec_bytes).
- *   edge_blk[2b] = slot of block b | slot above << 16, edge_blk[2b+1] = slot
- *   below | near << 31 (its 4 edge_nsrc-byte load would pass the tile's end,
- *   so it loads the bytes ending at its last cell);
+ * apply): blocks sit on an edge_grid x edge_grid grid (block b at
+ * lambda_{m-q}(b) in block units) with a one-block ring for the halo items;
+ * each has a record of 16 bytes: block b is record b, halo item h record
+ * blocks + h, and the last of the edge_records records (edge_rec_bytes in
+ * all, rounded up to 4 records) is all zeros, standing for positions with no
+ * block.
+ *   edge_blk[4b .. 4b+3] = the records of block b's neighbours, two per word
+ *   (low half first): left | right, above | below, above-left | above-right,
+ *   below-left | below-right (a block's 4 edge_nsrc-byte load passes the
+ *   tile's end when b * cells per block + 4 edge_nsrc > tile_cells; it loads
+ *   the bytes ending at its last cell instead);
  *   edge_halo[2h] = direction << 29 | block of that neighbour tile,
- *   edge_halo[2h+1] = ring slot | near << 31, for edge_halo_count items;
+ *   edge_halo[2h+1] = record | near << 31, for edge_halo_count items;
  *   edge_unpack / edge_pack: the v_perm selectors from a block's bytes to its
  *   rows and from next-state rows back to compact order ([0..3] for rows or
  *   output dwords 0-3 from the first pair of sources, [4..7] from the second).
@@ -527,7 +532,7 @@ typedef struct {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;
-    uint32_t edge_ok, edge_grid, edge_rows, edge_rec_bytes, edge_halo_count, edge_nsrc, edge_nsh;
+    uint32_t edge_ok, edge_grid, edge_records, edge_rec_bytes, edge_halo_count, edge_nsrc, edge_nsh;
     uint32_t edge_unpack[8], edge_pack[8];
     const uint32_t *edge_blk;
     const uint32_t *edge_halo;

@@ -486,7 +486,7 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->edge_ok = build_edge_plan(p->f, t.m, &p->edge, &msg) ? 1u : 0u;
     const EdgePlan &e = p->edge;
     view->edge_grid = e.G;
-    view->edge_rows = e.grid_rows;
+    view->edge_records = e.nrec;
     view->edge_rec_bytes = e.rec_bytes;
     view->edge_halo_count = e.nhalo;
     view->edge_nsrc = e.nsrc;
@@ -625,7 +625,8 @@ nbb_status nbb_query(const nbb_fractal *F, nbb_info *info) {
     }
     info->bbox_pitch = box_pitch(F->f);
     info->device_table_bytes = F->dmap.bytes + F->dbox.bytes + F->dtile.bytes + F->dedge.bytes + F->dmfma.bytes;
-    if (F->use_edges) info->lds_bytes = F->edge.rec_bytes;
+    uint32_t ebpt = 0, ehpt = 0;
+    if (F->use_edges && edge_case(F->edge.nblk, F->edge.nhalo, &ebpt, &ehpt)) info->lds_bytes = edge_lds_bytes(ebpt, ehpt);
     info->tiled_form = F->strategy == NBB_STRATEGY_DIRECT ? 0u : (F->use_edges ? 1u : 2u);
     info->box_low_side = F->box.SL;
     info->box_high_side = F->box.high.empty() ? 0 : F->box.NH;

@@ -11,11 +11,14 @@
 //      thread keeps its blocks for the whole launch), unpacks them into BS row
 //      dwords with v_perm (byte c of row r = cell (c, r), 0 off the fractal)
 //      and writes the block's edges (top row, bottom row, left column, right
-//      column) to four per-slot LDS arrays; the blocks of the eight
-//      neighbour tiles that touch the tile's blocks do the same into the ring
-//      of the slot grid (zeros where a neighbour tile does not exist);
-//   2. reads, per block, the bottom rows of the three slots above, the top
-//      rows of the three below and the facing columns of the two beside it:
+//      column) as its record in four LDS dword arrays, records in block order
+//      so that a wavefront's lanes write consecutive dwords; the blocks of
+//      the eight neighbour tiles that touch the tile's blocks (halo items)
+//      write records after them (zeros where a neighbour tile does not
+//      exist);
+//   2. reads, per block, the bottom rows of the three records above, the top
+//      rows of the three below and the facing columns of the two beside it
+//      (numbers from the plan; a record of zeros where there is no block):
 //      with the block's own rows these are its whole (BS+2)-square window.
 //      Row 3-sums four positions per dword (SWAR: bytes never exceed 9),
 //      the rule per byte, v_perm back into compact order, and the block's CB
@@ -167,35 +170,37 @@ __device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB_
     }
 }
 
-// The record grid in LDS: four dword arrays of one entry per slot (top
-// rows, bottom rows, left columns, right columns), so that the lanes of a
-// wavefront, whose slots lie close together, read distinct banks.
-struct EdgeGrid {
-    uint32_t *top, *bot, *left, *right;
+// The records in LDS: four dword arrays (top rows, bottom rows, left
+// columns, right columns) of SR entries each; a record is addressed by 4 x
+// its number, the array by an instruction offset.
+template <uint32_t SR>
+struct EdgeRecs {
+    uint8_t *lds;
+    __device__ __forceinline__ uint32_t &at(uint32_t k, uint32_t a4) const {
+        return *reinterpret_cast<uint32_t *>(lds + a4 + k * SR * 4);
+    }
+    __device__ __forceinline__ void put(uint32_t a4, const uint4 &r) const {
+        at(0, a4) = r.x;
+        at(1, a4) = r.y;
+        at(2, a4) = r.z;
+        at(3, a4) = r.w;
+    }
 };
-__device__ __forceinline__ EdgeGrid edge_grid(uint8_t *lds, uint32_t rec_bytes) {
-    uint32_t *w = reinterpret_cast<uint32_t *>(lds);
-    const uint32_t ns = rec_bytes >> 4;  // slots
-    return EdgeGrid{w, w + ns, w + 2 * ns, w + 3 * ns};
-}
+constexpr uint32_t kTop = 0, kBot = 1, kLeft = 2, kRight = 3;
 
-__device__ __forceinline__ void put_record(const EdgeGrid &g, uint32_t slot, const uint4 &r) {
-    g.top[slot] = r.x;
-    g.bot[slot] = r.y;
-    g.left[slot] = r.z;
-    g.right[slot] = r.w;
-}
+// A block's eight neighbouring records (4 x their numbers).
+struct EdgeNbrs {
+    uint32_t L, R, A, B, AL, AR, BL, BR;
+};
 
 // Next states of one block, rows in next[0..BS) (byte c = column c).
-// so / sa / sb: the slots of the block and of the blocks above and below it.
-template <int BS, bool EDGE, int RULE>
-__device__ __forceinline__ void edge_block_rule(const EdgeGrid &g, uint32_t so, uint32_t sa, uint32_t sb,
-                                                const uint32_t (&o)[BS], uint32_t rule, const RuleTables &RT,
-                                                uint32_t (&next)[4]) {
+template <int BS, bool EDGE, int RULE, uint32_t SR>
+__device__ __forceinline__ void edge_block_rule(const EdgeRecs<SR> &g, const EdgeNbrs &nb, const uint32_t (&o)[BS],
+                                                uint32_t rule, const RuleTables &RT, uint32_t (&next)[4]) {
     // the facing columns of the left and right neighbours
-    const uint32_t Lc = g.right[so - 1], Rc = g.left[so + 1];
-    // centre rows above and below (bottom row of the slot above, top row of the one below)
-    const uint32_t aC = g.bot[sa], bC = g.top[sb];
+    const uint32_t Lc = g.at(kRight, nb.L), Rc = g.at(kLeft, nb.R);
+    // centre rows above and below (bottom row of the record above, top row of the one below)
+    const uint32_t aC = g.at(kBot, nb.A), bC = g.at(kTop, nb.B);
     // lo: byte c = position c - 1, hi: byte c = position c + 1, for each window row
     uint32_t lo[BS], hi[BS];
 #pragma unroll
@@ -212,8 +217,8 @@ __device__ __forceinline__ void edge_block_rule(const EdgeGrid &g, uint32_t so, 
             n[r] = up + dn + lo[r] + hi[r];
         }
     } else {
-        const uint32_t aL = g.bot[sa - 1], aR = g.bot[sa + 1];
-        const uint32_t bL = g.top[sb - 1], bR = g.top[sb + 1];
+        const uint32_t aL = g.at(kBot, nb.AL), aR = g.at(kBot, nb.AR);
+        const uint32_t bL = g.at(kTop, nb.BL), bR = g.at(kTop, nb.BR);
         uint32_t H[BS + 2];
         if (BS == 4) {
             H[0] = alignbyte(aC, aL, 3) + aC + alignbyte(aR, aC, 1);
@@ -268,24 +273,26 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         return (!BATCH || l < 8) ? E.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
     };
 
-    for (uint32_t o = tid * 16; o < E.rec_bytes; o += 256 * 16)
+    constexpr uint32_t SR = edge_rec_stride(BPT, HPT);
+    for (uint32_t o = tid * 16; o < 16 * SR; o += 256 * 16)
         *reinterpret_cast<uint4 *>(lds_e + o) = make_uint4(0, 0, 0, 0);
     const RuleTables RT = rule_tables(rule);
     // this thread's blocks and halo items (the same in every tile)
-    uint32_t so[BPT], sa[BPT], sb[BPT], boff[BPT], loff[BPT];
+    EdgeNbrs nb[BPT];
+    uint32_t own[BPT], boff[BPT], loff[BPT];
     bool bnear[BPT];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
         const uint32_t bi = min(tid + 256 * j, E.nblk - 1);
-        const uint32_t w0 = E.blk[2 * bi], w1 = E.blk[2 * bi + 1];
-        so[j] = w0 & 0xFFFFu;
-        sa[j] = w0 >> 16;
-        sb[j] = w1 & 0xFFFFu;
-        bnear[j] = (w1 >> 31) != 0;
+        const uint4 w = *reinterpret_cast<const uint4 *>(E.blk + 4 * bi);
+        nb[j] = EdgeNbrs{(w.x & 0xFFFFu) * 4, (w.x >> 16) * 4, (w.y & 0xFFFFu) * 4, (w.y >> 16) * 4,
+                         (w.z & 0xFFFFu) * 4, (w.z >> 16) * 4, (w.w & 0xFFFFu) * 4, (w.w >> 16) * 4};
+        own[j] = bi * 4;
         boff[j] = bi * CB;
+        bnear[j] = boff[j] + 4 * NSRC > K;
         loff[j] = boff[j] - (bnear[j] ? E.nsh : 0u);
     }
-    uint32_t hdir[HPT], hoff[HPT], hslot[HPT];
+    uint32_t hdir[HPT], hoff[HPT], hrec[HPT];
     bool hnear[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
@@ -295,7 +302,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         hdir[j] = ok ? (w0 >> 29) : 8u;  // 8: no item
         hnear[j] = (w1 >> 31) != 0;
         hoff[j] = (w0 & 0x1FFFFFFFu) * CB - (hnear[j] ? E.nsh : 0u);
-        hslot[j] = w1 & 0xFFFFu;
+        hrec[j] = (w1 & 0xFFFFu) * 4;
     }
     if (tid >= kLane0) {
         if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         prefetch(nbr[0]);
     }
 
-    const EdgeGrid grid = edge_grid(lds_e, E.rec_bytes);
+    const EdgeRecs<SR> grid{lds_e};
     uint32_t it = 0;
     for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
         uint8_t *gout = dst + uint64_t(local) * K;
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             if (tid + 256 * j < E.nblk) {
                 if (bnear[j]) shift_block<NSRC>(raw[j], E.nsh);
                 unpack_rows<BS, NSRC, SEL>(E, raw[j], rows[j]);
-                put_record(grid, so[j], edge_record<BS>(rows[j]));
+                grid.put(own[j], edge_record<BS>(rows[j]));
             }
         }
 #pragma unroll
@@ -359,7 +366,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                 if (hnear[j]) shift_block<NSRC>(hraw[j], E.nsh);
                 uint32_t hr[BS];
                 unpack_rows<BS, NSRC, SEL>(E, hraw[j], hr);
-                put_record(grid, hslot[j], edge_record<BS>(hr));
+                grid.put(hrec[j], edge_record<BS>(hr));
             }
         }
         __syncthreads();
@@ -376,7 +383,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         for (int j = 0; j < BPT; ++j) {
             if (tid + 256 * j < E.nblk) {
                 uint32_t next[4];
-                edge_block_rule<BS, EDGE, RULE>(grid, so[j], sa[j], sb[j], rows[j], rule, RT, next);
+                edge_block_rule<BS, EDGE, RULE, SR>(grid, nb[j], rows[j], rule, RT, next);
                 uint32_t w[4];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
 template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE, int CBC, uint32_t SEL>
 static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
                                  const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
-    const size_t lds = E.rec_bytes;
+    const size_t lds = edge_lds_bytes(BPT, HPT);
     static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
     int per_cu = 0;
     const uint64_t c = cached.load(std::memory_order_relaxed);
@@ -422,9 +429,10 @@ static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t
 template <int BS, int NSRC, bool BATCH, bool EDGE, int RULE, int CBC = 0, uint32_t SEL = kAllSel>
 static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
                                  const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
-    const uint32_t bpt = (E.nblk + 255) / 256, hpt = (E.nhalo + 255) / 256;
+    uint32_t bpt = 0, hpt = 0;
+    if (!edge_case(E.nblk, E.nhalo, &bpt, &hpt)) return hipErrorInvalidValue;
 #define NBB_EDGES_CASE(B, H)                                                                              \
-    if (bpt <= B && hpt <= H)                                                                             \
+    if (bpt == B && hpt == H)                                                                             \
     return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE, CBC, SEL>(E, in, out, rule, rec, cu_count, max_per_cu, st)
     NBB_EDGES_CASE(1, 1);
     NBB_EDGES_CASE(2, 1);

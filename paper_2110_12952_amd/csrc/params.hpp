@@ -95,16 +95,19 @@ struct TileParams {
 
 // The edge-record form of the tiled step.  The tile is cut into the same
 // level-q blocks (side BS, CB cells, consecutive in compact order) placed on a
-// G x G grid of block slots (G = S / BS) with a ring of one slot around it for
-// the facing blocks of the eight neighbour tiles.  Each thread loads its
+// G x G grid (G = S / BS), with a ring of one block around it for the facing
+// blocks of the eight neighbour tiles (the halo items).  Each thread loads its
 // block's CB bytes into registers, unpacks them into BS row dwords (byte c of
 // row r = cell (c, r) of the block, 0 where the block has no cell) and writes
 // the block's edges (top row, bottom row, left column, right column; column
-// dword: byte r = row r) to its slot of four per-slot LDS arrays, 16 bytes
-// per slot in all.  A block's 3x3-window
-// ring is then the bottom rows of the three slots above it, the top rows of
-// the three below, and the facing columns of its left and right slots.  Rows
-// of the slot grid that no block occupies share one all-zero row.
+// dword: byte r = row r) as its record in four LDS dword arrays, 16 bytes per
+// record in all.  Records are numbered in block order (block b is record b,
+// halo item h record nblk + h, the last one all zeros), so the lanes of a
+// wavefront write consecutive dwords.  A block's 3x3-window ring is then the
+// bottom rows of the three records above it, the top rows of the three below
+// and the facing columns of its left and right records, found through the
+// block's eight neighbour record numbers (the zero record where the grid has
+// no block).
 //
 // Loads are LW = 4 * NSRC bytes wide (NSRC = 2 for 3 x 3 blocks of at most 8
 // cells, else 4).  A block
@@ -114,14 +117,29 @@ struct TileParams {
 struct EdgeParams {
     uint32_t K, CB, nblk, nhalo;
     uint32_t ntiles;        // tiles of the launch (batch tiles for a batch)
-    uint32_t rec_bytes;     // LDS of the record grid (16 bytes per slot: four dword arrays)
+    uint32_t rec_bytes;     // 16 bytes per record (four dword arrays), rounded up to 4 records
     uint32_t nsh;           // LW - CB
     uint32_t unpack01[4], unpack23[4];  // v_perm selectors: row r = perm(c1, c0, u01[r]) | perm(c3, c2, u23[r])
     uint32_t pack01[4], pack23[4];      // compact dword d = perm(n1, n0, p01[d]) | perm(n3, n2, p23[d])
-    const uint32_t *blk;    // 2 per block: own slot | slot above << 16, slot below | near << 31
-    const uint32_t *halo;   // 2 per item: direction << 29 | local block, slot | near << 31
+    const uint32_t *blk;    // 4 per block: the records left | right << 16, above | below << 16,
+                            // above-left | above-right << 16, below-left | below-right << 16
+    const uint32_t *halo;   // 2 per item: direction << 29 | local block, record | near << 31
     const uint32_t *nbr;    // 8 neighbour tiles per tile (0xFFFFFFFF = none)
 };
+
+// The edge kernel's instantiation for a plan: blocks and halo items per
+// thread (BPT in 1, 2, 4; HPT in 1, 2), false if none fits; its record
+// arrays hold 256 (BPT + HPT) + 4 records each, a stride known when it is
+// compiled, so that the four arrays are reached through instruction offsets.
+inline bool edge_case(uint32_t nblk, uint32_t nhalo, uint32_t *bpt, uint32_t *hpt) {
+    const uint32_t b = (nblk + 255) / 256, h = (nhalo + 255) / 256;
+    if (b > 4 || h > 2) return false;
+    *bpt = b <= 1 ? 1 : (b <= 2 ? 2 : 4);
+    *hpt = h <= 1 ? 1 : 2;
+    return true;
+}
+constexpr uint32_t edge_rec_stride(uint32_t bpt, uint32_t hpt) { return 256 * (bpt + hpt) + 4; }
+constexpr uint32_t edge_lds_bytes(uint32_t bpt, uint32_t hpt) { return 16 * edge_rec_stride(bpt, hpt); }
 
 // Temporal blocking (several generations per launch): work-group t holds
 // tile t's square and a ring of depth h as a B x B box (pitch P bytes) in

@@ -532,45 +532,36 @@ bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg
         *msg = "more than 512 halo blocks per tile";
         return false;
     }
-    // slot-grid rows: rows holding a block or a halo item, in order; rows
-    // that are only read share one zero row
-    std::vector<int32_t> row_of(G + 2, -1);  // index Y + 1
-    for (uint64_t b = 0; b < nb; ++b) row_of[p->blk_xy[2 * b + 1] + 1] = 0;
-    for (uint32_t h = 0; h < p->nhalo; ++h) row_of[p->halo_xy[2 * h + 1] + 1] = 0;
-    uint32_t rows = 0;
-    for (auto &v : row_of)
-        if (v == 0) v = int32_t(rows++);
-    bool zero_row = false;
-    for (uint64_t b = 0; b < nb; ++b)
-        for (int dy = -1; dy <= 1; dy += 2)
-            if (row_of[p->blk_xy[2 * b + 1] + dy + 1] < 0) zero_row = true;
-    const uint32_t zrow = rows;
-    if (zero_row) ++rows;
-    p->grid_w = G + 2;
-    p->grid_rows = rows;
-    const uint64_t slots = uint64_t(rows) * p->grid_w;
-    if (slots * 16 > 65536) {
-        *msg = "record grid beyond 64 KiB";
-        return false;
-    }
-    p->rec_bytes = uint32_t(slots * 16);
-    auto slot = [&](int64_t X, int64_t Y) -> uint32_t {
-        const int32_t r = row_of[Y + 1];
-        return uint32_t(r < 0 ? zrow : uint32_t(r)) * p->grid_w + uint32_t(X + 1);
+    // records: block b is record b, halo item h record nblk + h, and one
+    // record of zeros (nrec - 1) stands for every position that holds no
+    // block; the lanes of a wavefront write consecutive records
+    const uint32_t zrec = p->nblk + p->nhalo;
+    p->nrec = zrec + 1;
+    p->rec_bytes = 16 * ((p->nrec + 3) & ~3u);
+    std::vector<int32_t> ring(size_t(G + 2) * (G + 2), -1);  // halo item at (X, Y), X, Y in -1..G
+    for (uint32_t h = 0; h < p->nhalo; ++h)
+        ring[size_t(p->halo_xy[2 * h + 1] + 1) * (G + 2) + size_t(p->halo_xy[2 * h] + 1)] = int32_t(h);
+    auto record_at = [&](int64_t X, int64_t Y) -> uint32_t {
+        if (X < -1 || Y < -1 || X > Gi || Y > Gi) return zrec;
+        const int32_t b = at(X, Y);
+        if (b >= 0) return uint32_t(b);
+        const int32_t h = ring[size_t(Y + 1) * (G + 2) + size_t(X + 1)];
+        return h >= 0 ? p->nblk + uint32_t(h) : zrec;
     };
-    p->blk.resize(2 * nb);
+    p->blk.resize(4 * nb);
     for (uint64_t b = 0; b < nb; ++b) {
         const int64_t X = p->blk_xy[2 * b], Y = p->blk_xy[2 * b + 1];
-        const uint32_t near = b * CB + LW > K ? 1u : 0u;
-        p->blk[2 * b] = slot(X, Y) | (slot(X, Y - 1) << 16);
-        p->blk[2 * b + 1] = slot(X, Y + 1) | (near << 31);
+        p->blk[4 * b] = record_at(X - 1, Y) | (record_at(X + 1, Y) << 16);
+        p->blk[4 * b + 1] = record_at(X, Y - 1) | (record_at(X, Y + 1) << 16);
+        p->blk[4 * b + 2] = record_at(X - 1, Y - 1) | (record_at(X + 1, Y - 1) << 16);
+        p->blk[4 * b + 3] = record_at(X - 1, Y + 1) | (record_at(X + 1, Y + 1) << 16);
     }
     p->halo.resize(2 * size_t(p->nhalo));
     for (uint32_t h = 0; h < p->nhalo; ++h) {
         const uint32_t lb = hd[h] & 0x1FFFFFFFu;
         const uint32_t near = uint64_t(lb) * CB + LW > K ? 1u : 0u;
         p->halo[2 * h] = hd[h];
-        p->halo[2 * h + 1] = slot(p->halo_xy[2 * h], p->halo_xy[2 * h + 1]) | (near << 31);
+        p->halo[2 * h + 1] = (p->nblk + h) | (near << 31);
     }
     // v_perm selectors: byte c of row r is cell bid(c, r) of the block's CB
     // bytes (dwords c0..c3), 12 (a zero byte) where the block has no cell

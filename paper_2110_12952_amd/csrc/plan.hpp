@@ -67,26 +67,24 @@ uint32_t auto_tile_level(const Fractal &f);
 // per tile (256 or 64); false if it does not fit.
 bool build_tile_plan(const Fractal &f, uint32_t m, TilePlan *p, std::string *msg, uint32_t team = 256);
 
-// The edge-record form of the tiled step (EdgeParams) at tile level m: block
-// slots, halo items and v_perm selectors.  Uses the neighbour table of the
-// tile plan at the same level.
+// The edge-record form of the tiled step (EdgeParams) at tile level m: each
+// block's eight neighbouring records, halo items and v_perm selectors.  Uses
+// the neighbour table of the tile plan at the same level.
 struct EdgePlan {
     bool ok = false;
     uint32_t m = 0, q = 0, S = 0, K = 0, BS = 0, CB = 0, G = 0, nblk = 0, nhalo = 0;
     uint32_t nsrc = 0;      // dwords per block load: 2 (3 x 3 blocks of at most 8 cells) or 4
-    uint32_t grid_w = 0;    // slots per slot-grid row (G + 2)
-    uint32_t grid_rows = 0; // rows kept (rows holding a block or a halo item, plus one shared zero row if read)
-    uint32_t rec_bytes = 0; // 16 * grid_w * grid_rows
+    uint32_t nrec = 0;      // records: the blocks, the halo items and one of zeros
+    uint32_t rec_bytes = 0; // 16 bytes per record, rounded up to 4 records
     uint32_t nsh = 0;       // 4 nsrc - CB
     uint32_t unpack01[4] = {}, unpack23[4] = {}, pack01[4] = {}, pack23[4] = {};
-    std::vector<uint32_t> blk;   // 2 per block, see EdgeParams
+    std::vector<uint32_t> blk;   // 4 per block, see EdgeParams
     std::vector<uint32_t> halo;  // 2 per halo item, see EdgeParams
-    std::vector<int32_t> blk_xy; // 2 per block: its slot coordinates (X, Y) in [0, G)
-    std::vector<int32_t> halo_xy; // 2 per halo item: ring slot coordinates in [-1, G]
+    std::vector<int32_t> blk_xy; // 2 per block: its grid coordinates (X, Y) in [0, G)
+    std::vector<int32_t> halo_xy; // 2 per halo item: ring coordinates in [-1, G]
 };
 // false (with *msg) if the form does not apply at this level: tiles below
-// 2 loads' width, more than 1024 blocks or 512 halo items, or a record grid
-// beyond 64 KiB.
+// 2 loads' width, more than 1024 blocks or more than 512 halo items.
 bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg);
 
 // Several generations per launch (temporal blocking) for small instances: a

@@ -69,7 +69,7 @@ class PlanView(ctypes.Structure):
                 ("lut0", ctypes.POINTER(ctypes.c_uint16)), ("lut1", ctypes.POINTER(ctypes.c_uint16)),
                 ("halo_src", ctypes.POINTER(ctypes.c_uint32)), ("halo_dst", ctypes.POINTER(ctypes.c_uint32)),
                 ("nbr", ctypes.POINTER(ctypes.c_uint32)),
-                ("edge_ok", ctypes.c_uint32), ("edge_grid", ctypes.c_uint32), ("edge_rows", ctypes.c_uint32),
+                ("edge_ok", ctypes.c_uint32), ("edge_grid", ctypes.c_uint32), ("edge_records", ctypes.c_uint32),
                 ("edge_rec_bytes", ctypes.c_uint32), ("edge_halo_count", ctypes.c_uint32),
                 ("edge_nsrc", ctypes.c_uint32), ("edge_nsh", ctypes.c_uint32),
                 ("edge_unpack", ctypes.c_uint32 * 8), ("edge_pack", ctypes.c_uint32 * 8),
@@ -236,11 +236,11 @@ def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: 
         out["nbr"] = np.ctypeslib.as_array(v.nbr, (int(v.tiles) * 8,)).copy()
         out["edge_ok"] = bool(v.edge_ok)
         if v.edge_ok:
-            for f in ("edge_grid", "edge_rows", "edge_rec_bytes", "edge_halo_count", "edge_nsrc", "edge_nsh"):
+            for f in ("edge_grid", "edge_records", "edge_rec_bytes", "edge_halo_count", "edge_nsrc", "edge_nsh"):
                 out[f] = getattr(v, f)
             out["edge_unpack"] = np.array(list(v.edge_unpack), np.uint32)
             out["edge_pack"] = np.array(list(v.edge_pack), np.uint32)
-            out["edge_blk"] = np.ctypeslib.as_array(v.edge_blk, (2 * v.blocks,)).copy()
+            out["edge_blk"] = np.ctypeslib.as_array(v.edge_blk, (4 * v.blocks,)).copy()
             out["edge_halo"] = np.ctypeslib.as_array(v.edge_halo, (2 * v.edge_halo_count,)).copy() \
                 if v.edge_halo_count else np.zeros(0, np.uint32)
         return out

@@ -1,15 +1,16 @@
 """The edge-record form's host plan, checked on the CPU.
 
-The plan (block slots, halo items, near-end loads, v_perm selectors) is read
+The plan (neighbour records, halo items, near-end loads, v_perm selectors) is read
 through nbb_plan_build and driven by a numpy model of the kernel's data
 movement: every block's bytes are loaded as the kernel loads them (4*nsrc
 bytes, the near-end ones ending at their last cell and shifted down), turned
-into rows and edge records with the plan's selectors, the records placed in a
-slot grid per tile, each block's window read back from its own rows and the
-neighbouring records, and the rule applied to four positions per dword as the
-kernel does.  One generation of that model must equal the oracle's step for
-every fractal, level and rule here; a wrong slot, a missing halo block, a bad
-selector or shift fails it.  No GPU is involved.
+into rows and edge records with the plan's selectors, the records numbered
+per tile as the kernel numbers them (blocks, then halo items, then one of
+zeros), each block's window read back from its own rows and the neighbouring
+records named by the plan, and the rule applied to four positions per dword as
+the kernel does.  One generation of that model must equal the oracle's step
+for every fractal, level and rule here; a wrong neighbour record, a missing
+halo block, a bad selector or shift fails it.  No GPU is involved.
 """
 import numpy as np
 import pytest
@@ -97,13 +98,16 @@ def model_step(fd, r, state, rule, m=0):
     assert (BS, nsrc) in ((3, 2), (3, 4), (4, 4))  # the shapes the library instantiates
     LW = 4 * nsrc
     assert nsh == LW - CB
-    slots = p["edge_rows"] * (p["edge_grid"] + 2)
-    assert p["edge_rec_bytes"] == 16 * slots
-    blk = p["edge_blk"].reshape(nb, 2)
-    so, sa = blk[:, 0] & 0xFFFF, blk[:, 0] >> 16
-    sb, bnear = blk[:, 1] & 0xFFFF, (blk[:, 1] >> 31).astype(bool)
-    assert (bnear == (np.arange(nb) * CB + LW > K)).all()
-    rec = np.zeros((T, slots, 4), U32)
+    nh = p["edge_halo_count"]
+    nrec = p["edge_records"]
+    assert nrec == nb + nh + 1 and p["edge_rec_bytes"] == 16 * ((nrec + 3) // 4 * 4)
+    blk = p["edge_blk"].reshape(nb, 4)
+    # the eight neighbour records: left, right, above, below, above-left,
+    # above-right, below-left, below-right
+    nbrec = np.stack([blk[:, i // 2] >> (16 * (i % 2)) & 0xFFFF for i in range(8)], axis=1).astype(np.int64)
+    assert nbrec.max() < nrec
+    bnear = np.arange(nb) * CB + LW > K
+    rec = np.zeros((T, nrec, 4), U32)  # the last record stays zero
     tiles = np.arange(T)
     # own blocks: loads, rows, records
     off = tiles[:, None] * K + (np.arange(nb) * CB - np.where(bnear, nsh, 0))[None, :]
@@ -112,13 +116,13 @@ def model_step(fd, r, state, rule, m=0):
     if near.any():
         raw[near] = shift(raw[near], nsh, nsrc)
     rows = unpack(p, raw, BS)
-    rec[np.repeat(tiles, nb), np.tile(so, T)] = record(rows, BS)
+    rec[np.repeat(tiles, nb), np.tile(np.arange(nb), T)] = record(rows, BS)
     # halo items
-    nh = p["edge_halo_count"]
     if nh:
         hal = p["edge_halo"].reshape(nh, 2)
         hdir, hlb = hal[:, 0] >> 29, hal[:, 0] & 0x1FFFFFFF
         hslot, hnear = hal[:, 1] & 0xFFFF, (hal[:, 1] >> 31).astype(bool)
+        assert (hslot == nb + np.arange(nh)).all()
         nbr = p["nbr"].reshape(T, 8)
         nt = nbr[:, hdir]  # T x nh
         ok = nt != 0xFFFFFFFF
@@ -129,12 +133,12 @@ def model_step(fd, r, state, rule, m=0):
             hraw[hnear[hh]] = shift(hraw[hnear[hh]], nsh, nsrc)
         rec[tt, hslot[hh]] = record(unpack(p, hraw, BS), BS)
     # the rule per block, read as the kernel reads
-    R = rec.reshape(T, slots * 4)
+    R = rec.reshape(T, nrec * 4)
     ti = np.repeat(tiles, nb)
-    rd = lambda s_, w: R[ti, 4 * np.tile(s_, T).astype(np.int64) + w]
-    Lc, Rc = rd(so - 1, 3), rd(so + 1, 2)
-    aC, bC = rd(sa, 1), rd(sb, 0)
-    aL, aR, bL, bR = rd(sa - 1, 1), rd(sa + 1, 1), rd(sb - 1, 0), rd(sb + 1, 0)
+    rd = lambda i, w: R[ti, 4 * np.tile(nbrec[:, i], T) + w]
+    Lc, Rc = rd(0, 3), rd(1, 2)
+    aC, bC = rd(2, 1), rd(3, 0)
+    aL, aR, bL, bR = rd(4, 1), rd(5, 1), rd(6, 0), rd(7, 0)
     o = rows
     lo = [vperm(o[q], Lc, sel4(q, 4, 5, 6)) for q in range(BS)]
     hi = [vperm(Rc, o[q], sel4(1, 2, 3, 4 + q) if BS == 4 else sel4(1, 2, 4 + q, 12)) for q in range(BS)]
@@ -201,7 +205,7 @@ def shift(raw, sh, nsrc):
 # (fractal, r, tile level): the workloads' levels and tile sizes around them,
 # fractals whose blocks need four source dwords (triangle, grid4_12,
 # fullsquare) or two, near-end blocks (CB not a multiple of the load width),
-# sparse slot grids with a shared zero row (chandelier, cantor dust)
+# sparse grids whose blocks often border no block (chandelier, cantor dust)
 CASES = [("triangle", 7, 7), ("triangle", 9, 7), ("triangle", 10, 5), ("triangle", 12, 6), ("carpet", 4, 4),
          ("carpet", 5, 3), ("carpet", 6, 4), ("hfractal", 5, 4), ("hfractal", 6, 3), ("chandelier", 7, 5),
          ("chandelier", 9, 4), ("vicsek", 5, 3), ("xfractal", 5, 4), ("cantordust", 6, 3),
@@ -262,3 +266,4 @@ def test_edge_plan_applies_to_the_workloads():
         p = N.plan_tables(fd.s, fd.offsets, r)
         assert p["edge_ok"], name
         assert p["edge_rec_bytes"] <= 32768, (name, p["edge_rec_bytes"])
+        assert p["edge_records"] == p["blocks"] + p["edge_halo_count"] + 1
