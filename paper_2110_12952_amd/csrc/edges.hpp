@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
 // by the tiles.
 template <int BS, int NSRC, int BPT, int HPT, bool BATCH, bool EDGE, int RULE, int CBC, uint32_t SEL>
 static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
-                                 const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
+                                 const uint32_t *rec, int cu_count, EdgeCaps caps, hipStream_t st) {
     const size_t lds = edge_lds_bytes(BPT, HPT);
     static std::atomic<uint64_t> cached{0};  // lds << 32 | per_cu
     int per_cu = 0;
@@ -419,7 +419,8 @@ static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t
         if (per_cu < 1) per_cu = 1;
         cached.store(uint64_t(lds) << 32 | uint32_t(per_cu), std::memory_order_relaxed);
     }
-    if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
+    const int cap = BPT == 1 ? caps.one : caps.more;
+    if (cap > 0) per_cu = std::min(per_cu, cap);
     const uint64_t grid = std::min<uint64_t>(uint64_t(per_cu) * cu_count, E.ntiles);
     if (!grid) return hipSuccess;
     hipLaunchKernelGGL((k_step_edges<BS, NSRC, BPT, HPT, BATCH, EDGE, RULE, CBC, SEL>), dim3(uint32_t(grid)), dim3(256), lds,
@@ -428,12 +429,12 @@ static hipError_t launch_edges_t(const EdgeParams &E, const uint8_t *in, uint8_t
 }
 template <int BS, int NSRC, bool BATCH, bool EDGE, int RULE, int CBC = 0, uint32_t SEL = kAllSel>
 static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t *out, uint32_t rule,
-                                 const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
+                                 const uint32_t *rec, int cu_count, EdgeCaps caps, hipStream_t st) {
     uint32_t bpt = 0, hpt = 0;
     if (!edge_case(E.nblk, E.nhalo, &bpt, &hpt)) return hipErrorInvalidValue;
 #define NBB_EDGES_CASE(B, H)                                                                              \
     if (bpt == B && hpt == H)                                                                             \
-    return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE, CBC, SEL>(E, in, out, rule, rec, cu_count, max_per_cu, st)
+    return launch_edges_t<BS, NSRC, B, H, BATCH, EDGE, RULE, CBC, SEL>(E, in, out, rule, rec, cu_count, caps, st)
     NBB_EDGES_CASE(1, 1);
     NBB_EDGES_CASE(2, 1);
     NBB_EDGES_CASE(4, 1);
@@ -458,22 +459,22 @@ constexpr EdgeSpec kSpecTriangle{4, 4, 9, 0x6387u};
 // shape: BS 3 or 4, and 2 or 4 source dwords per block
 template <bool BATCH, bool EDGE, int RULE>
 static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in,
-                                     uint8_t *out, uint32_t rule, const uint32_t *rec, int cu_count, int max_per_cu,
+                                     uint8_t *out, uint32_t rule, const uint32_t *rec, int cu_count, EdgeCaps caps,
                                      hipStream_t st) {
     const uint32_t sel = edge_sel_mask(E);
     auto is = [&](const EdgeSpec &p) { return BS == p.BS && nsrc == p.nsrc && E.CB == p.CB && sel == p.sel; };
 #define NBB_EDGES_SPEC(P)                                                                                        \
     if (is(P))                                                                                                   \
     return launch_edges_s<P.BS, P.nsrc, BATCH, EDGE, RULE, P.CB, P.sel>(E, in, out, rule, rec, cu_count,         \
-                                                                        max_per_cu, st)
+                                                                        caps, st)
     NBB_EDGES_SPEC(kSpecTriangle);
 #undef NBB_EDGES_SPEC
     if (BS == 3 && nsrc == 2)
-        return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+        return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, caps, st);
     if (BS == 3 && nsrc == 4)
-        return launch_edges_s<3, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+        return launch_edges_s<3, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, caps, st);
     if (BS == 4 && nsrc == 4)
-        return launch_edges_s<4, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, max_per_cu, st);
+        return launch_edges_s<4, 4, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, caps, st);
     return hipErrorInvalidValue;
 }
 

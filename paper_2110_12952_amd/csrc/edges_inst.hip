@@ -13,12 +13,12 @@ namespace nbb {
 
 template <bool BATCH, bool EDGE, int RULE>
 hipError_t launch_edges_inst(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
-                             uint32_t rule, const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st) {
-    return launch_edges_shape<BATCH, EDGE, RULE>(E, BS, nsrc, in, out, rule, rec, cu_count, max_per_cu, st);
+                             uint32_t rule, const uint32_t *rec, int cu_count, EdgeCaps caps, hipStream_t st) {
+    return launch_edges_shape<BATCH, EDGE, RULE>(E, BS, nsrc, in, out, rule, rec, cu_count, caps, st);
 }
 
 template hipError_t launch_edges_inst<bool(NBB_INST_BATCH), bool(NBB_INST_EDGE), NBB_INST_RULE>(
-    const EdgeParams &, uint32_t, uint32_t, const uint8_t *, uint8_t *, uint32_t, const uint32_t *, int, int,
+    const EdgeParams &, uint32_t, uint32_t, const uint8_t *, uint8_t *, uint32_t, const uint32_t *, int, EdgeCaps,
     hipStream_t);
 
 }  // namespace nbb

@@ -11,12 +11,12 @@ namespace nbb {
 
 template <bool BATCH, bool EDGE, int RULE>
 hipError_t launch_edges_inst(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
-                             uint32_t rule, const uint32_t *rec, int cu_count, int max_per_cu, hipStream_t st);
+                             uint32_t rule, const uint32_t *rec, int cu_count, EdgeCaps caps, hipStream_t st);
 
 #define NBB_EDGES_INST_DECL(B, E, R)                                                                       \
     extern template hipError_t launch_edges_inst<B, E, R>(const EdgeParams &, uint32_t, uint32_t,          \
                                                           const uint8_t *, uint8_t *, uint32_t,            \
-                                                          const uint32_t *, int, int, hipStream_t);
+                                                          const uint32_t *, int, EdgeCaps, hipStream_t);
 NBB_EDGES_INST_DECL(false, false, 0)
 NBB_EDGES_INST_DECL(false, false, 1)
 NBB_EDGES_INST_DECL(false, false, 2)

@@ -1119,18 +1119,22 @@ static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, cons
     return hipErrorInvalidValue;
 }
 // Most resident work-groups per CU of the edge-record step (0: as many as
-// fit).  Measured with eight of them resident (what the occupancy allows):
-// triangle r16 31.3 us per generation, carpet r9 68.4, H r10 234; capped at
-// seven: 26.2, 61.3, 180.
+// fit), for plans of one block per thread and of more.  Measured with the
+// records in block order: triangle r16 (one block per thread) 22.5 us per
+// generation with eight resident, 22.8 with seven; carpet r9 (two) 67.2 with
+// eight, 59.6 with seven, 61.6 with six.
+#ifndef NBB_EDGES_MAX_PER_CU_ONE
+#define NBB_EDGES_MAX_PER_CU_ONE 8
+#endif
 #ifndef NBB_EDGES_MAX_PER_CU
 #define NBB_EDGES_MAX_PER_CU 7
 #endif
-static constexpr int kEdgesMaxPerCU = NBB_EDGES_MAX_PER_CU;
+static constexpr EdgeCaps kEdgesCaps{NBB_EDGES_MAX_PER_CU_ONE, NBB_EDGES_MAX_PER_CU};
 hipError_t launch_step_edges(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
                              uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
     const bool edge = (rule >> 31) != 0;
     const int kind = edges_rule_kind(rule);
-    const int mx = kEdgesMaxPerCU;
+    const EdgeCaps mx = kEdgesCaps;
 #define NBB_EDGES_GO(B)                                                                                  \
     do {                                                                                                  \
         if (edge) return launch_edges_inst<B, true, 1>(E, BS, nsrc, in, out, rule, rec, cu_count, mx, st); \

@@ -138,6 +138,11 @@ inline bool edge_case(uint32_t nblk, uint32_t nhalo, uint32_t *bpt, uint32_t *hp
     *hpt = h <= 1 ? 1 : 2;
     return true;
 }
+// Most resident work-groups per CU of the edge-record step (0: as many as
+// fit) for plans of one block per thread and of more.
+struct EdgeCaps {
+    int one, more;
+};
 constexpr uint32_t edge_rec_stride(uint32_t bpt, uint32_t hpt) { return 256 * (bpt + hpt) + 4; }
 constexpr uint32_t edge_lds_bytes(uint32_t bpt, uint32_t hpt) { return 16 * edge_rec_stride(bpt, hpt); }
 
