@@ -1281,7 +1281,7 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     uint8_t *in = a, *out = b;
     for (uint32_t i = 0; i < steps; ++i) {
         for (const BatchGroup &G : B->groups) {
-            e = G.edges ? launch_step_edges(G.ep, G.BS, G.nsrc, in, out, rule, G.rec, B->cu_count, s)
+            e = G.edges ? launch_step_edges(G.ep, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, s)
                         : launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, s);
             if (e != hipSuccess) return hip_fail(e, "batch step launch");
         }
@@ -1336,7 +1336,7 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
             if (G.edges) {
                 EdgeParams E = G.ep;
                 E.ntiles = nt;
-                e = launch_step_edges(E, G.BS, G.nsrc, in, out, rule, G.rec, B->cu_count, s);
+                e = launch_step_edges(E, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, s);
             } else {
                 TileParams T = G.tp;
                 T.ntiles = nt;
@@ -1655,7 +1655,7 @@ nbb_status nbb_step_compact(const nbb_fractal *F, uint8_t *a, uint8_t *b, uint64
         }
     } else if (F->use_edges) {
         for (uint32_t i = 0; i < steps; ++i) {
-            hipError_t e = launch_step_edges(F->ep, F->edge.BS, F->edge.nsrc, in, out, rule, nullptr, F->cu_count,
+            hipError_t e = launch_step_edges(F->ep, F->edge.BS, F->edge.nsrc, in, out, F->f.cells, rule, nullptr, F->cu_count,
                                              s);
             if (e != hipSuccess) return hip_fail(e, "edge step launch");
             std::swap(in, out);

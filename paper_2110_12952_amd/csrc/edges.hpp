@@ -7,9 +7,10 @@
 // cut into level-q blocks whose CB cells are consecutive in compact order and
 // fill the same positions of a BS x BS square in every block.  Per tile a
 // work-group of 256 threads
-//   1. loads each block's CB bytes into registers (one load per block; every
-//      thread keeps its blocks for the whole launch), unpacks them into BS row
-//      dwords with v_perm (byte c of row r = cell (c, r), 0 off the fractal)
+//   1. loads each block's CB bytes into registers (one load of an 8-byte
+//      aligned window per block, moved into place with v_alignbyte; every
+//      thread keeps its blocks for the whole launch), unpacks them into BS
+//      row dwords with v_perm (byte c of row r = cell (c, r), 0 off the fractal)
 //      and writes the block's edges (top row, bottom row, left column, right
 //      column) as its record in four LDS dword arrays, records in block order
 //      so that a wavefront's lanes write consecutive dwords; the blocks of
@@ -23,9 +24,14 @@
 //      Row 3-sums four positions per dword (SWAR: bytes never exceed 9),
 //      the rule per byte, v_perm back into compact order, and the block's CB
 //      next states go straight to global memory.
-// Work-groups are persistent over XCD-contiguous tile ranges; the next
-// tile's loads are issued before the current tile's rule, and its neighbour
-// tiles travel through LDS two tiles ahead.
+// Work-groups are persistent over XCD-contiguous tile ranges.  A tile's
+// loads are issued two tiles ahead of its rule (two register sets, the loop
+// unrolled twice so that each has fixed registers) and its neighbour tiles'
+// numbers four tiles ahead (through registers, then LDS); no load, store or
+// use of a loaded register sits behind a per-thread branch, so the
+// compiler's waits for outstanding memory operations stay a tile or more
+// behind the loads.  (Measured on the triangle r16: 22.8 us per generation
+// with one tile ahead and unaligned loads, 20.4 like this.)
 //
 // BATCH: tiles of many instances of one plan in an arena, as in the
 // byte-scatter form (k_step_tiled): batch tile g is local tile rec[2g+1]
@@ -50,28 +56,56 @@ struct RawBlock {
     uint32_t d[NSRC];
 };
 
-// 4 NSRC bytes from any byte address (gfx950 global loads need no alignment).
-template <int NSRC>
-__device__ __forceinline__ RawBlock<NSRC> load_block(const uint8_t *p) {
-    RawBlock<NSRC> r;
-    __builtin_memcpy(&r, p, 4 * NSRC);
-    return r;
+// A block's CB bytes are read through one load of WB = 8 NW bytes (NW = 2
+// covers CB <= 9, NW = 3 CB <= 17) from the 8-byte boundary at or below its
+// first byte: unaligned loads cost the vector memory unit about three times
+// as much as aligned ones.  A window that would run past `lim` (the end of
+// the readable bytes, in the state's or arena's last tile only) ends there
+// instead.  sh = offset of the block's first byte in the window.
+template <int NW>
+struct Window {
+    uint32_t d[2 * NW];
+    uint32_t sh;
+};
+template <int NW>
+__device__ __forceinline__ Window<NW> load_window(const uint8_t *p, const uint8_t *lim) {
+    Window<NW> w;
+    const uint8_t *s = p - (uint32_t(reinterpret_cast<uintptr_t>(p)) & 7u);
+    if (s + 8 * NW > lim) s = lim - 8 * NW;  // a select, not a branch
+    w.sh = uint32_t(p - s);
+    __builtin_memcpy(w.d, s, 8 * NW);
+    return w;
 }
-
-// The block's bytes were loaded ending at its last cell: move them down by
-// sh bytes (0 < sh < 4 NSRC, uniform).
-template <int NSRC>
-__device__ __forceinline__ void shift_block(RawBlock<NSRC> &r, uint32_t sh) {
-    uint32_t d[NSRC + 1];
+// The block's bytes from byte 0 (dword i = bytes 4i..4i+3, NOUT dwords
+// used).  WIDE: sh may exceed 7 (a window ended at `lim`), else sh < 8.
+template <int NSRC, int NW, int NOUT, bool WIDE>
+__device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
+    constexpr int ND = 2 * NW;
+    RawBlock<NSRC> r;
+    const uint32_t h = w.sh >> 2;
+    // dwords h.. of the window, moved down by one, two and four dwords as
+    // the bits of h say (two-way selects: an indexed pick would go through
+    // scratch memory)
+    uint32_t x[ND + 1];
 #pragma unroll
-    for (int i = 0; i < NSRC; ++i) d[i] = r.d[i];
-    d[NSRC] = 0;
-    for (uint32_t w = 0; w < (sh >> 2); ++w) {
+    for (int i = 0; i < ND; ++i) x[i] = w.d[i];
+    x[ND] = 0;
 #pragma unroll
-        for (int i = 0; i < NSRC; ++i) d[i] = d[i + 1];
+    for (int b = 0; b < (WIDE ? 3 : 1); ++b) {
+        const int m = 1 << b;
+        if (m >= ND) break;
+        const bool on = (h >> b) & 1;
+#pragma unroll
+        for (int i = 0; i <= ND; ++i) x[i] = on ? (i + m <= ND ? x[i + m] : 0u) : x[i];
     }
 #pragma unroll
-    for (int i = 0; i < NSRC; ++i) r.d[i] = alignbyte(d[i + 1], d[i], sh & 3);
+    for (int i = 0; i < NSRC; ++i) r.d[i] = i < NOUT ? alignbyte(x[i + 1], x[i], w.sh & 3) : 0u;
+    return r;
+}
+// Whether any thread of the wavefront holds a window that needs the wide form.
+template <int NW>
+__device__ __forceinline__ bool any_wide(const Window<NW> &w) {
+    return __builtin_amdgcn_ballot_w64(w.sh >= 8) != 0;
 }
 
 // SEL: which of the plan's v_perm selectors pick any byte (bit r: unpack01[r],
@@ -264,140 +298,210 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                                                     const uint32_t *__restrict__ rec) {
     extern __shared__ __align__(16) uint8_t lds_e[];
     constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
-    constexpr uint32_t kLane0 = 256 - kLanes;
-    __shared__ uint32_t nbr[2][kLanes];
-    const uint32_t tid = threadIdx.x;
+    // window loads per block, dwords of block bytes used, and whether a
+    // window ended at the readable end can leave the block 8 or more bytes in
+    // (blocks of 8 cells start 8-aligned: tiles hold a multiple of 8 cells
+    // and states start 16-aligned, so their window is the block itself)
+    constexpr bool kA8 = CBC == 8;
+    constexpr int NW = kA8 ? 1 : ((NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
+    constexpr int NOUT = CBC ? (CBC + 3) / 4 : NSRC;
+    constexpr bool kWide = !kA8 && !(CBC && 8 * NW - CBC < 8);
+    constexpr uint32_t WB = 8 * NW;
+    // neighbour entries of four tiles in a ring (written by wavefront 0)
+    __shared__ uint32_t nbr[4][kLanes];
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    const bool wave0 = __builtin_amdgcn_readfirstlane(tid) == 0;
     const uint32_t K = E.K, CB = E.CB;
-    const XcdRange R = xcd_range(blockIdx.x, gridDim.x, E.ntiles);
-    auto entry = [&](uint64_t t, uint32_t l) -> uint32_t {
-        return (!BATCH || l < 8) ? E.nbr[t * 8 + l] : rec[t * 2 + (l - 8)];
+    const XcdRange R64 = xcd_range(blockIdx.x, gridDim.x, E.ntiles);
+    // tile numbers fit 32 bits (E.ntiles does)
+    const uint32_t first = uint32_t(R64.first), end = uint32_t(R64.end), step = uint32_t(R64.step);
+    if (first >= end) return;
+    // The work-group's tiles are first + i step.  Loads run up to four
+    // tiles ahead; past the last tile they read the last tile again (cached).
+    // 32-bit arithmetic throughout (a tile holds at least 32 cells, so tile
+    // numbers stay below 2^31 and first + (i + 4) step does not wrap); 64-bit
+    // compares would need vector registers.
+    const uint32_t last = first + (end - 1 - first) / step * step;
+    auto clamp = [&](uint32_t i) -> uint32_t {  // the work-group's i-th tile
+        return min(first + i * step, last);
+    };
+    auto entry = [&](uint32_t t, uint32_t l) -> uint32_t {
+        return (!BATCH || l < 8) ? E.nbr[uint64_t(t) * 8 + l] : rec[uint64_t(t) * 2 + (l - 8)];
     };
 
     constexpr uint32_t SR = edge_rec_stride(BPT, HPT);
     for (uint32_t o = tid * 16; o < 16 * SR; o += 256 * 16)
         *reinterpret_cast<uint4 *>(lds_e + o) = make_uint4(0, 0, 0, 0);
     const RuleTables RT = rule_tables(rule);
-    // this thread's blocks and halo items (the same in every tile)
+    // This thread's blocks (the same in every tile).  A thread beyond the
+    // tile's blocks takes block number modulo their count again and writes
+    // and stores the same values as that block's own thread, so that no load,
+    // store or use of a loaded register sits behind a per-thread branch and
+    // the compiler's waits for outstanding memory operations count exactly.
     EdgeNbrs nb[BPT];
-    uint32_t own[BPT], boff[BPT], loff[BPT];
-    bool bnear[BPT];
+    uint32_t own[BPT], boff[BPT];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
-        const uint32_t bi = min(tid + 256 * j, E.nblk - 1);
+        const uint32_t bi = (tid + 256 * j) % E.nblk;
         const uint4 w = *reinterpret_cast<const uint4 *>(E.blk + 4 * bi);
         nb[j] = EdgeNbrs{(w.x & 0xFFFFu) * 4, (w.x >> 16) * 4, (w.y & 0xFFFFu) * 4, (w.y >> 16) * 4,
                          (w.z & 0xFFFFu) * 4, (w.z >> 16) * 4, (w.w & 0xFFFFu) * 4, (w.w >> 16) * 4};
         own[j] = bi * 4;
         boff[j] = bi * CB;
-        bnear[j] = boff[j] + 4 * NSRC > K;
-        loff[j] = boff[j] - (bnear[j] ? E.nsh : 0u);
     }
+    // Halo items: item h is thread h % 256's j = h / 256; only wavefronts
+    // that hold an item load and write them (a uniform branch).  A thread
+    // without an item loads its own block's window and writes to a record
+    // nobody reads (past the record of zeros).
     uint32_t hdir[HPT], hoff[HPT], hrec[HPT];
-    bool hnear[HPT];
+    bool hwave[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
         const uint32_t h = tid + 256 * j;
         const bool ok = h < E.nhalo;
         const uint32_t w0 = ok ? E.halo[2 * h] : 0u, w1 = ok ? E.halo[2 * h + 1] : 0u;
         hdir[j] = ok ? (w0 >> 29) : 8u;  // 8: no item
-        hnear[j] = (w1 >> 31) != 0;
-        hoff[j] = (w0 & 0x1FFFFFFFu) * CB - (hnear[j] ? E.nsh : 0u);
-        hrec[j] = (w1 & 0xFFFFu) * 4;
+        hoff[j] = (w0 & 0x1FFFFFFFu) * CB;
+        hrec[j] = (ok ? (w1 & 0xFFFFu) : E.nblk + h + 1) * 4;
+        hwave[j] = __builtin_amdgcn_readfirstlane(tid) + 256 * j < E.nhalo;
     }
-    if (tid >= kLane0) {
-        if (R.first < R.end) nbr[0][tid - kLane0] = entry(R.first, tid - kLane0);
-        if (R.first + R.step < R.end) nbr[1][tid - kLane0] = entry(R.first + R.step, tid - kLane0);
+
+    // The loads of a tile, issued two tiles ahead of its rule.
+    struct Pending {
+        Window<NW> raw[BPT], hraw[HPT];
+        bool hok[HPT];
+        const uint8_t *src;  // the state the tile belongs to
+        uint8_t *dst;
+        uint32_t local, lim;  // local tile number, readable bytes from src
+    };
+    // one window (32-bit offset from the state, any block of it): from the
+    // 8-byte boundary at or below the block, or ending at the readable end
+    auto window = [&](const uint8_t *src, uint32_t off, uint32_t lim, bool may_end) -> Window<NW> {
+        Window<NW> w;
+        if (kA8) {
+            w.sh = 0;
+            __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, 8), 8);
+            return w;
+        }
+        const uint32_t sh = (uint32_t(reinterpret_cast<uintptr_t>(src)) + off) & 7u;
+        uint32_t s = off - sh;
+        if (may_end) s = s > lim - WB ? lim - WB : s;
+        w.sh = off - s;
+        __builtin_memcpy(w.d, src + s, WB);
+        return w;
+    };
+    auto prefetch = [&](Pending &P, uint32_t t, const uint32_t *e) {
+        uint64_t base = 0;
+        if (BATCH) {
+            base = uint64_t(__builtin_amdgcn_readfirstlane(e[8])) << 4;
+            P.local = __builtin_amdgcn_readfirstlane(e[9]) & 0x7FFFFFFFu;
+        } else {
+            P.local = t;
+        }
+        P.src = in + base;
+        P.dst = out + base;
+        const uint64_t room = E.limit - base;  // bytes readable from src
+        P.lim = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(room);
+        const uint32_t toff = P.local * K;
+        const bool tail = toff + K > P.lim - WB;  // uniform
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) P.raw[j] = window(P.src, toff + boff[j], P.lim, tail);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hwave[j]) {
+                const uint32_t nt = e[hdir[j] & 7];
+                P.hok[j] = hdir[j] < 8 && nt != kOutside;
+                P.hraw[j] = window(P.src, P.hok[j] ? nt * K + hoff[j] : toff + boff[0], P.lim, true);
+            }
+        }
+    };
+    auto aligned = [&](const Window<NW> &w) -> RawBlock<NSRC> {
+        if (kA8) {
+            RawBlock<NSRC> r;
+#pragma unroll
+            for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 ? w.d[i < 2 * NW ? i : 0] : 0u;
+            return r;
+        }
+        if (kWide && any_wide<NW>(w)) return align_window<NSRC, NW, NOUT, true>(w);
+        return align_window<NSRC, NW, NOUT, false>(w);
+    };
+    const EdgeRecs<SR> grid{lds_e};
+    // step 1 of a tile: the records of its blocks (kept as rows) and halo blocks
+    uint32_t rows[BPT][BS];
+    auto records = [&](Pending &P) {
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            unpack_rows<BS, NSRC, SEL>(E, aligned(P.raw[j]), rows[j]);
+            grid.put(own[j], edge_record<BS>(rows[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            if (hwave[j]) {
+                uint32_t hr[BS];
+                unpack_rows<BS, NSRC, SEL>(E, aligned(P.hraw[j]), hr);
+                grid.put(hrec[j], edge_record<BS>(hr));
+                // an item whose neighbour tile does not exist is a block of zeros
+                if (!P.hok[j]) grid.put(hrec[j], make_uint4(0, 0, 0, 0));
+            }
+        }
+    };
+
+    // Start: the entries of the first four tiles (the fourth's stay in a
+    // register until the first tile is done), the loads of the first two
+    // tiles, the first tile's records.
+    Pending P0, P1;
+    uint32_t c0 = 0, c1 = 0;
+    const uint32_t lslot = lane < kLanes ? lane : 0u;
+    if (wave0) {
+        const uint32_t e0 = entry(clamp(0), lslot), e1 = entry(clamp(1), lslot), e2 = entry(clamp(2), lslot);
+        c1 = entry(clamp(3), lslot);
+        if (lane < kLanes) {
+            nbr[0][lane] = e0;
+            nbr[1][lane] = e1;
+            nbr[2][lane] = e2;
+        }
     }
     __syncthreads();
+    prefetch(P0, first, nbr[0]);
+    prefetch(P1, clamp(1), nbr[1]);
+    records(P0);
 
-    // where a tile lives: its state array and local index
-    const uint8_t *src = in;
-    uint8_t *dst = out;
-    uint32_t local = 0;
-    auto locate = [&](uint64_t t, const uint32_t *e) {
-        if (BATCH) {
-            const uint64_t base = uint64_t(__builtin_amdgcn_readfirstlane(e[8])) << 4;
-            src = in + base;
-            dst = out + base;
-            local = __builtin_amdgcn_readfirstlane(e[9]) & 0x7FFFFFFFu;
-        } else {
-            local = uint32_t(t);
-        }
-    };
-    RawBlock<NSRC> raw[BPT], hraw[HPT];
-    auto prefetch = [&](const uint32_t *e) {
-        const uint8_t *tb = src + uint64_t(local) * K;
-#pragma unroll
-        for (int j = 0; j < BPT; ++j)
-            if (tid + 256 * j < E.nblk) raw[j] = load_block<NSRC>(tb + loff[j]);
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            const uint32_t nt = hdir[j] < 8 ? e[hdir[j]] : kOutside;
-            if (nt != kOutside) {
-                hraw[j] = load_block<NSRC>(src + uint64_t(nt) * K + hoff[j]);
-            } else {
-#pragma unroll
-                for (int i = 0; i < NSRC; ++i) hraw[j].d[i] = 0;
-            }
-        }
-    };
-    if (R.first < R.end) {
-        locate(R.first, nbr[0]);
-        prefetch(nbr[0]);
-    }
-
-    const EdgeRecs<SR> grid{lds_e};
-    uint32_t it = 0;
-    for (uint64_t t64 = R.first; t64 < R.end; t64 += R.step, ++it) {
-        uint8_t *gout = dst + uint64_t(local) * K;
-        // 1. records of the tile's blocks (kept as rows) and of the halo blocks
-        uint32_t rows[BPT][BS];
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            if (tid + 256 * j < E.nblk) {
-                if (bnear[j]) shift_block<NSRC>(raw[j], E.nsh);
-                unpack_rows<BS, NSRC, SEL>(E, raw[j], rows[j]);
-                grid.put(own[j], edge_record<BS>(rows[j]));
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            if (hdir[j] < 8) {
-                if (hnear[j]) shift_block<NSRC>(hraw[j], E.nsh);
-                uint32_t hr[BS];
-                unpack_rows<BS, NSRC, SEL>(E, hraw[j], hr);
-                grid.put(hrec[j], edge_record<BS>(hr));
-            }
-        }
+    // Tile number i: its records are written (visible after the first
+    // barrier), P holds the loads of the next tile and Q's registers
+    // (consumed) take those of the tile after it; cl receives the entries of
+    // the tile four ahead, cw holds those of the tile three ahead.
+    uint32_t i = 0;
+    auto body = [&](Pending &Q, Pending &P, uint32_t &cl, const uint32_t &cw) -> bool {
+        uint8_t *gout = Q.dst + uint64_t(Q.local) * K;
         __syncthreads();
-        // 2. loads of the next tile
-        if (t64 + R.step < R.end) {
-            const uint32_t *e = nbr[(it + 1) & 1];
-            locate(t64 + R.step, e);
-            prefetch(e);
-        }
-        uint32_t nb2 = kOutside;
-        if (tid >= kLane0 && t64 + 2 * R.step < R.end) nb2 = entry(t64 + 2 * R.step, tid - kLane0);
-        // 3. the rule per block, next states straight to global memory
+        if (wave0) cl = entry(clamp(i + 4), lslot);
+        prefetch(Q, clamp(i + 2), nbr[(i + 2) & 3]);
+        // step 2: the rule per block, next states straight to global memory
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
-            if (tid + 256 * j < E.nblk) {
-                uint32_t next[4];
-                edge_block_rule<BS, EDGE, RULE, SR>(grid, nb[j], rows[j], rule, RT, next);
-                uint32_t w[4];
+            uint32_t next[4];
+            edge_block_rule<BS, EDGE, RULE, SR>(grid, nb[j], rows[j], rule, RT, next);
+            uint32_t w[4];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    uint32_t v = 0;
-                    if (SEL & (256u << d)) v = __builtin_amdgcn_perm(next[1], next[0], E.pack01[d]);
-                    if (BS >= 3 && (SEL & (4096u << d))) v |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
-                    w[d] = v;
-                }
-                store_cells<CBC>(w, CB, gout + boff[j]);
+            for (int d = 0; d < 4; ++d) {
+                uint32_t v = 0;
+                if (SEL & (256u << d)) v = __builtin_amdgcn_perm(next[1], next[0], E.pack01[d]);
+                if (BS >= 3 && (SEL & (4096u << d))) v |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
+                w[d] = v;
             }
+            store_cells<CBC>(w, CB, gout + boff[j]);
         }
         // the records are read until here; the next tile's come after
         __syncthreads();
-        if (tid >= kLane0) nbr[it & 1][tid - kLane0] = nb2;
+        if (wave0 && lane < kLanes) nbr[(i + 3) & 3][lane] = cw;
+        ++i;
+        if (first + i * step >= end) return false;
+        records(P);
+        return true;
+    };
+    for (;;) {
+        if (!body(P0, P1, c0, c1)) break;
+        if (!body(P1, P0, c1, c0)) break;
     }
 }
 
@@ -455,6 +559,9 @@ struct EdgeSpec {
     uint32_t BS, nsrc, CB, sel;
 };
 constexpr EdgeSpec kSpecTriangle{4, 4, 9, 0x6387u};
+// Blocks of 8 cells (the carpet F^{8,3} at block level 1): every block starts
+// 8-aligned, one aligned 8-byte load and store each (any selector mask).
+constexpr EdgeSpec kSpecEight{3, 2, 8, kAllSel};
 
 // shape: BS 3 or 4, and 2 or 4 source dwords per block
 template <bool BATCH, bool EDGE, int RULE>
@@ -469,6 +576,8 @@ static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t 
                                                                         caps, st)
     NBB_EDGES_SPEC(kSpecTriangle);
 #undef NBB_EDGES_SPEC
+    if (BS == kSpecEight.BS && nsrc == kSpecEight.nsrc && E.CB == kSpecEight.CB)
+        return launch_edges_s<3, 2, BATCH, EDGE, RULE, 8, kAllSel>(E, in, out, rule, rec, cu_count, caps, st);
     if (BS == 3 && nsrc == 2)
         return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, caps, st);
     if (BS == 3 && nsrc == 4)

@@ -1119,19 +1119,21 @@ static hipError_t launch_tiled_any(const MapParams &P, const TileParams &T, cons
     return hipErrorInvalidValue;
 }
 // Most resident work-groups per CU of the edge-record step (0: as many as
-// fit), for plans of one block per thread and of more.  Measured with the
-// records in block order: triangle r16 (one block per thread) 22.5 us per
-// generation with eight resident, 22.8 with seven; carpet r9 (two) 67.2 with
-// eight, 59.6 with seven, 61.6 with six.
+// fit), for plans of one block per thread and of more.  Measured with loads
+// two tiles ahead: triangle r16 (one block per thread) 20.4 us per
+// generation with eight resident or seven; carpet r9 (two) 50.9 with eight,
+// 52.1 with seven, 53.2 with six.
 #ifndef NBB_EDGES_MAX_PER_CU_ONE
 #define NBB_EDGES_MAX_PER_CU_ONE 8
 #endif
 #ifndef NBB_EDGES_MAX_PER_CU
-#define NBB_EDGES_MAX_PER_CU 7
+#define NBB_EDGES_MAX_PER_CU 8
 #endif
 static constexpr EdgeCaps kEdgesCaps{NBB_EDGES_MAX_PER_CU_ONE, NBB_EDGES_MAX_PER_CU};
-hipError_t launch_step_edges(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
-                             uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+hipError_t launch_step_edges(const EdgeParams &E0, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
+                             uint64_t limit, uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st) {
+    EdgeParams E = E0;
+    E.limit = limit;
     const bool edge = (rule >> 31) != 0;
     const int kind = edges_rule_kind(rule);
     const EdgeCaps mx = kEdgesCaps;

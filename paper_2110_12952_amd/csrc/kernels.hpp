@@ -43,9 +43,10 @@ hipError_t launch_step_tiled(const MapParams &P, const TileParams &T, const uint
                              uint32_t rule, int cu_count, hipStream_t st);
 // The tiled step in edge-record form (edges.hpp): BS 3 or 4, nsrc 2 or 4
 // source dwords per block; rec = NULL for one instance, else the batch's
-// per-tile records (E.nbr / E.ntiles then the batch's).
+// per-tile records (E.nbr / E.ntiles then the batch's).  limit: bytes of
+// `in` the step may read (the state's k^r, or the arena's length).
 hipError_t launch_step_edges(const EdgeParams &E, uint32_t BS, uint32_t nsrc, const uint8_t *in, uint8_t *out,
-                             uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st);
+                             uint64_t limit, uint32_t rule, const uint32_t *rec, int cu_count, hipStream_t st);
 // The tiled step over the tiles of a batch (tables from launch_batch_tiles,
 // T.ntiles = batch tiles, T.nbr = the batch neighbour table).
 hipError_t launch_step_tiled_batch(const TileParams &T, const uint32_t *rec, const uint8_t *arena_in,
