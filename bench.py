@@ -46,6 +46,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def warm_up(torch, run, steps, min_ms):
+    """Runs run(steps), then run(chunk) until min_ms of GPU time have passed
+    since the start; returns the number of steps run."""
+    done = 0
+    if steps:
+        run(steps)
+        done += steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = max(steps, 20)
+    while min_ms > 0 and (time.perf_counter() - t0) * 1e3 < min_ms:
+        run(chunk)
+        torch.cuda.synchronize()
+        done += chunk
+    return done
+
+
 def time_events(torch, fn, reps=1):
     """Milliseconds of fn() on the current stream, bracketed by HIP events."""
     s = torch.cuda.current_stream()
@@ -285,7 +302,7 @@ def serve_run(torch, W, args):
     return out
 
 
-def large_case(torch, N, W, name, rule, steps):
+def large_case(torch, N, W, name, rule, steps, warm_ms=50.0):
     """One of the HBM-sized workloads (carpet r = 9: 134M cells, H r = 10:
     282M cells; their double buffers exceed the 256 MB Infinity Cache): the
     compact step and the box step for `steps` generations each, per-generation
@@ -295,7 +312,7 @@ def large_case(torch, N, W, name, rule, steps):
     g = N.Fractal(fd.s, fd.offsets, wl.r)
     a = g.init_compact(wl.seeds[0], wl.p)
     b = torch.empty_like(a)
-    g.step_compact(a.clone(), b, 2, rule)
+    warm_up(torch, lambda n: g.step_compact(a.clone(), b, n, rule), 2, warm_ms)
     ms, res = time_events(torch, lambda: g.step_compact(a, b, steps, rule))
     alg = 2 * g.cells
     out = {"cells": g.cells, "n": g.n, "steps": steps, "tile_level": g.info().tile_level,
@@ -325,6 +342,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup-ms", type=float, default=100.0,
+                    help="after --warmup steps, keep warming up until this much time has passed")
     ap.add_argument("--workload", default="triangle_r16")
     ap.add_argument("--bbox-steps", type=int, default=None, help="box-step generations (default: --steps)")
     ap.add_argument("--map-reps", type=int, default=20)
@@ -387,8 +406,10 @@ def main():
     a = g.init_compact(wl.seeds[0], wl.p)
     b = torch.empty_like(a)
     init = a.clone()
-    if Wu:
-        g.step_compact(a.clone(), b, Wu, rule)
+    # untimed warm-up: the W steps asked for, then more until the GPU has run
+    # this step for --warmup-ms (its clocks ramp up over the first ~10 ms of
+    # sustained work; warmup_total_steps in the JSON line counts them all)
+    warm_steps = warm_up(torch, lambda n: g.step_compact(a.clone(), b, n, rule), Wu, args.warmup_ms)
     ms, res = time_events(torch, lambda: g.step_compact(a, b, K, rule))
     ms_step = ms / K
     value = g.cells * K / (ms * 1e-3)
@@ -558,6 +579,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": Wu,
+        "warmup_total_steps": warm_steps,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",

@@ -310,7 +310,12 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     // neighbour entries of four tiles in a ring (written by wavefront 0)
     __shared__ uint32_t nbr[4][kLanes];
     const uint32_t tid = threadIdx.x, lane = tid & 63;
-    const bool wave0 = __builtin_amdgcn_readfirstlane(tid) == 0;
+    // The halo items and the neighbour entries go to wavefronts that rotate
+    // with the work-group, so that no SIMD carries that work for every
+    // work-group on the CU.
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid) >> 6, rot = blockIdx.x & 3;
+    const bool went = wave == ((rot + 2) & 3);  // the neighbour entries
+    const uint32_t hslot = (((wave + 4 - rot) & 3) << 6) | lane;  // this thread's halo position
     const uint32_t K = E.K, CB = E.CB;
     const XcdRange R64 = xcd_range(blockIdx.x, gridDim.x, E.ntiles);
     // tile numbers fit 32 bits (E.ntiles does)
@@ -349,21 +354,21 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         own[j] = bi * 4;
         boff[j] = bi * CB;
     }
-    // Halo items: item h is thread h % 256's j = h / 256; only wavefronts
-    // that hold an item load and write them (a uniform branch).  A thread
-    // without an item loads its own block's window and writes to a record
-    // nobody reads (past the record of zeros).
+    // Halo items: item h is the thread with halo position h % 256, j = h /
+    // 256; only wavefronts that hold an item load and write them (a uniform
+    // branch).  A thread without an item loads its own block's window and
+    // writes to a record nobody reads (past the record of zeros).
     uint32_t hdir[HPT], hoff[HPT], hrec[HPT];
     bool hwave[HPT];
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
-        const uint32_t h = tid + 256 * j;
+        const uint32_t h = hslot + 256 * j;
         const bool ok = h < E.nhalo;
         const uint32_t w0 = ok ? E.halo[2 * h] : 0u, w1 = ok ? E.halo[2 * h + 1] : 0u;
         hdir[j] = ok ? (w0 >> 29) : 8u;  // 8: no item
         hoff[j] = (w0 & 0x1FFFFFFFu) * CB;
         hrec[j] = (ok ? (w1 & 0xFFFFu) : E.nblk + h + 1) * 4;
-        hwave[j] = __builtin_amdgcn_readfirstlane(tid) + 256 * j < E.nhalo;
+        hwave[j] = (hslot & ~63u) + 256 * j < E.nhalo;
     }
 
     // The loads of a tile, issued two tiles ahead of its rule.
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     Pending P0, P1;
     uint32_t c0 = 0, c1 = 0;
     const uint32_t lslot = lane < kLanes ? lane : 0u;
-    if (wave0) {
+    if (went) {
         const uint32_t e0 = entry(clamp(0), lslot), e1 = entry(clamp(1), lslot), e2 = entry(clamp(2), lslot);
         c1 = entry(clamp(3), lslot);
         if (lane < kLanes) {
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     auto body = [&](Pending &Q, Pending &P, uint32_t &cl, const uint32_t &cw) -> bool {
         uint8_t *gout = Q.dst + uint64_t(Q.local) * K;
         __syncthreads();
-        if (wave0) cl = entry(clamp(i + 4), lslot);
+        if (went) cl = entry(clamp(i + 4), lslot);
         prefetch(Q, clamp(i + 2), nbr[(i + 2) & 3]);
         // step 2: the rule per block, next states straight to global memory
 #pragma unroll
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         }
         // the records are read until here; the next tile's come after
         __syncthreads();
-        if (wave0 && lane < kLanes) nbr[(i + 3) & 3][lane] = cw;
+        if (went && lane < kLanes) nbr[(i + 3) & 3][lane] = cw;
         ++i;
         if (first + i * step >= end) return false;
         records(P);
