@@ -300,12 +300,13 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
     // window loads per block, dwords of block bytes used, and whether a
     // window ended at the readable end can leave the block 8 or more bytes in
-    // (blocks of 8 cells start 8-aligned: tiles hold a multiple of 8 cells
-    // and states start 16-aligned, so their window is the block itself)
-    constexpr bool kA8 = CBC == 8;
-    constexpr int NW = kA8 ? 1 : ((NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
+    // (blocks of 4, 8 or 16 cells start aligned to their size: tiles hold a
+    // multiple of CB cells and states start 16-aligned, so their window is
+    // the block itself)
+    constexpr bool kAW = CBC == 4 || CBC == 8 || CBC == 16;
+    constexpr int NW = kAW ? (CBC == 16 ? 2 : 1) : ((NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
     constexpr int NOUT = CBC ? (CBC + 3) / 4 : NSRC;
-    constexpr bool kWide = !kA8 && !(CBC && 8 * NW - CBC < 8);
+    constexpr bool kWide = !kAW && !(CBC && 8 * NW - CBC < 8);
     constexpr uint32_t WB = 8 * NW;
     // neighbour entries of four tiles in a ring (written by wavefront 0)
     __shared__ uint32_t nbr[4][kLanes];
@@ -343,10 +344,14 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     // and stores the same values as that block's own thread, so that no load,
     // store or use of a loaded register sits behind a per-thread branch and
     // the compiler's waits for outstanding memory operations count exactly.
+    // For j >= 1 a wavefront none of whose threads has a j-th block of its
+    // own skips that block altogether (a uniform branch).
     EdgeNbrs nb[BPT];
     uint32_t own[BPT], boff[BPT];
+    bool bwave[BPT];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
+        bwave[j] = j == 0 || (wave << 6) + 256 * j < E.nblk;
         const uint32_t bi = (tid + 256 * j) % E.nblk;
         const uint4 w = *reinterpret_cast<const uint4 *>(E.blk + 4 * bi);
         nb[j] = EdgeNbrs{(w.x & 0xFFFFu) * 4, (w.x >> 16) * 4, (w.y & 0xFFFFu) * 4, (w.y >> 16) * 4,
@@ -383,9 +388,11 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     // 8-byte boundary at or below the block, or ending at the readable end
     auto window = [&](const uint8_t *src, uint32_t off, uint32_t lim, bool may_end) -> Window<NW> {
         Window<NW> w;
-        if (kA8) {
+        if (kAW) {
             w.sh = 0;
-            __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, 8), 8);
+            w.d[2 * NW - 1] = 0;
+            constexpr int kB = kAW ? CBC : 4;  // (the branch is not taken otherwise)
+            __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, kB), kB);
             return w;
         }
         const uint32_t sh = (uint32_t(reinterpret_cast<uintptr_t>(src)) + off) & 7u;
@@ -410,7 +417,8 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         const uint32_t toff = P.local * K;
         const bool tail = toff + K > P.lim - WB;  // uniform
 #pragma unroll
-        for (int j = 0; j < BPT; ++j) P.raw[j] = window(P.src, toff + boff[j], P.lim, tail);
+        for (int j = 0; j < BPT; ++j)
+            if (bwave[j]) P.raw[j] = window(P.src, toff + boff[j], P.lim, tail);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hwave[j]) {
@@ -421,10 +429,10 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         }
     };
     auto aligned = [&](const Window<NW> &w) -> RawBlock<NSRC> {
-        if (kA8) {
+        if (kAW) {
             RawBlock<NSRC> r;
 #pragma unroll
-            for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 ? w.d[i < 2 * NW ? i : 0] : 0u;
+            for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 * NW ? w.d[i < 2 * NW ? i : 0] : 0u;
             return r;
         }
         if (kWide && any_wide<NW>(w)) return align_window<NSRC, NW, NOUT, true>(w);
@@ -436,6 +444,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     auto records = [&](Pending &P) {
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
+            if (!bwave[j]) continue;
             unpack_rows<BS, NSRC, SEL>(E, aligned(P.raw[j]), rows[j]);
             grid.put(own[j], edge_record<BS>(rows[j]));
         }
@@ -484,6 +493,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         // step 2: the rule per block, next states straight to global memory
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
+            if (!bwave[j]) continue;
             uint32_t next[4];
             edge_block_rule<BS, EDGE, RULE, SR>(grid, nb[j], rows[j], rule, RT, next);
             uint32_t w[4];
@@ -564,9 +574,12 @@ struct EdgeSpec {
     uint32_t BS, nsrc, CB, sel;
 };
 constexpr EdgeSpec kSpecTriangle{4, 4, 9, 0x6387u};
-// Blocks of 8 cells (the carpet F^{8,3} at block level 1): every block starts
-// 8-aligned, one aligned 8-byte load and store each (any selector mask).
+// Blocks of 4, 8 or 16 cells (the chandelier-like F^{4,3} and the carpet
+// F^{8,3} at block level 1, the full square at level 2): every block starts
+// aligned to its size, one aligned load and store each (any selector mask).
+constexpr EdgeSpec kSpecFour{3, 2, 4, kAllSel};
 constexpr EdgeSpec kSpecEight{3, 2, 8, kAllSel};
+constexpr EdgeSpec kSpecSixteen{4, 4, 16, kAllSel};
 
 // shape: BS 3 or 4, and 2 or 4 source dwords per block
 template <bool BATCH, bool EDGE, int RULE>
@@ -581,8 +594,13 @@ static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t 
                                                                         caps, st)
     NBB_EDGES_SPEC(kSpecTriangle);
 #undef NBB_EDGES_SPEC
-    if (BS == kSpecEight.BS && nsrc == kSpecEight.nsrc && E.CB == kSpecEight.CB)
-        return launch_edges_s<3, 2, BATCH, EDGE, RULE, 8, kAllSel>(E, in, out, rule, rec, cu_count, caps, st);
+#define NBB_EDGES_ALIGNED(P)                                                                                     \
+    if (BS == P.BS && nsrc == P.nsrc && E.CB == P.CB)                                                           \
+    return launch_edges_s<P.BS, P.nsrc, BATCH, EDGE, RULE, P.CB, kAllSel>(E, in, out, rule, rec, cu_count, caps, st)
+    NBB_EDGES_ALIGNED(kSpecFour);
+    NBB_EDGES_ALIGNED(kSpecEight);
+    NBB_EDGES_ALIGNED(kSpecSixteen);
+#undef NBB_EDGES_ALIGNED
     if (BS == 3 && nsrc == 2)
         return launch_edges_s<3, 2, BATCH, EDGE, RULE>(E, in, out, rule, rec, cu_count, caps, st);
     if (BS == 3 && nsrc == 4)
