@@ -380,6 +380,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     struct Pending {
         Window<NW> raw[BPT], hraw[HPT];
         bool hok[HPT];
+        bool tail;  // the tile's own windows may end at the readable end
         const uint8_t *src;  // the state the tile belongs to
         uint8_t *dst;
         uint32_t local, lim;  // local tile number, readable bytes from src
@@ -416,6 +417,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         P.lim = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(room);
         const uint32_t toff = P.local * K;
         const bool tail = toff + K > P.lim - WB;  // uniform
+        P.tail = tail;
 #pragma unroll
         for (int j = 0; j < BPT; ++j)
             if (bwave[j]) P.raw[j] = window(P.src, toff + boff[j], P.lim, tail);
@@ -428,14 +430,14 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             }
         }
     };
-    auto aligned = [&](const Window<NW> &w) -> RawBlock<NSRC> {
+    auto aligned = [&](const Window<NW> &w, bool may_be_wide) -> RawBlock<NSRC> {
         if (kAW) {
             RawBlock<NSRC> r;
 #pragma unroll
             for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 * NW ? w.d[i < 2 * NW ? i : 0] : 0u;
             return r;
         }
-        if (kWide && any_wide<NW>(w)) return align_window<NSRC, NW, NOUT, true>(w);
+        if (kWide && may_be_wide && any_wide<NW>(w)) return align_window<NSRC, NW, NOUT, true>(w);
         return align_window<NSRC, NW, NOUT, false>(w);
     };
     const EdgeRecs<SR> grid{lds_e};
@@ -445,14 +447,14 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
             if (!bwave[j]) continue;
-            unpack_rows<BS, NSRC, SEL>(E, aligned(P.raw[j]), rows[j]);
+            unpack_rows<BS, NSRC, SEL>(E, aligned(P.raw[j], P.tail), rows[j]);
             grid.put(own[j], edge_record<BS>(rows[j]));
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hwave[j]) {
                 uint32_t hr[BS];
-                unpack_rows<BS, NSRC, SEL>(E, aligned(P.hraw[j]), hr);
+                unpack_rows<BS, NSRC, SEL>(E, aligned(P.hraw[j], true), hr);
                 grid.put(hrec[j], edge_record<BS>(hr));
                 // an item whose neighbour tile does not exist is a block of zeros
                 if (!P.hok[j]) grid.put(hrec[j], make_uint4(0, 0, 0, 0));
@@ -567,13 +569,19 @@ static hipError_t launch_edges_s(const EdgeParams &E, const uint8_t *in, uint8_t
 // block, selector mask).  The triangle F^{3,2} with offsets (0,0), (1,0),
 // (0,1) at block level 2 needs 4 of the 8 unpacking and 5 of the 12 packing
 // permutes and stores 8 + 1 bytes per block: 25.0 us per generation at r16
-// against 26.3 in the general form.  (Compiled the same way for the carpet
-// at level 1 it ran 62.7 us against 61.5, so the carpet, H and chandelier
-// plans keep the general form.)  Any other plan takes the general form.
+// against 26.3 in the general form (before loads ran two tiles ahead).  Any
+// other plan takes the general form.
 struct EdgeSpec {
     uint32_t BS, nsrc, CB, sel;
 };
 constexpr EdgeSpec kSpecTriangle{4, 4, 9, 0x6387u};
+// The same for the other fractals of the batched and served workloads at
+// block level 1: the carpet F^{8,3}, the H F^{7,3} and the chandelier-like
+// F^{4,3} (whose third block row holds no cell; chandelier r13 at level 5:
+// 36.2 -> 31.2 us per generation, H r10 forced into this form 176 -> 172).
+constexpr EdgeSpec kSpecCarpet{3, 2, 8, 0x2307u};
+constexpr EdgeSpec kSpecH{3, 2, 7, 0x3307u};
+constexpr EdgeSpec kSpecChandelier{3, 2, 4, 0x0103u};
 // Blocks of 4, 8 or 16 cells (the chandelier-like F^{4,3} and the carpet
 // F^{8,3} at block level 1, the full square at level 2): every block starts
 // aligned to its size, one aligned load and store each (any selector mask).
@@ -593,6 +601,9 @@ static hipError_t launch_edges_shape(const EdgeParams &E, uint32_t BS, uint32_t 
     return launch_edges_s<P.BS, P.nsrc, BATCH, EDGE, RULE, P.CB, P.sel>(E, in, out, rule, rec, cu_count,         \
                                                                         caps, st)
     NBB_EDGES_SPEC(kSpecTriangle);
+    NBB_EDGES_SPEC(kSpecCarpet);
+    NBB_EDGES_SPEC(kSpecH);
+    NBB_EDGES_SPEC(kSpecChandelier);
 #undef NBB_EDGES_SPEC
 #define NBB_EDGES_ALIGNED(P)                                                                                     \
     if (BS == P.BS && nsrc == P.nsrc && E.CB == P.CB)                                                           \
