@@ -513,11 +513,10 @@ const char *nbb_status_string(nbb_status s);
  * block.
  *   edge_blk[4b .. 4b+3] = the records of block b's neighbours, two per word
  *   (low half first): left | right, above | below, above-left | above-right,
- *   below-left | below-right (a block's 4 edge_nsrc-byte load passes the
- *   tile's end when b * cells per block + 4 edge_nsrc > tile_cells; it loads
- *   the bytes ending at its last cell instead);
+ *   below-left | below-right (the step reads a block's bytes as edge_nsrc
+ *   dwords through one aligned load of the 8-byte window holding them);
  *   edge_halo[2h] = direction << 29 | block of that neighbour tile,
- *   edge_halo[2h+1] = record | near << 31, for edge_halo_count items;
+ *   edge_halo[2h+1] = its record, for edge_halo_count items;
  *   edge_unpack / edge_pack: the v_perm selectors from a block's bytes to its
  *   rows and from next-state rows back to compact order ([0..3] for rows or
  *   output dwords 0-3 from the first pair of sources, [4..7] from the second).
@@ -532,7 +531,7 @@ typedef struct {
     const uint32_t *halo_src;
     const uint32_t *halo_dst;
     const uint32_t *nbr;
-    uint32_t edge_ok, edge_grid, edge_records, edge_rec_bytes, edge_halo_count, edge_nsrc, edge_nsh;
+    uint32_t edge_ok, edge_grid, edge_records, edge_rec_bytes, edge_halo_count, edge_nsrc;
     uint32_t edge_unpack[8], edge_pack[8];
     const uint32_t *edge_blk;
     const uint32_t *edge_halo;

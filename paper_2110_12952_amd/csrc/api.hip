@@ -317,7 +317,6 @@ nbb_status upload_edges(const EdgePlan &p, const TileParams &T, DevBlob *blob, E
     E->nhalo = p.nhalo;
     E->ntiles = T.ntiles;
     E->rec_bytes = p.rec_bytes;
-    E->nsh = p.nsh;
     std::memcpy(E->unpack01, p.unpack01, sizeof(E->unpack01));
     std::memcpy(E->unpack23, p.unpack23, sizeof(E->unpack23));
     std::memcpy(E->pack01, p.pack01, sizeof(E->pack01));
@@ -490,7 +489,6 @@ nbb_status nbb_plan_build(uint32_t k, uint32_t s, const int32_t *offsets, uint32
     view->edge_rec_bytes = e.rec_bytes;
     view->edge_halo_count = e.nhalo;
     view->edge_nsrc = e.nsrc;
-    view->edge_nsh = e.nsh;
     for (int i = 0; i < 4; ++i) {
         view->edge_unpack[i] = e.unpack01[i];
         view->edge_unpack[4 + i] = e.unpack23[i];

@@ -116,12 +116,11 @@ struct EdgeParams {
     uint32_t K, CB, nblk, nhalo;
     uint32_t ntiles;        // tiles of the launch (batch tiles for a batch)
     uint32_t rec_bytes;     // 16 bytes per record (four dword arrays), rounded up to 4 records
-    uint32_t nsh;           // 4 NSRC - CB (the plan's; the step's windows do not use it)
     uint32_t unpack01[4], unpack23[4];  // v_perm selectors: row r = perm(c1, c0, u01[r]) | perm(c3, c2, u23[r])
     uint32_t pack01[4], pack23[4];      // compact dword d = perm(n1, n0, p01[d]) | perm(n3, n2, p23[d])
     const uint32_t *blk;    // 4 per block: the records left | right << 16, above | below << 16,
                             // above-left | above-right << 16, below-left | below-right << 16
-    const uint32_t *halo;   // 2 per item: direction << 29 | local block, record (| near << 31, unused)
+    const uint32_t *halo;   // 2 per item: direction << 29 | local block, record
     const uint32_t *nbr;    // 8 neighbour tiles per tile (0xFFFFFFFF = none)
     uint64_t limit;         // bytes of the input that may be read (the state, or the whole arena)
 };

@@ -489,7 +489,6 @@ bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg
     p->G = G;
     p->nblk = uint32_t(nb);
     p->nsrc = nsrc;
-    p->nsh = LW - CB;
     // block slots: block b of the tile sits at lambda_{m-q}(b) on the G x G grid
     const int64_t Gi = G;
     std::vector<int32_t> own(size_t(G + 2) * (G + 2), -1);  // (Y+1)*(G+2) + X+1 -> block
@@ -558,10 +557,8 @@ bool build_edge_plan(const Fractal &f, uint32_t m, EdgePlan *p, std::string *msg
     }
     p->halo.resize(2 * size_t(p->nhalo));
     for (uint32_t h = 0; h < p->nhalo; ++h) {
-        const uint32_t lb = hd[h] & 0x1FFFFFFFu;
-        const uint32_t near = uint64_t(lb) * CB + LW > K ? 1u : 0u;
         p->halo[2 * h] = hd[h];
-        p->halo[2 * h + 1] = (p->nblk + h) | (near << 31);
+        p->halo[2 * h + 1] = p->nblk + h;
     }
     // v_perm selectors: byte c of row r is cell bid(c, r) of the block's CB
     // bytes (dwords c0..c3), 12 (a zero byte) where the block has no cell

@@ -76,7 +76,6 @@ struct EdgePlan {
     uint32_t nsrc = 0;      // dwords per block load: 2 (3 x 3 blocks of at most 8 cells) or 4
     uint32_t nrec = 0;      // records: the blocks, the halo items and one of zeros
     uint32_t rec_bytes = 0; // 16 bytes per record, rounded up to 4 records
-    uint32_t nsh = 0;       // 4 nsrc - CB
     uint32_t unpack01[4] = {}, unpack23[4] = {}, pack01[4] = {}, pack23[4] = {};
     std::vector<uint32_t> blk;   // 4 per block, see EdgeParams
     std::vector<uint32_t> halo;  // 2 per halo item, see EdgeParams

@@ -71,7 +71,7 @@ class PlanView(ctypes.Structure):
                 ("nbr", ctypes.POINTER(ctypes.c_uint32)),
                 ("edge_ok", ctypes.c_uint32), ("edge_grid", ctypes.c_uint32), ("edge_records", ctypes.c_uint32),
                 ("edge_rec_bytes", ctypes.c_uint32), ("edge_halo_count", ctypes.c_uint32),
-                ("edge_nsrc", ctypes.c_uint32), ("edge_nsh", ctypes.c_uint32),
+                ("edge_nsrc", ctypes.c_uint32),
                 ("edge_unpack", ctypes.c_uint32 * 8), ("edge_pack", ctypes.c_uint32 * 8),
                 ("edge_blk", ctypes.POINTER(ctypes.c_uint32)), ("edge_halo", ctypes.POINTER(ctypes.c_uint32))]
 
@@ -236,7 +236,7 @@ def plan_tables(s: int, offsets: Sequence[Tuple[int, int]], r: int, tile_level: 
         out["nbr"] = np.ctypeslib.as_array(v.nbr, (int(v.tiles) * 8,)).copy()
         out["edge_ok"] = bool(v.edge_ok)
         if v.edge_ok:
-            for f in ("edge_grid", "edge_records", "edge_rec_bytes", "edge_halo_count", "edge_nsrc", "edge_nsh"):
+            for f in ("edge_grid", "edge_records", "edge_rec_bytes", "edge_halo_count", "edge_nsrc"):
                 out[f] = getattr(v, f)
             out["edge_unpack"] = np.array(list(v.edge_unpack), np.uint32)
             out["edge_pack"] = np.array(list(v.edge_pack), np.uint32)

@@ -1,9 +1,10 @@
 """The edge-record form's host plan, checked on the CPU.
 
-The plan (neighbour records, halo items, near-end loads, v_perm selectors) is read
-through nbb_plan_build and driven by a numpy model of the kernel's data
-movement: every block's bytes are loaded as the kernel loads them (4*nsrc
-bytes, the near-end ones ending at their last cell and shifted down), turned
+The plan (neighbour records, halo items, v_perm selectors) is read through
+nbb_plan_build and driven by a numpy model of the kernel's data movement:
+every block's bytes are loaded as the kernel loads them (the aligned 8-byte
+window holding them, or the window ending at the state's end, moved down to
+the block's first byte; blocks of 4, 8 or 16 cells read whole), turned
 into rows and edge records with the plan's selectors, the records numbered
 per tile as the kernel numbers them (blocks, then halo items, then one of
 zeros), each block's window read back from its own rows and the neighbouring
@@ -51,13 +52,46 @@ def alignbyte(hi, lo, sh):
     return ((v >> np.uint64(8 * sh)) & np.uint64(0xFFFFFFFF)).astype(U32)
 
 
-def load_dwords(state, offs, nsrc):
-    """nsrc little-endian dwords from byte offsets offs of state (must stay inside)."""
-    if offs.size == 0:
+def window_bytes(p, BS, CB, nsrc):
+    """The window the kernel reads a block through: 16 bytes for two source
+    dwords and for the form compiled for the triangle's plan (4 x 4 blocks of
+    9 cells, selector mask 0x6387), else 24."""
+    sel = 0
+    for i in range(4):
+        sel |= int(p["edge_unpack"][i] != 0x0C0C0C0C) << i
+        sel |= int(p["edge_unpack"][4 + i] != 0x0C0C0C0C) << (4 + i)
+        sel |= int(p["edge_pack"][i] != 0x0C0C0C0C) << (8 + i)
+        sel |= int(p["edge_pack"][4 + i] != 0x0C0C0C0C) << (12 + i)
+    return 16 if (nsrc == 2 or (BS == 4 and CB == 9 and sel == 0x6387)) else 24
+
+
+def load_blocks(state, offs, CB, nsrc, WB):
+    """nsrc little-endian dwords of each block at byte offset offs, as the
+    kernel assembles them: blocks of 4, 8 or 16 cells whole (the rest zero);
+    others from the 8-byte aligned window of WB bytes at or below the block,
+    or the window ending
+    at the state's end when that one would pass it, moved down to the block's
+    first byte (bytes past the window zero).  Every read stays inside the
+    state (the state starts 16-byte aligned, so offsets and addresses agree
+    modulo 8)."""
+    n = offs.size
+    out = np.zeros((n, 4 * nsrc), np.uint64)
+    if n == 0:
         return np.zeros((0, nsrc), U32)
-    assert offs.min() >= 0 and offs.max() + 4 * nsrc <= state.size
-    b = state[offs[:, None] + np.arange(4 * nsrc)[None, :]].astype(np.uint64)
-    b = b.reshape(-1, nsrc, 4)
+    if CB in (4, 8, 16):
+        assert (offs % CB == 0).all() and offs.max() + CB <= state.size
+        out[:, :CB] = state[offs[:, None] + np.arange(CB)[None, :]]
+    else:
+        s = offs - offs % 8
+        s = np.where(s + WB > state.size, state.size - WB, s)
+        assert s.min() >= 0 and (s + WB <= state.size).all()
+        win = state[s[:, None] + np.arange(WB)[None, :]].astype(np.uint64)
+        sh = offs - s
+        take = np.minimum(4 * nsrc, WB - sh)
+        for i in range(4 * nsrc):
+            ok = i < take
+            out[ok, i] = win[np.nonzero(ok)[0], sh[ok] + i]
+    b = out.reshape(-1, nsrc, 4)
     return (b[..., 0] | (b[..., 1] << 8) | (b[..., 2] << 16) | (b[..., 3] << 24)).astype(U32)
 
 
@@ -94,10 +128,9 @@ def model_step(fd, r, state, rule, m=0):
     assert p["edge_ok"]
     K, BS, nb, T = p["tile_cells"], p["block_side"], p["blocks"], int(p["tiles"])
     CB = fd.k ** p["block_level"]
-    nsrc, nsh = p["edge_nsrc"], p["edge_nsh"]
+    nsrc = p["edge_nsrc"]
     assert (BS, nsrc) in ((3, 2), (3, 4), (4, 4))  # the shapes the library instantiates
-    LW = 4 * nsrc
-    assert nsh == LW - CB
+    assert CB <= 4 * nsrc
     nh = p["edge_halo_count"]
     nrec = p["edge_records"]
     assert nrec == nb + nh + 1 and p["edge_rec_bytes"] == 16 * ((nrec + 3) // 4 * 4)
@@ -106,31 +139,26 @@ def model_step(fd, r, state, rule, m=0):
     # above-right, below-left, below-right
     nbrec = np.stack([blk[:, i // 2] >> (16 * (i % 2)) & 0xFFFF for i in range(8)], axis=1).astype(np.int64)
     assert nbrec.max() < nrec
-    bnear = np.arange(nb) * CB + LW > K
     rec = np.zeros((T, nrec, 4), U32)  # the last record stays zero
     tiles = np.arange(T)
     # own blocks: loads, rows, records
-    off = tiles[:, None] * K + (np.arange(nb) * CB - np.where(bnear, nsh, 0))[None, :]
-    raw = load_dwords(state, off.ravel(), nsrc)
-    near = np.broadcast_to(bnear[None, :], (T, nb)).ravel()
-    if near.any():
-        raw[near] = shift(raw[near], nsh, nsrc)
+    off = tiles[:, None] * K + (np.arange(nb) * CB)[None, :]
+    WB = window_bytes(p, BS, CB, nsrc)
+    raw = load_blocks(state, off.ravel(), CB, nsrc, WB)
     rows = unpack(p, raw, BS)
     rec[np.repeat(tiles, nb), np.tile(np.arange(nb), T)] = record(rows, BS)
     # halo items
     if nh:
         hal = p["edge_halo"].reshape(nh, 2)
         hdir, hlb = hal[:, 0] >> 29, hal[:, 0] & 0x1FFFFFFF
-        hslot, hnear = hal[:, 1] & 0xFFFF, (hal[:, 1] >> 31).astype(bool)
+        hslot = hal[:, 1]
         assert (hslot == nb + np.arange(nh)).all()
         nbr = p["nbr"].reshape(T, 8)
         nt = nbr[:, hdir]  # T x nh
         ok = nt != 0xFFFFFFFF
         tt, hh = np.nonzero(ok)
-        hoff = nt[tt, hh].astype(np.int64) * K + hlb[hh].astype(np.int64) * CB - np.where(hnear[hh], nsh, 0)
-        hraw = load_dwords(state, hoff, nsrc)
-        if hnear[hh].any():
-            hraw[hnear[hh]] = shift(hraw[hnear[hh]], nsh, nsrc)
+        hoff = nt[tt, hh].astype(np.int64) * K + hlb[hh].astype(np.int64) * CB
+        hraw = load_blocks(state, hoff, CB, nsrc, WB)
         rec[tt, hslot[hh]] = record(unpack(p, hraw, BS), BS)
     # the rule per block, read as the kernel reads
     R = rec.reshape(T, nrec * 4)
@@ -195,16 +223,9 @@ def rule_dword(n, o, rule):
     return v.astype(U32)
 
 
-def shift(raw, sh, nsrc):
-    d = np.concatenate([raw, np.zeros((raw.shape[0], 1), U32)], axis=1)
-    q, b = sh // 4, sh % 4
-    d = np.concatenate([d[:, q:], np.zeros((raw.shape[0], q), U32)], axis=1)
-    return np.stack([alignbyte(d[:, i + 1], d[:, i], b) for i in range(nsrc)], axis=1)
-
-
 # (fractal, r, tile level): the workloads' levels and tile sizes around them,
 # fractals whose blocks need four source dwords (triangle, grid4_12,
-# fullsquare) or two, near-end blocks (CB not a multiple of the load width),
+# fullsquare) or two, windows that end at the state's end,
 # sparse grids whose blocks often border no block (chandelier, cantor dust)
 CASES = [("triangle", 7, 7), ("triangle", 9, 7), ("triangle", 10, 5), ("triangle", 12, 6), ("carpet", 4, 4),
          ("carpet", 5, 3), ("carpet", 6, 4), ("hfractal", 5, 4), ("hfractal", 6, 3), ("chandelier", 7, 5),
