@@ -77,8 +77,9 @@ __device__ __forceinline__ Window<NW> load_window(const uint8_t *p, const uint8_
     return w;
 }
 // The block's bytes from byte 0 (dword i = bytes 4i..4i+3, NOUT dwords
-// used).  WIDE: sh may exceed 7 (a window ended at `lim`), else sh < 8.
-template <int NSRC, int NW, int NOUT, bool WIDE>
+// used).  STAGES: how many dword moves (by 1, 2, 4) sh may need: 0 when
+// sh < 4, 1 when sh < 8, 3 for any sh (a window ended at `lim`).
+template <int NSRC, int NW, int NOUT, int STAGES>
 __device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
     constexpr int ND = 2 * NW;
     RawBlock<NSRC> r;
@@ -91,7 +92,7 @@ __device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
     for (int i = 0; i < ND; ++i) x[i] = w.d[i];
     x[ND] = 0;
 #pragma unroll
-    for (int b = 0; b < (WIDE ? 3 : 1); ++b) {
+    for (int b = 0; b < STAGES; ++b) {
         const int m = 1 << b;
         if (m >= ND) break;
         const bool on = (h >> b) & 1;
@@ -102,10 +103,10 @@ __device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
     for (int i = 0; i < NSRC; ++i) r.d[i] = i < NOUT ? alignbyte(x[i + 1], x[i], w.sh & 3) : 0u;
     return r;
 }
-// Whether any thread of the wavefront holds a window that needs the wide form.
+// Whether any thread of the wavefront holds a window with sh >= limit.
 template <int NW>
-__device__ __forceinline__ bool any_wide(const Window<NW> &w) {
-    return __builtin_amdgcn_ballot_w64(w.sh >= 8) != 0;
+__device__ __forceinline__ bool any_wide(const Window<NW> &w, uint32_t limit) {
+    return __builtin_amdgcn_ballot_w64(w.sh >= limit) != 0;
 }
 
 // SEL: which of the plan's v_perm selectors pick any byte (bit r: unpack01[r],
@@ -304,9 +305,15 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     // multiple of CB cells and states start 16-aligned, so their window is
     // the block itself)
     constexpr bool kAW = CBC == 4 || CBC == 8 || CBC == 16;
-    constexpr int NW = kAW ? (CBC == 16 ? 2 : 1) : ((NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
+    // (blocks of at most 13 cells whose count is known: a 16-byte window from
+    // the 4-byte boundary at or below the block, so that v_alignbyte alone
+    // moves it into place; 4-aligned 16-byte loads measured as cheap as
+    // 8-aligned ones)
+    constexpr bool kA4 = !kAW && CBC && CBC <= 13;
+    constexpr int NW = kAW ? (CBC == 16 ? 2 : 1) : ((kA4 || NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
     constexpr int NOUT = CBC ? (CBC + 3) / 4 : NSRC;
-    constexpr bool kWide = !kAW && !(CBC && 8 * NW - CBC < 8);
+    constexpr uint32_t kAlign = kA4 ? 4 : 8;  // window start alignment
+    constexpr bool kWide = !kAW && !(CBC && 8 * NW - CBC < kAlign);
     constexpr uint32_t WB = 8 * NW;
     // neighbour entries of four tiles in a ring (written by wavefront 0)
     __shared__ uint32_t nbr[4][kLanes];
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, kB), kB);
             return w;
         }
-        const uint32_t sh = (uint32_t(reinterpret_cast<uintptr_t>(src)) + off) & 7u;
+        const uint32_t sh = (uint32_t(reinterpret_cast<uintptr_t>(src)) + off) & (kAlign - 1);
         uint32_t s = off - sh;
         if (may_end) s = s > lim - WB ? lim - WB : s;
         w.sh = off - s;
@@ -437,8 +444,8 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 * NW ? w.d[i < 2 * NW ? i : 0] : 0u;
             return r;
         }
-        if (kWide && may_be_wide && any_wide<NW>(w)) return align_window<NSRC, NW, NOUT, true>(w);
-        return align_window<NSRC, NW, NOUT, false>(w);
+        if (kWide && may_be_wide && any_wide<NW>(w, kAlign)) return align_window<NSRC, NW, NOUT, 3>(w);
+        return align_window<NSRC, NW, NOUT, kA4 ? 0 : 1>(w);
     };
     const EdgeRecs<SR> grid{lds_e};
     // step 1 of a tile: the records of its blocks (kept as rows) and halo blocks
