@@ -56,32 +56,22 @@ struct RawBlock {
     uint32_t d[NSRC];
 };
 
-// A block's CB bytes are read through one load of WB = 8 NW bytes (NW = 2
-// covers CB <= 9, NW = 3 CB <= 17) from the 8-byte boundary at or below its
-// first byte: unaligned loads cost the vector memory unit about three times
-// as much as aligned ones.  A window that would run past `lim` (the end of
-// the readable bytes, in the state's or arena's last tile only) ends there
-// instead.  sh = offset of the block's first byte in the window.
-template <int NW>
+// A block's CB bytes are read through one load of a window of ND dwords
+// that holds them, from the 4- or 8-byte boundary at or below its first byte:
+// unaligned loads cost the vector memory unit about three times as much as
+// aligned ones.  A window that would run past the end of the readable bytes
+// (in the state's or arena's last tile only) ends there instead.
+// sh = offset of the block's first byte in the window.
+template <int ND>
 struct Window {
-    uint32_t d[2 * NW];
+    uint32_t d[ND];
     uint32_t sh;
 };
-template <int NW>
-__device__ __forceinline__ Window<NW> load_window(const uint8_t *p, const uint8_t *lim) {
-    Window<NW> w;
-    const uint8_t *s = p - (uint32_t(reinterpret_cast<uintptr_t>(p)) & 7u);
-    if (s + 8 * NW > lim) s = lim - 8 * NW;  // a select, not a branch
-    w.sh = uint32_t(p - s);
-    __builtin_memcpy(w.d, s, 8 * NW);
-    return w;
-}
 // The block's bytes from byte 0 (dword i = bytes 4i..4i+3, NOUT dwords
 // used).  STAGES: how many dword moves (by 1, 2, 4) sh may need: 0 when
 // sh < 4, 1 when sh < 8, 3 for any sh (a window ended at `lim`).
-template <int NSRC, int NW, int NOUT, int STAGES>
-__device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
-    constexpr int ND = 2 * NW;
+template <int NSRC, int ND, int NOUT, int STAGES>
+__device__ __forceinline__ RawBlock<NSRC> align_window(const Window<ND> &w) {
     RawBlock<NSRC> r;
     const uint32_t h = w.sh >> 2;
     // dwords h.. of the window, moved down by one, two and four dwords as
@@ -100,12 +90,12 @@ __device__ __forceinline__ RawBlock<NSRC> align_window(const Window<NW> &w) {
         for (int i = 0; i <= ND; ++i) x[i] = on ? (i + m <= ND ? x[i + m] : 0u) : x[i];
     }
 #pragma unroll
-    for (int i = 0; i < NSRC; ++i) r.d[i] = i < NOUT ? alignbyte(x[i + 1], x[i], w.sh & 3) : 0u;
+    for (int i = 0; i < NSRC; ++i) r.d[i] = i < NOUT ? alignbyte(x[i + 1], x[i], w.sh) : 0u;  // (uses sh & 3)
     return r;
 }
 // Whether any thread of the wavefront holds a window with sh >= limit.
-template <int NW>
-__device__ __forceinline__ bool any_wide(const Window<NW> &w, uint32_t limit) {
+template <int ND>
+__device__ __forceinline__ bool any_wide(const Window<ND> &w, uint32_t limit) {
     return __builtin_amdgcn_ballot_w64(w.sh >= limit) != 0;
 }
 
@@ -299,22 +289,21 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                                                     const uint32_t *__restrict__ rec) {
     extern __shared__ __align__(16) uint8_t lds_e[];
     constexpr uint32_t kLanes = BATCH ? 10 : 8;  // neighbour tiles (+ record) per tile
-    // window loads per block, dwords of block bytes used, and whether a
-    // window ended at the readable end can leave the block 8 or more bytes in
-    // (blocks of 4, 8 or 16 cells start aligned to their size: tiles hold a
-    // multiple of CB cells and states start 16-aligned, so their window is
-    // the block itself)
+    // The window per block (ND dwords from a kAlign-byte boundary), the
+    // dwords of block bytes used, and whether a window ended at the readable
+    // end can leave the block kAlign or more bytes in.  Blocks of 4, 8 or 16
+    // cells start aligned to their size (tiles hold a multiple of CB cells,
+    // states start 16-aligned): their window is the block itself.  Blocks of
+    // at most 13 cells whose count is known read the dwords from the 4-byte
+    // boundary at or below them, so that v_alignbyte alone moves them into
+    // place.  Others read 16 or 24 bytes from the 8-byte boundary.
     constexpr bool kAW = CBC == 4 || CBC == 8 || CBC == 16;
-    // (blocks of at most 13 cells whose count is known: a 16-byte window from
-    // the 4-byte boundary at or below the block, so that v_alignbyte alone
-    // moves it into place; 4-aligned 16-byte loads measured as cheap as
-    // 8-aligned ones)
     constexpr bool kA4 = !kAW && CBC && CBC <= 13;
-    constexpr int NW = kAW ? (CBC == 16 ? 2 : 1) : ((kA4 || NSRC == 2 || (CBC && CBC <= 9)) ? 2 : 3);
+    constexpr int ND = kAW ? CBC / 4 : (kA4 ? (CBC + 6) / 4 : ((NSRC == 2 || (CBC && CBC <= 9)) ? 4 : 6));
     constexpr int NOUT = CBC ? (CBC + 3) / 4 : NSRC;
-    constexpr uint32_t kAlign = kA4 ? 4 : 8;  // window start alignment
-    constexpr bool kWide = !kAW && !(CBC && 8 * NW - CBC < kAlign);
-    constexpr uint32_t WB = 8 * NW;
+    constexpr uint32_t kAlign = kA4 ? 4 : 8;
+    constexpr uint32_t WB = 4 * ND;  // window bytes
+    constexpr bool kWide = !kAW && !(CBC && WB - CBC < kAlign);
     // neighbour entries of four tiles in a ring (written by wavefront 0)
     __shared__ uint32_t nbr[4][kLanes];
     const uint32_t tid = threadIdx.x, lane = tid & 63;
@@ -385,7 +374,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
 
     // The loads of a tile, issued two tiles ahead of its rule.
     struct Pending {
-        Window<NW> raw[BPT], hraw[HPT];
+        Window<ND> raw[BPT], hraw[HPT];
         bool hok[HPT];
         bool tail;  // the tile's own windows may end at the readable end
         const uint8_t *src;  // the state the tile belongs to
@@ -394,11 +383,10 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     };
     // one window (32-bit offset from the state, any block of it): from the
     // 8-byte boundary at or below the block, or ending at the readable end
-    auto window = [&](const uint8_t *src, uint32_t off, uint32_t lim, bool may_end) -> Window<NW> {
-        Window<NW> w;
+    auto window = [&](const uint8_t *src, uint32_t off, uint32_t lim, bool may_end) -> Window<ND> {
+        Window<ND> w;
         if (kAW) {
             w.sh = 0;
-            w.d[2 * NW - 1] = 0;
             constexpr int kB = kAW ? CBC : 4;  // (the branch is not taken otherwise)
             __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, kB), kB);
             return w;
@@ -437,15 +425,15 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             }
         }
     };
-    auto aligned = [&](const Window<NW> &w, bool may_be_wide) -> RawBlock<NSRC> {
+    auto aligned = [&](const Window<ND> &w, bool may_be_wide) -> RawBlock<NSRC> {
         if (kAW) {
             RawBlock<NSRC> r;
 #pragma unroll
-            for (int i = 0; i < NSRC; ++i) r.d[i] = i < 2 * NW ? w.d[i < 2 * NW ? i : 0] : 0u;
+            for (int i = 0; i < NSRC; ++i) r.d[i] = i < ND ? w.d[i < ND ? i : 0] : 0u;
             return r;
         }
-        if (kWide && may_be_wide && any_wide<NW>(w, kAlign)) return align_window<NSRC, NW, NOUT, 3>(w);
-        return align_window<NSRC, NW, NOUT, kA4 ? 0 : 1>(w);
+        if (kWide && may_be_wide && any_wide<ND>(w, kAlign)) return align_window<NSRC, ND, NOUT, 3>(w);
+        return align_window<NSRC, ND, NOUT, kA4 ? 0 : 1>(w);
     };
     const EdgeRecs<SR> grid{lds_e};
     // step 1 of a tile: the records of its blocks (kept as rows) and halo blocks
