@@ -195,6 +195,54 @@ __device__ __forceinline__ void store_cells(const uint32_t (&w)[4], uint32_t CB_
     }
 }
 
+// Raw buffer stores into a tile's output: the resource's base is the tile's
+// first byte (uniform), its range the whole 32-bit offset space (untyped
+// 32-bit data format, as gfx9 buffer resources need for untyped stores).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(uint8_t *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, 0x00020000);
+}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// Stores the CB compact bytes of w at byte offset off of the resource (any
+// alignment), as store_cells does.
+template <int CBC>
+__device__ __forceinline__ void store_cells_buf(const uint32_t (&w)[4], uint32_t CB_, __amdgpu_buffer_rsrc_t r,
+                                                uint32_t off) {
+    const uint32_t CB = CBC ? uint32_t(CBC) : CB_;
+    const u32x2 w01 = {w[0], w[1]}, w23 = {w[2], w[3]};
+    if (CB == 16) {
+        __builtin_amdgcn_raw_buffer_store_b64(w01, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(w23, r, off + 8, 0, 0);
+    } else if (CB > 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(w01, r, off, 0, 0);
+        uint32_t rem = CB - 8, x = w[2], o = off + 8;
+        if (rem >= 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(x, r, o, 0, 0);
+            o += 4;
+            rem -= 4;
+            x = w[3];
+        }
+        if (rem >= 2) {
+            __builtin_amdgcn_raw_buffer_store_b16(uint16_t(x), r, o, 0, 0);
+            o += 2;
+            rem -= 2;
+            x >>= 16;
+        }
+        if (rem) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(x), r, o, 0, 0);
+    } else if (CB == 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(w01, r, off, 0, 0);
+    } else if (CB > 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(alignbyte(w[1], w[0], CB - 4), r, off + (CB - 4), 0, 0);
+    } else if (CB == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, off, 0, 0);
+    } else if (CB >= 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), r, off, 0, 0);
+        if (CB == 3) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] >> 8), r, off + 1, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), r, off, 0, 0);
+    }
+}
+
 // The records in LDS: four dword arrays (top rows, bottom rows, left
 // columns, right columns) of SR entries each; a record is addressed by 4 x
 // its number, the array by an instruction offset.
@@ -391,7 +439,9 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
             __builtin_memcpy(w.d, __builtin_assume_aligned(src + off, kB), kB);
             return w;
         }
-        const uint32_t sh = (uint32_t(reinterpret_cast<uintptr_t>(src)) + off) & (kAlign - 1);
+        // (states and arenas start 16-aligned, so the offset alone gives the
+        // alignment)
+        const uint32_t sh = off & (kAlign - 1);
         uint32_t s = off - sh;
         if (may_end) s = s > lim - WB ? lim - WB : s;
         w.sh = off - s;
@@ -414,8 +464,9 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
         const bool tail = toff + K > P.lim - WB;  // uniform
         P.tail = tail;
 #pragma unroll
-        for (int j = 0; j < BPT; ++j)
-            if (bwave[j]) P.raw[j] = window(P.src, toff + boff[j], P.lim, tail);
+        for (int j = 0; j < BPT; ++j)  // (a uniform branch: both sides issue the same loads)
+            if (bwave[j]) P.raw[j] = tail ? window(P.src, toff + boff[j], P.lim, true)
+                                          : window(P.src, toff + boff[j], P.lim, false);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (hwave[j]) {
@@ -483,7 +534,9 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
     // the tile four ahead, cw holds those of the tile three ahead.
     uint32_t i = 0;
     auto body = [&](Pending &Q, Pending &P, uint32_t &cl, const uint32_t &cw) -> bool {
-        uint8_t *gout = Q.dst + uint64_t(Q.local) * K;
+        // the tile's output as a buffer resource (its base uniform), so that each
+        // store takes the block's 32-bit offset as it is
+        const __amdgpu_buffer_rsrc_t gout = out_rsrc(Q.dst + uint64_t(Q.local * K));
         __syncthreads();
         if (went) cl = entry(clamp(i + 4), lslot);
         prefetch(Q, clamp(i + 2), nbr[(i + 2) & 3]);
@@ -501,7 +554,7 @@ __global__ __launch_bounds__(256) void k_step_edges(EdgeParams E, const uint8_t 
                 if (BS >= 3 && (SEL & (4096u << d))) v |= __builtin_amdgcn_perm(next[3], next[2], E.pack23[d]);
                 w[d] = v;
             }
-            store_cells<CBC>(w, CB, gout + boff[j]);
+            store_cells_buf<CBC>(w, CB, gout, boff[j]);
         }
         // the records are read until here; the next tile's come after
         __syncthreads();
