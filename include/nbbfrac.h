@@ -367,7 +367,12 @@ nbb_status nbb_autotune(nbb_fractal *f, uint8_t *a, uint8_t *b, uint64_t len, ui
  * launches it runs on a side stream of the library (one per device, kept
  * until the process ends) that is forked from `stream` at the start of each
  * step call and joined back to it before the call's last enqueued work (so,
- * seen from `stream`, the call's work is ordered as before).  Step calls on one batch
+ * seen from `stream`, the call's work is ordered as before).  With more than
+ * one group, groups after the first run on up to three more streams of the
+ * library (per device, kept until the process ends), forked and joined the
+ * same way, so that one group's launches fill the start and the end of
+ * another's; the batch built by nbb_batch_step_each_noalloc runs every group
+ * on `stream`.  Step calls on one batch
  * share its small device tables: enqueue them from one host thread, and order
  * calls made on different streams (an event) before the later one starts.
  *
@@ -410,7 +415,9 @@ nbb_status nbb_batch_query(const nbb_batch *batch, nbb_batch_info *info);
  * starting in arena a, alternating with arena b as nbb_step_compact does
  * (*result_in_b = steps & 1).  Both arenas must be 16-byte aligned, at least
  * arena_bytes long (arena_len), and must not overlap; bytes outside the
- * instances' ranges are neither read nor written.  Only the result is
+ * instances' ranges are not written (loads of a block may reach past its
+ * instance's range, never past arena_len; those bytes are not used).  Only
+ * the result is
  * specified: an instance's range in the other arena holds some earlier
  * generation (instances stepped in LDS leave it untouched).
  */

@@ -139,6 +139,14 @@ struct nbb_batch {
     // stream, so that the two overlap
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // With several groups, group k > 0 runs on gstream[(k - 1) % size] (the
+    // device's group streams, forked from the caller's stream and joined back
+    // to it), so that one group's launches fill the start and the tail of
+    // another's; empty when the batch has one group or was built without
+    // allocation.
+    std::vector<hipStream_t> gstream;
+    std::vector<hipEvent_t> gjoin;  // one per group stream
+    hipEvent_t gfork = nullptr;
 };
 
 namespace {
@@ -908,27 +916,34 @@ static const TileParams *resident_plan(const nbb_fractal *F, uint32_t *teams) {
     return &F->res_tp;
 }
 
-// The device's side stream for resident launches (created on first use,
-// kept until the process ends; default priority, non-blocking).
-static hipError_t resident_stream(int dev, hipStream_t *out) {
+// The device's streams beside the caller's (created on first use, kept
+// until the process ends; default priority, non-blocking): slot 0 for
+// resident launches, slots 1 .. kGroupStreams for the groups of a batch.
+constexpr int kGroupStreams = 3;
+static hipError_t device_stream(int dev, int slot, hipStream_t *out) {
     static std::mutex mu;
-    static std::vector<hipStream_t> pool;
+    static std::vector<std::vector<hipStream_t>> pool;
     std::lock_guard<std::mutex> lock(mu);
-    if (pool.size() <= size_t(dev)) pool.resize(dev + 1, nullptr);
-    if (!pool[dev]) {
-        hipError_t e = hipStreamCreateWithFlags(&pool[dev], hipStreamNonBlocking);
+    if (pool.size() <= size_t(dev)) pool.resize(dev + 1);
+    std::vector<hipStream_t> &p = pool[dev];
+    if (p.empty()) p.assign(1 + kGroupStreams, nullptr);
+    if (!p[slot]) {
+        hipError_t e = hipStreamCreateWithFlags(&p[slot], hipStreamNonBlocking);
         if (e != hipSuccess) {
-            pool[dev] = nullptr;
+            p[slot] = nullptr;
             return e;
         }
     }
-    *out = pool[dev];
+    *out = p[slot];
     return hipSuccess;
 }
+static hipError_t resident_stream(int dev, hipStream_t *out) { return device_stream(dev, 0, out); }
 
 static void batch_free(nbb_batch *B) {
     if (B->fork) (void)hipEventDestroy(B->fork);
     if (B->join) (void)hipEventDestroy(B->join);
+    if (B->gfork) (void)hipEventDestroy(B->gfork);
+    for (hipEvent_t ev : B->gjoin) (void)hipEventDestroy(ev);
     blob_free(&B->dtab);
     delete B;
 }
@@ -1192,6 +1207,24 @@ static nbb_status batch_create(const nbb_fractal *const *fractals, const uint64_
             return hip_fail(e, "batch stream");
         }
     }
+    if (!fixed && B->groups.size() > 1) {
+        const size_t ns = std::min<size_t>(B->groups.size() - 1, kGroupStreams);
+        e = hipEventCreateWithFlags(&B->gfork, hipEventDisableTiming);
+        for (size_t i = 0; i < ns && e == hipSuccess; ++i) {
+            hipStream_t gs = nullptr;
+            hipEvent_t ev = nullptr;
+            e = device_stream(dev, int(1 + i), &gs);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) {
+                B->gstream.push_back(gs);
+                B->gjoin.push_back(ev);
+            }
+        }
+        if (e != hipSuccess) {
+            batch_free(B);
+            return hip_fail(e, "batch group streams");
+        }
+    }
     *out = B;
     return NBB_OK;
 }
@@ -1257,6 +1290,28 @@ static hipError_t batch_fork_resident(const nbb_batch *B, uint8_t *a, uint8_t *b
 static hipError_t batch_join_resident(const nbb_batch *B, hipStream_t s, bool launched_) {
     return (launched_ && B->side) ? hipStreamWaitEvent(s, B->join, 0) : hipSuccess;
 }
+// The group streams start after the work enqueued on s so far; group k's
+// launches go to batch_group_stream(B, k, s); batch_join_groups makes s wait
+// for all of them.  Groups touch disjoint instance ranges of the arenas
+// (a window read past a block's bytes may reach into another instance's
+// range, but those bytes are not used), so they need no order between them.
+static hipError_t batch_fork_groups(const nbb_batch *B, hipStream_t s) {
+    if (B->gstream.empty()) return hipSuccess;
+    hipError_t e = hipEventRecord(B->gfork, s);
+    for (size_t i = 0; i < B->gstream.size() && e == hipSuccess; ++i) e = hipStreamWaitEvent(B->gstream[i], B->gfork, 0);
+    return e;
+}
+static hipStream_t batch_group_stream(const nbb_batch *B, size_t k, hipStream_t s) {
+    return (k == 0 || B->gstream.empty()) ? s : B->gstream[(k - 1) % B->gstream.size()];
+}
+static hipError_t batch_join_groups(const nbb_batch *B, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < B->gstream.size() && e == hipSuccess; ++i) {
+        e = hipEventRecord(B->gjoin[i], B->gstream[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, B->gjoin[i], 0);
+    }
+    return e;
+}
 
 nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t arena_len, uint32_t steps,
                           uint32_t rule, int *result_in_b, void *stream) {
@@ -1276,21 +1331,36 @@ nbb_status nbb_batch_step(const nbb_batch *B, uint8_t *a, uint8_t *b, uint64_t a
     bool res_launched = false;
     e = batch_fork_resident(B, a, b, rule, nullptr, steps, s, &res_launched);
     if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
-    uint8_t *in = a, *out = b;
-    for (uint32_t i = 0; i < steps; ++i) {
-        for (const BatchGroup &G : B->groups) {
-            e = G.edges ? launch_step_edges(G.ep, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, s)
-                        : launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, s);
-            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    e = batch_fork_groups(B, s);
+    if (e != hipSuccess) return hip_fail(e, "batch group fork");
+    // each group takes all its generations on its stream
+    for (size_t k = 0; k < B->groups.size() && e == hipSuccess; ++k) {
+        const BatchGroup &G = B->groups[k];
+        const hipStream_t gs = batch_group_stream(B, k, s);
+        uint8_t *in = a, *out = b;
+        for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) {
+            e = G.edges ? launch_step_edges(G.ep, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, gs)
+                        : launch_step_tiled_batch(G.tp, G.rec, in, out, rule, B->cu_count, gs);
+            std::swap(in, out);
         }
-        for (const BatchDirect &d : B->direct) {
-            const nbb_fractal *F = d.f;
-            e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + d.offset, out + d.offset, rule,
-                                   map_grid(F, F->f.cells), s);
-            if (e != hipSuccess) return hip_fail(e, "batch direct step launch");
-        }
-        std::swap(in, out);
     }
+    const char *what = "batch step launch";
+    for (size_t j = 0; j < B->direct.size() && e == hipSuccess; ++j) {
+        const nbb_fractal *F = B->direct[j].f;
+        const uint64_t off = B->direct[j].offset;
+        uint8_t *in = a, *out = b;
+        for (uint32_t i = 0; i < steps && e == hipSuccess; ++i) {
+            e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + off, out + off, rule,
+                                   map_grid(F, F->f.cells), s);
+            std::swap(in, out);
+        }
+        what = "batch direct step launch";
+    }
+    // joined also after a failed launch, so that s does not run ahead of
+    // what was enqueued on the other streams
+    const hipError_t ej = batch_join_groups(B, s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (ej != hipSuccess) return hip_fail(ej, "batch group join");
     e = batch_join_resident(B, s, res_launched);
     return e == hipSuccess ? NBB_OK : hip_fail(e, "batch resident join");
 }
@@ -1322,35 +1392,44 @@ nbb_status nbb_batch_step_each(const nbb_batch *B, uint8_t *a, uint8_t *b, uint6
     bool res_launched = false;
     e = batch_fork_resident(B, a, b, rule, steps, 0, s, &res_launched);
     if (e != hipSuccess) return hip_fail(e, "batch resident step launch");
-    std::vector<size_t> live(B->groups.size());
-    for (size_t k = 0; k < B->groups.size(); ++k) live[k] = B->groups[k].index.size();
-    uint8_t *in = a, *out = b;
-    for (uint32_t g = 0; g < most; ++g) {
-        for (size_t k = 0; k < B->groups.size(); ++k) {
-            const BatchGroup &G = B->groups[k];
-            while (live[k] && steps[G.index[live[k] - 1]] <= g) --live[k];
-            if (!live[k]) continue;
-            const uint32_t nt = uint32_t(G.tiles_end[live[k] - 1]);
+    e = batch_fork_groups(B, s);
+    if (e != hipSuccess) return hip_fail(e, "batch group fork");
+    for (size_t k = 0; k < B->groups.size() && e == hipSuccess; ++k) {
+        const BatchGroup &G = B->groups[k];
+        const hipStream_t gs = batch_group_stream(B, k, s);
+        size_t live = G.index.size();
+        uint8_t *in = a, *out = b;
+        for (uint32_t g = 0; g < most && e == hipSuccess; ++g) {
+            while (live && steps[G.index[live - 1]] <= g) --live;
+            if (!live) break;
+            const uint32_t nt = uint32_t(G.tiles_end[live - 1]);
             if (G.edges) {
                 EdgeParams E = G.ep;
                 E.ntiles = nt;
-                e = launch_step_edges(E, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, s);
+                e = launch_step_edges(E, G.BS, G.nsrc, in, out, arena_len, rule, G.rec, B->cu_count, gs);
             } else {
                 TileParams T = G.tp;
                 T.ntiles = nt;
-                e = launch_step_tiled_batch(T, G.rec, in, out, rule, B->cu_count, s);
+                e = launch_step_tiled_batch(T, G.rec, in, out, rule, B->cu_count, gs);
             }
-            if (e != hipSuccess) return hip_fail(e, "batch step launch");
+            std::swap(in, out);
         }
-        for (const BatchDirect &d : B->direct) {
-            if (steps[d.index] <= g) continue;
-            const nbb_fractal *F = d.f;
+    }
+    const char *what = "batch step launch";
+    for (size_t j = 0; j < B->direct.size() && e == hipSuccess; ++j) {
+        const BatchDirect &d = B->direct[j];
+        const nbb_fractal *F = d.f;
+        uint8_t *in = a, *out = b;
+        for (uint32_t g = 0; g < steps[d.index] && e == hipSuccess; ++g) {
             e = launch_step_direct(F->mp, F->lam_words, F->nu_halves, in + d.offset, out + d.offset, rule,
                                    map_grid(F, F->f.cells), s);
-            if (e != hipSuccess) return hip_fail(e, "batch direct step launch");
+            std::swap(in, out);
         }
-        std::swap(in, out);
+        what = "batch direct step launch";
     }
+    const hipError_t ej = batch_join_groups(B, s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (ej != hipSuccess) return hip_fail(ej, "batch group join");
     e = batch_join_resident(B, s, res_launched);
     if (e != hipSuccess) return hip_fail(e, "batch resident join");
     return NBB_OK;
