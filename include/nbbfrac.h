@@ -521,7 +521,7 @@ const char *nbb_status_string(nbb_status s);
  *   edge_blk[4b .. 4b+3] = the records of block b's neighbours, two per word
  *   (low half first): left | right, above | below, above-left | above-right,
  *   below-left | below-right (the step reads a block's bytes as edge_nsrc
- *   dwords through one aligned load of the 8-byte window holding them);
+ *   dwords through one aligned load of a window holding them);
  *   edge_halo[2h] = direction << 29 | block of that neighbour tile,
  *   edge_halo[2h+1] = its record, for edge_halo_count items;
  *   edge_unpack / edge_pack: the v_perm selectors from a block's bytes to its

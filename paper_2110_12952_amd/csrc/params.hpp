@@ -109,9 +109,11 @@ struct TileParams {
 // block's eight neighbour record numbers (the zero record where the grid has
 // no block).
 //
-// A block's bytes are loaded as NSRC dwords (NSRC = 2 for 3 x 3 blocks of at
-// most 8 cells, else 4) through one aligned load of the 8-byte window that
-// holds them; a window that would run past `limit` ends at it instead.
+// A block's bytes (NSRC dwords of them: 2 for 3 x 3 blocks of at most 8
+// cells, else 4) are read through one aligned load of a window that holds
+// them: the block itself for blocks of 4, 8 or 16 cells, else a few dwords
+// from the 4- or 8-byte boundary below the block; a window that would run
+// past `limit` ends at it instead.
 struct EdgeParams {
     uint32_t K, CB, nblk, nhalo;
     uint32_t ntiles;        // tiles of the launch (batch tiles for a batch)
