@@ -238,6 +238,36 @@ def test_batch512_equals_single_runs_and_oracle(N):
         np.testing.assert_array_equal(got[batch.offsets[i]:batch.offsets[i] + frs[i].cells], exp)
 
 
+def test_batch512_on_a_side_stream_is_ordered_on_it(N):
+    # the groups run on streams of the library forked from the caller's and
+    # joined back to it: two calls in a row and a copy enqueued after them on
+    # the caller's (non-default) stream, waited for on that stream alone, see
+    # every group's last generation
+    items = W.BATCH512.items()
+    frs = _c4(N, items)
+    batch = N.Batch(frs)
+    assert batch.info().groups == 4
+    a, b = batch.new_arena(), batch.new_arena()
+    for i, (it, f) in enumerate(zip(items, frs)):
+        f.init_compact(it.seed, it.p, out=batch.state(a, i))
+    ref = torch.empty_like(a)
+    tmp = torch.empty(max(f.cells for f in frs), dtype=torch.uint8, device="cuda")
+    for i, f in enumerate(frs):
+        out = f.step_compact(batch.state(a, i).clone(), tmp[:f.cells], 7)
+        batch.state(ref, i).copy_(out)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        r1 = batch.step(a, b, 3)
+        r2 = batch.step(r1, a if r1 is b else b, 4)
+        seen = r2.clone()
+    side.synchronize()
+    got, want = seen.cpu().numpy(), host(ref)
+    for i, f in enumerate(frs):
+        sl = slice(batch.offsets[i], batch.offsets[i] + f.cells)
+        np.testing.assert_array_equal(got[sl], want[sl], err_msg=f"instance {i}")
+
+
 # ------------------------------------------------------------- autotuner --
 @pytest.mark.parametrize("name,r", [("triangle", 10), ("carpet", 5), ("chandelier", 6), ("hfractal", 2)])
 def test_autotune_then_step_matches_oracle(N, name, r):
