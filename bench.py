@@ -95,6 +95,30 @@ def measured_traffic(per_launch_alg_bytes):
         return None
 
 
+LARGE_COUNTERS = os.path.join(ROOT, "profiles", "large_steps_carpet_r9_hfractal_r10_counters.txt")
+LARGE_ROWS = {"carpet_r9": "carpet r9", "hfractal_r10": "H r10"}
+
+
+def measured_large_traffic(name):
+    """(compact, box) HBM traffic over algorithmic bytes of an HBM-sized
+    workload from the committed counter summary, if it was taken on the
+    current kernel source; else (None, None)."""
+    if name not in LARGE_ROWS or not os.path.exists(LARGE_COUNTERS):
+        return None, None
+    lines = open(LARGE_COUNTERS).read().splitlines()
+    if f"kernel_sources_sha256_16: {kernel_sources_hash()}" not in lines:
+        return None, None
+    got = {}
+    for line in lines:
+        for form in ("compact", "box"):
+            if line.startswith(f"{LARGE_ROWS[name]} {form} "):
+                try:
+                    got[form] = float(line.rsplit("|", 1)[1])
+                except ValueError:
+                    pass
+    return got.get("compact"), got.get("box")
+
+
 def cpu_baseline(W, wl, seconds, one_thread=True):
     from oracle import oracle as O
     fd = wl.fractal
@@ -325,6 +349,7 @@ def large_case(torch, N, W, name, rule, steps, warm_ms=50.0):
            "ms_per_step": ms / steps, "cell_updates_per_s": g.cells * steps / (ms * 1e-3),
            "alg_gbps": alg / (ms / steps * 1e-3) / 1e9}
     out["roofline_frac"] = out["alg_gbps"] / HBM_PEAK_GBPS
+    out["traffic_over_alg"], box_traffic = measured_large_traffic(name)
     res = res.clone()
     del a, b, pair
     box = g.init_bbox(wl.seeds[0], wl.p)
@@ -334,6 +359,7 @@ def large_case(torch, N, W, name, rule, steps, warm_ms=50.0):
     out["bbox_ms_per_step"] = msb / steps
     out["bbox_alg_gbps"] = 2 * g.n * g.n / (msb / steps * 1e-3) / 1e9
     out["bbox_roofline_frac"] = out["bbox_alg_gbps"] / HBM_PEAK_GBPS
+    out["bbox_traffic_over_alg"] = box_traffic
     out["speedup_vs_bbox"] = msb / ms
     out["compact_equals_bbox"] = bool(torch.equal(g.gather(resb), res))
     log(f"{name}: compact {ms / steps * 1e3:.1f} us/step ({out['roofline_frac']:.3f} of HBM peak), box "

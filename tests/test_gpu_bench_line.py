@@ -48,6 +48,7 @@ def test_bench_prints_one_complete_json_line():
         lw = d["large_workloads"][nm]
         assert lw["compact_equals_bbox"] is True and lw["steps"] == 3
         assert abs(lw["roofline_frac"] - lw["alg_gbps"] / 8000.0) < 1e-9
+        assert "traffic_over_alg" in lw and "bbox_traffic_over_alg" in lw
 
 
 def test_bench_refuses_several_gpus():
